@@ -1,0 +1,181 @@
+/*
+ * rqrcp.h -- C ABI of the gfx950 (MI355X) library for randomized QR with
+ * column pivoting (Duersch & Gu, "Randomized QR with Column Pivoting",
+ * arXiv 1509.06820).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Matrices are column-major, double precision, with a leading dimension
+ *   ld >= max(1, rows).  Every pointer to matrix/vector data is a DEVICE
+ *   pointer owned by the caller; the library never allocates or frees
+ *   device memory.  Scratch memory is the caller's `work` buffer of at least
+ *   rq_workspace_bytes(...) bytes (device memory, 256-byte aligned).
+ * - `stream` is a hipStream_t (passed as void*; NULL = default stream).  The
+ *   calls only ENQUEUE work: they return as soon as the kernels are queued
+ *   and the results are valid once the stream reaches that point.  Calls
+ *   that share a `work` buffer must be ordered on one stream.
+ * - Return value (enqueue status): 0 on success; -i when argument i (1-based)
+ *   is invalid, LAPACK xerbla style; -100 when the workspace is too small;
+ *   1000 + hipError_t on a HIP runtime error (including a cooperative launch
+ *   that does not fit the device).
+ * - `info` (device int32, may be NULL) is written by the kernels: 0 = no
+ *   issue; j > 0 = a non-finite sample norm was first met around pivot step j
+ *   (the factorization still completes; a NaN norm never wins a pivot
+ *   choice); -1 = an internal cross-workgroup wait timed out (results are
+ *   invalid).
+ * - Limits of this version: 1 <= b <= 64, 0 <= p, b + p <= 128, n <= 65536,
+ *   k <= 1024 for rq_tuxv.
+ * - Pivot indices are 0-based int64.  jpvt[j] is the original index of column
+ *   j of A P.
+ */
+#ifndef RQRCP_H
+#define RQRCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Operation codes for rq_workspace_bytes. */
+enum {
+  RQ_OP_RQRCP = 0,        /* rq_rqrcp / rq_rqrcp_omega          */
+  RQ_OP_TRQRCP = 1,       /* rq_trqrcp / rq_trqrcp_omega        */
+  RQ_OP_TUXV = 2,         /* rq_tuxv / rq_tuxv_omega            */
+  RQ_OP_QR = 3,           /* rq_unpivoted_qr                    */
+  RQ_OP_SAMPLE_QRCP = 4,  /* rq_sample_qrcp                     */
+  RQ_OP_SVD = 5           /* rq_small_svd                       */
+};
+
+/* Library version string (static storage). */
+const char* rq_version(void);
+
+/*
+ * Workspace size in bytes for operation `op` at the given sizes (host-only
+ * query, no GPU work).  k is ignored for RQ_OP_RQRCP and RQ_OP_QR.
+ * Returns 0 on success or -i for an invalid argument i.
+ */
+int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, int32_t p, size_t* bytes);
+
+/*
+ * RQRCP -- Alg. 4 (Section 5), full factorization with k = min(m, n):
+ * A P = Q R with Q = H_0 ... H_{k-1}.
+ *   Omega (l x m, l = b + p) is drawn from `seed` (Philox4x64-10 + Box-Muller,
+ *   see rq_omega); the sample B = Omega A picks each block of b pivots by a
+ *   partial QRCP of the l x n sample; the selected columns get a Householder
+ *   panel and a compact-WY update of the trailing matrix; the sample is then
+ *   refreshed by eq. (update1) instead of being re-drawn.
+ *   On exit A holds R on and above the diagonal and the Householder vectors
+ *   below it (unit diagonal implicit; the LAPACK dgeqp3 layout), tau[k]
+ *   holds the reflector coefficients (H_i = I - tau_i y_i y_i^T) and jpvt[n]
+ *   the column permutation.
+ *   Arguments: 1 stream, 2 m, 3 n, 4 A (in/out, m x n, device), 5 lda,
+ *   6 b (block size), 7 p (oversampling), 8 seed, 9 jpvt (out, n int64),
+ *   10 tau (out, min(m,n)), 11 work, 12 work_bytes, 13 info (out, device).
+ */
+int rq_rqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+             int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info);
+
+/* As rq_rqrcp with a caller-supplied compression matrix Omega (l x m,
+ * column-major, leading dimension ldo >= l, device; argument 8 = Omega,
+ * 9 = ldo; the later arguments shift by one). */
+int rq_rqrcp_omega(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p,
+                   const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work, size_t work_bytes,
+                   int32_t* info);
+
+/*
+ * TRQRCP -- Alg. 6 (Section 5.1): truncated RQRCP to rank k that never
+ * updates the trailing matrix; it keeps the reflector block Y and the inner
+ * products W^T = T^T Y^T A and forms selected columns A - Y W^T and new rows
+ * of R on demand.  On exit rows 0..k-1 of A hold R (k x n upper trapezoidal),
+ * columns 0..k-1 below the diagonal hold the Householder vectors, and the
+ * block A(k:m, k:n) holds the PERMUTED ORIGINAL entries (unlike dgeqp3).
+ * jpvt[0..k-1] are the pivots; jpvt[k..n-1] is the swap-induced order of the
+ * other columns.  tau has k entries.  1 <= k <= min(m, n).
+ * Arguments: 1 stream, 2 m, 3 n, 4 k, 5 A, 6 lda, 7 b, 8 p, 9 seed, 10 jpvt,
+ * 11 tau, 12 work, 13 work_bytes, 14 info.
+ */
+int rq_trqrcp(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
+              uint64_t seed, int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info);
+
+int rq_trqrcp_omega(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
+                    const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work, size_t work_bytes,
+                    int32_t* info);
+
+/*
+ * TUXV -- Alg. 7 with j_max = 1 (Section 6, eq. tuxv) followed by the SVD of
+ * the k x k connection matrix X: A ~= U diag(sigma) VT.
+ *   TRQRCP on a copy of A -> Z0 = R P^T -> V from the QR of Z0^T -> Z1 = A V
+ *   -> U1, X from the QR of Z1 -> X = Ux diag(sigma) Vx^T (one-sided Jacobi)
+ *   -> U = U1 Ux, VT = Vx^T V^T.
+ *   A is read-only.  Outputs: U (m x k, orthonormal columns, ldu >= m),
+ *   sigma (k, descending, >= 0), VT (k x n, orthonormal rows, ldvt >= k).
+ *   Singular vectors are defined up to sign.
+ * Arguments: 1 stream, 2 m, 3 n, 4 k, 5 A, 6 lda, 7 b, 8 p, 9 seed, 10 U,
+ * 11 ldu, 12 sigma, 13 VT, 14 ldvt, 15 work, 16 work_bytes, 17 info.
+ */
+int rq_tuxv(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
+            uint64_t seed, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt, void* work,
+            size_t work_bytes, int32_t* info);
+
+int rq_tuxv_omega(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
+                  const double* Omega, int64_t ldo, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt,
+                  void* work, size_t work_bytes, int32_t* info);
+
+/*
+ * Unpivoted blocked Householder QR (the paper's "qr" comparator, Section 7:
+ * RQRCP with sampling and pivoting removed), same output layout as rq_rqrcp
+ * without jpvt.  Arguments: 1 stream, 2 m, 3 n, 4 A, 5 lda, 6 b, 7 tau,
+ * 8 work, 9 work_bytes, 10 info.
+ */
+int rq_unpivoted_qr(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, double* tau, void* work,
+                    size_t work_bytes, int32_t* info);
+
+/*
+ * Compression matrix alone (Section 3: i.i.d. N(0,1) entries): Omega(r, c),
+ * r < l, c < m, is normal number r*m + c of the stream for `seed`:
+ * Philox4x64-10 (Salmon et al., SC'11) with key (seed, 0), block q = counter
+ * (q+1, 0, 0, 0); u = ((x >> 12) + 1/2) 2^-52; Box-Muller on word pairs
+ * (0,1) and (2,3).  Output column-major l x m with ldo >= l.
+ * Arguments: 1 stream, 2 seed, 3 l, 4 m, 5 Omega (out), 6 ldo.
+ */
+int rq_omega(void* stream, uint64_t seed, int64_t l, int64_t m, double* Omega, int64_t ldo);
+
+/*
+ * Sketch alone (Alg. 4, "form the initial sample"): B = Omega A with Omega
+ * drawn from `seed` as in rq_omega; B is l x n column-major (ldb >= l).
+ * Arguments: 1 stream, 2 m, 3 n, 4 A, 5 lda, 6 l, 7 seed, 8 B, 9 ldb,
+ * 10 work, 11 work_bytes (RQ_OP_RQRCP workspace with b = l, p = 0 suffices).
+ */
+int rq_sketch(void* stream, int64_t m, int64_t n, const double* A, int64_t lda, int32_t l, uint64_t seed, double* B,
+              int64_t ldb, void* work, size_t work_bytes);
+
+/*
+ * Partial QRCP of a sample alone (Alg. 1 run for bsteps steps on an l x n
+ * matrix, the "qrcp(B, b)" step of Alg. 4): trailing squared norms are
+ * recomputed at every step, the largest wins with ties to the lowest
+ * position, swaps are sequential (step t exchanges positions t and piv[t]).
+ * On exit B (l x n, ldb >= l, in/out) holds S: the first bsteps columns are
+ * upper triangular (S11 above S21 = 0), the rest hold S12 / S22.
+ * Arguments: 1 stream, 2 l, 3 n, 4 bsteps (<= min(64, l, n)), 5 B, 6 ldb,
+ * 7 piv (out, bsteps int32, device), 8 work, 9 work_bytes, 10 info.
+ */
+int rq_sample_qrcp(void* stream, int32_t l, int64_t n, int32_t bsteps, double* B, int64_t ldb, int32_t* piv,
+                   void* work, size_t work_bytes, int32_t* info);
+
+/*
+ * SVD of a small square matrix alone (the SVD of X in TUXV): X = U diag(s) V^T
+ * by one-sided Jacobi.  X (k x k, ldx) is overwritten.  U (ldu), V (ldv) are
+ * k x k outputs, sigma descending.
+ * Arguments: 1 stream, 2 k, 3 X, 4 ldx, 5 U, 6 ldu, 7 sigma, 8 V, 9 ldv,
+ * 10 work, 11 work_bytes.
+ */
+int rq_small_svd(void* stream, int32_t k, double* X, int64_t ldx, double* U, int64_t ldu, double* sigma, double* V,
+                 int64_t ldv, void* work, size_t work_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RQRCP_H */

@@ -1,0 +1,662 @@
+// C ABI and host-side drivers: RQRCP (Alg. 4), TRQRCP (Alg. 6), TUXV (Alg. 7
+// with j_max = 1 plus the SVD of X) and the unpivoted blocked QR comparator.
+// The drivers only enqueue kernels on the caller's stream; pivot indices and
+// all intermediate state stay on the device (no host synchronisation).
+#include "rqrcp.h"
+#include "kernels.hpp"
+
+namespace rq {
+
+namespace {
+
+constexpr int FLAG_STRIDE = 512;  // 32-bit flag words per block (sample QRCP + panel)
+constexpr int RQ_ERR_WORKSPACE = -100;
+
+__global__ void iota64_kernel(int64_t n, int64_t* v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
+__global__ void finish_kernel(const int* err, const int* info_ws, int32_t* info) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int v = *info_ws;
+    if (*err) v = -1;
+    *info = v;
+  }
+}
+
+__global__ void transpose_kernel(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
+                                 double* __restrict__ dst, int64_t ldd) {
+  // dst(j, i) = src(i, j), src rows x cols
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = idx - j * rows;
+  dst[j + i * ldd] = src[i + j * lds];
+}
+
+int launch_iota(hipStream_t s, int64_t n, int64_t* v) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(iota64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, v);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_transpose(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
+                     int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return 0;
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((rows * cols + 255) / 256)), dim3(256), 0, s, rows, cols, src,
+                     lds, dst, ldd);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
+
+#define RQ_TRY(x)            \
+  do {                       \
+    int _rc = (x);           \
+    if (_rc) return _rc;     \
+  } while (0)
+
+// ------------------------------------------------------------------ workspace
+// Every operation carves its buffers from the caller's workspace with the
+// same code path used by rq_workspace_bytes (base pointer null = size query).
+struct Common {
+  unsigned* flags;   // nblk * FLAG_STRIDE words
+  int* err;          // 1 word
+  int* info;         // 1 word
+  size_t flag_words;
+};
+
+void carve_common(Carve& cv, int64_t nblk, Common& c) {
+  c.flag_words = (size_t)nblk * FLAG_STRIDE + 64;
+  c.flags = cv.take<unsigned>(c.flag_words);
+  c.err = (int*)(c.flags + (size_t)nblk * FLAG_STRIDE);
+  c.info = c.err + 1;
+}
+
+struct SampleBufs {
+  double* omega;      // l x m (ld l)
+  double* bt;         // n x l (ld n): transposed sample
+  SampleQrcpWork sq;
+  int* piv;           // b
+  double* w11;        // b x b
+};
+
+void carve_sample(Carve& cv, int64_t m, int64_t n, int b, int l, SampleBufs& sb) {
+  sb.omega = cv.take<double>((size_t)l * m);
+  sb.bt = cv.take<double>((size_t)n * l);
+  sb.sq.refl = cv.take<double>((size_t)l * b);
+  sb.sq.rtau = cv.take<double>(b);
+  sb.sq.cand_pos = cv.take<long long>(64 * 256);
+  sb.sq.theta = cv.take<double>(64);
+  sb.piv = cv.take<int>(b);
+  sb.w11 = cv.take<double>((size_t)b * b);
+}
+
+struct BlockBufs {
+  double* panel_slots;
+  double* G;          // b x b
+  double* T;          // b x b
+  double* zbuf;       // b x n
+  double* wt;         // b x n
+  double* splitk;
+  size_t splitk_elems;
+};
+
+void carve_block(Carve& cv, int64_t m, int64_t n, int b, BlockBufs& bb) {
+  bb.panel_slots = cv.take<double>(panel_slot_elems(m, b));
+  bb.G = cv.take<double>((size_t)b * b);
+  bb.T = cv.take<double>((size_t)b * b);
+  bb.zbuf = cv.take<double>((size_t)b * std::max<int64_t>(n, 1));
+  bb.wt = cv.take<double>((size_t)b * std::max<int64_t>(n, 1));
+  bb.splitk_elems = std::max<size_t>({gemm_scratch_elems(b, n, m), gemm_scratch_elems(b, b, m), (size_t)1});
+  bb.splitk = cv.take<double>(bb.splitk_elems);
+}
+
+PanelWork panel_work(const BlockBufs& bb, const Common& c, int64_t J) {
+  PanelWork w;
+  w.slots = bb.panel_slots;
+  w.flags = c.flags + (size_t)J * FLAG_STRIDE + 128;
+  w.err = c.err;
+  return w;
+}
+
+SampleQrcpWork sq_work(const SampleBufs& sb, const Common& c, int64_t J) {
+  SampleQrcpWork w = sb.sq;
+  w.flags = c.flags + (size_t)J * FLAG_STRIDE;
+  w.err = c.err;
+  return w;
+}
+
+int64_t nblocks(int64_t k, int b) { return (k + b - 1) / b; }
+
+// ------------------------------------------------------------------ pieces
+// Panel QR of A(i0:m, i0:i0+bJ) + connection matrix T of its reflectors.
+int panel_and_t(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t i0, int bJ, double* tau, double* Y,
+                int64_t ldy, const BlockBufs& bb, const Common& c, int64_t J) {
+  const int64_t mJ = m - i0;
+  RQ_TRY(launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, panel_work(bb, c, J)));
+  RQ_TRY(launch_gemm(s, true, false, bJ, bJ, mJ, 1.0, Y, ldy, Y, ldy, 0.0, bb.G, bJ, bb.splitk, bb.splitk_elems));
+  RQ_TRY(launch_larft(s, bJ, bb.G, tau, bb.T));
+  return 0;
+}
+
+// Trailing update Q^T C = C - Y (T^T (Y^T C)) of C = A(i0:m, i0+bJ:n).
+int trailing_update(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t n, int64_t i0, int bJ, const double* Y,
+                    int64_t ldy, const BlockBufs& bb) {
+  const int64_t mJ = m - i0, Nt = n - i0 - bJ;
+  if (Nt <= 0) return 0;
+  double* C = A + i0 + (i0 + bJ) * lda;
+  RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y, ldy, C, lda, 0.0, bb.zbuf, bJ, bb.splitk, bb.splitk_elems));
+  RQ_TRY(launch_gemm(s, true, false, bJ, Nt, bJ, 1.0, bb.T, bJ, bb.zbuf, bJ, 0.0, bb.wt, bJ, nullptr, 0));
+  RQ_TRY(launch_gemm(s, false, false, mJ, Nt, bJ, -1.0, Y, ldy, bb.wt, bJ, 1.0, C, lda, nullptr, 0));
+  return 0;
+}
+
+// Sample update, eq. (update1): B1 = S12 - (S11 R11^-1) R12, B2 = S22, on the
+// transposed sample of this block (Bt + i0, ld n).
+int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, int bJ, double* bt_blk,
+                  const SampleBufs& sb) {
+  const int64_t Nt = n - i0 - bJ;
+  if (Nt <= 0) return 0;
+  const double* R11 = A + i0 + i0 * lda;
+  const double* R12 = A + i0 + (i0 + bJ) * lda;
+  RQ_TRY(launch_w11(s, bJ, bt_blk, n, 1, R11, lda, sb.w11));
+  // Bt(bJ:, 0:bJ) -= R12^T W11^T
+  RQ_TRY(launch_gemm(s, true, true, Nt, bJ, bJ, -1.0, R12, lda, sb.w11, bJ, 1.0, bt_blk + bJ, n, nullptr, 0));
+  return 0;
+}
+
+// Sketch: Bt (n x l) = A^T Omega^T with Omega l x m (ld ldo).
+int sketch(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, int l, const double* Omega,
+           int64_t ldo, double* bt) {
+  return launch_gemm(s, true, true, n, l, m, 1.0, A, lda, Omega, ldo, 0.0, bt, n, nullptr, 0);
+}
+
+// ------------------------------------------------------------------ RQRCP / QR
+struct FactorWS {
+  Common c;
+  SampleBufs sb;
+  BlockBufs bb;
+  double* ybuf;  // m x b
+};
+
+void carve_factor(Carve& cv, int64_t m, int64_t n, int b, int p, bool pivoting, FactorWS& f) {
+  const int64_t k = std::min(m, n);
+  carve_common(cv, nblocks(k, b), f.c);
+  if (pivoting) carve_sample(cv, m, n, b, b + p, f.sb);
+  carve_block(cv, m, n, b, f.bb);
+  f.ybuf = cv.take<double>((size_t)m * b);
+}
+
+int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int b, int p, uint64_t seed,
+                const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work, size_t wbytes,
+                int32_t* info, bool pivoting) {
+  FactorWS f;
+  Carve cv(work, wbytes);
+  carve_factor(cv, m, n, b, p, pivoting, f);
+  if (!cv.ok) return RQ_ERR_WORKSPACE;
+  const int64_t k = std::min(m, n);
+  const int l = b + p;
+  RQ_TRY(launch_fill(s, f.c.flags, f.c.flag_words));
+  if (pivoting) {
+    RQ_TRY(launch_iota(s, n, jpvt));
+    const double* Om = Omega;
+    int64_t ldom = ldo;
+    if (!Om) {
+      RQ_TRY(launch_omega(s, seed, l, m, f.sb.omega, 1, l));
+      Om = f.sb.omega;
+      ldom = l;
+    }
+    RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, f.sb.bt));
+  }
+  for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
+    const int bJ = (int)std::min<int64_t>(b, k - i0);
+    const int64_t mJ = m - i0, nJ = n - i0;
+    (void)mJ;
+    double* bt_blk = pivoting ? f.sb.bt + i0 : nullptr;
+    if (pivoting) {
+      RQ_TRY(launch_sample_qrcp(s, bt_blk, n, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J)));
+      RQ_TRY(launch_apply_swaps(s, f.sb.piv, bJ, i0, A, lda, m, jpvt));
+    }
+    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J));
+    RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
+    if (pivoting && i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, bt_blk, f.sb));
+    i0 += bJ;
+  }
+  if (info) {
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, f.c.err, f.c.info, info);
+    RQ_HIP(hipGetLastError());
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------ TRQRCP
+struct TrqWS {
+  Common c;
+  SampleBufs sb;
+  BlockBufs bb;
+  double* yall;   // m x k
+  double* wt;     // k x n
+  double* gk;     // b x k
+};
+
+void carve_trq(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TrqWS& t) {
+  carve_common(cv, nblocks(k, b), t.c);
+  carve_sample(cv, m, n, b, b + p, t.sb);
+  carve_block(cv, m, std::max(n, k), b, t.bb);
+  t.yall = cv.take<double>((size_t)m * k);
+  t.wt = cv.take<double>((size_t)k * n);
+  t.gk = cv.take<double>((size_t)b * k);
+}
+
+int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int b, int p, uint64_t seed,
+                const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, TrqWS& t) {
+  const int l = b + p;
+  RQ_TRY(launch_fill(s, t.c.flags, t.c.flag_words));
+  RQ_TRY(launch_fill(s, t.yall, (size_t)m * k * 2));
+  RQ_TRY(launch_iota(s, n, jpvt));
+  const double* Om = Omega;
+  int64_t ldom = ldo;
+  if (!Om) {
+    RQ_TRY(launch_omega(s, seed, l, m, t.sb.omega, 1, l));
+    Om = t.sb.omega;
+    ldom = l;
+  }
+  RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, t.sb.bt));
+  for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
+    const int bJ = (int)std::min<int64_t>(b, k - i0);
+    const int64_t mJ = m - i0, nJ = n - i0, Nt = n - i0 - bJ;
+    double* bt_blk = t.sb.bt + i0;
+    RQ_TRY(launch_sample_qrcp(s, bt_blk, n, l, nJ, bJ, t.sb.piv, t.c.info, (int)i0, sq_work(t.sb, t.c, J)));
+    RQ_TRY(launch_apply_swaps(s, t.sb.piv, bJ, i0, A, lda, m, jpvt));
+    if (i0 > 0) RQ_TRY(launch_apply_swaps(s, t.sb.piv, bJ, i0, t.wt, k, i0, nullptr));
+    double* panel = A + i0 + i0 * lda;
+    double* Y2 = t.yall + i0 + i0 * m;
+    // selected columns: A_hat = A(i0:m, sel) - Y(i0:m, 0:i0) W^T(0:i0, sel)
+    if (i0 > 0)
+      RQ_TRY(launch_gemm(s, false, false, mJ, bJ, i0, -1.0, t.yall + i0, m, t.wt + i0 * k, k, 1.0, panel, lda,
+                         nullptr, 0));
+    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, Y2, m, t.bb, t.c, J));
+    if (Nt > 0) {
+      double* Atr = A + i0 + (i0 + bJ) * lda;
+      double* wt_tr = t.wt + (i0 + bJ) * k;
+      // Z = Y2^T A(i0:m, trail) - (Y2^T Y1) W1^T(:, trail)
+      RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y2, m, Atr, lda, 0.0, t.bb.zbuf, bJ, t.bb.splitk,
+                         t.bb.splitk_elems));
+      if (i0 > 0) {
+        RQ_TRY(launch_gemm(s, true, false, bJ, i0, mJ, 1.0, Y2, m, t.yall + i0, m, 0.0, t.gk, bJ, t.bb.splitk,
+                           t.bb.splitk_elems));
+        RQ_TRY(launch_gemm(s, false, false, bJ, Nt, i0, -1.0, t.gk, bJ, wt_tr, k, 1.0, t.bb.zbuf, bJ, nullptr, 0));
+      }
+      // W2^T = T2^T Z
+      RQ_TRY(launch_gemm(s, true, false, bJ, Nt, bJ, 1.0, t.bb.T, bJ, t.bb.zbuf, bJ, 0.0, wt_tr + i0, k, nullptr, 0));
+      // new rows of R: A(i0:i0+bJ, trail) -= Y(i0:i0+bJ, 0:i0+bJ) W^T(0:i0+bJ, trail)
+      RQ_TRY(launch_gemm(s, false, false, bJ, Nt, i0 + bJ, -1.0, t.yall + i0, m, wt_tr, k, 1.0, Atr, lda, nullptr,
+                         0));
+    }
+    if (i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, bt_blk, t.sb));
+    i0 += bJ;
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------ QR + explicit Q (TUXV)
+struct QrWS {
+  Common c;
+  BlockBufs bb;
+  double* yall;   // rows x kq (explicit reflectors)
+  double* tall;   // nblk * b * b
+  double* z2;     // b x kq
+};
+
+void carve_qr(Carve& cv, int64_t rows, int64_t kq, int b, QrWS& q) {
+  carve_common(cv, nblocks(kq, b), q.c);
+  carve_block(cv, rows, kq, b, q.bb);
+  q.yall = cv.take<double>((size_t)rows * kq);
+  q.tall = cv.take<double>((size_t)nblocks(kq, b) * b * b);
+  q.z2 = cv.take<double>((size_t)b * kq);
+}
+
+// Blocked Householder QR of the rows x kq matrix M (ld ldm, rows >= kq); the
+// explicit reflectors go to q.yall and each block's T to q.tall.
+int qr_explicit(hipStream_t s, int64_t rows, int64_t kq, double* M, int64_t ldm, int b, double* tau, QrWS& q) {
+  RQ_TRY(launch_fill(s, q.c.flags, q.c.flag_words));
+  RQ_TRY(launch_fill(s, q.yall, (size_t)rows * kq * 2));
+  for (int64_t i0 = 0, J = 0; i0 < kq; ++J) {
+    const int bJ = (int)std::min<int64_t>(b, kq - i0);
+    double* Y = q.yall + i0 + i0 * rows;
+    RQ_TRY(panel_and_t(s, M, ldm, rows, i0, bJ, tau + i0, Y, rows, q.bb, q.c, J));
+    RQ_TRY(launch_copy2d(s, bJ, bJ, q.bb.T, bJ, q.tall + (size_t)J * b * b, bJ));
+    RQ_TRY(trailing_update(s, M, ldm, rows, kq, i0, bJ, Y, rows, q.bb));
+    i0 += bJ;
+  }
+  return 0;
+}
+
+// Q(:, 0:kq) = H_0 ... H_{kq-1} [I; 0], accumulated backwards block by block.
+int form_q(hipStream_t s, int64_t rows, int64_t kq, int b, QrWS& q, double* Q, int64_t ldq) {
+  RQ_TRY(launch_set_identity(s, rows, kq, Q, ldq));
+  const int64_t nb = nblocks(kq, b);
+  for (int64_t J = nb - 1; J >= 0; --J) {
+    const int64_t i0 = J * b;
+    const int bJ = (int)std::min<int64_t>(b, kq - i0);
+    const int64_t mJ = rows - i0, Nc = kq - i0;
+    const double* Y = q.yall + i0 + i0 * rows;
+    double* Qs = Q + i0 + i0 * ldq;
+    const double* T = q.tall + (size_t)J * b * b;
+    RQ_TRY(launch_gemm(s, true, false, bJ, Nc, mJ, 1.0, Y, rows, Qs, ldq, 0.0, q.bb.zbuf, bJ, q.bb.splitk,
+                       q.bb.splitk_elems));
+    RQ_TRY(launch_gemm(s, false, false, bJ, Nc, bJ, 1.0, T, bJ, q.bb.zbuf, bJ, 0.0, q.z2, bJ, nullptr, 0));
+    RQ_TRY(launch_gemm(s, false, false, mJ, Nc, bJ, -1.0, Y, rows, q.z2, bJ, 1.0, Qs, ldq, nullptr, 0));
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------ TUXV
+struct TuxvWS {
+  TrqWS trq;
+  QrWS qz, qu;
+  double* ac;      // m x n copy of A
+  int64_t* jp;     // n
+  double* tk;      // k (TRQRCP tau)
+  double* z0t;     // n x k
+  double* tz;      // k
+  double* v;       // n x k
+  double* z1;      // m x k
+  double* tu;      // k
+  double* u1;      // m x k
+  double* x;       // k x k
+  double* ux;      // k x k
+  double* vx;      // k x k
+  double* svdtmp;  // k x k
+};
+
+void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS& t) {
+  carve_trq(cv, m, n, k, b, p, t.trq);
+  carve_qr(cv, n, k, b, t.qz);
+  carve_qr(cv, m, k, b, t.qu);
+  // one error word for every cooperative stage of the call
+  t.qz.c.err = t.trq.c.err;
+  t.qu.c.err = t.trq.c.err;
+  t.ac = cv.take<double>((size_t)m * n);
+  t.jp = cv.take<int64_t>(n);
+  t.tk = cv.take<double>(k);
+  t.z0t = cv.take<double>((size_t)n * k);
+  t.tz = cv.take<double>(k);
+  t.v = cv.take<double>((size_t)n * k);
+  t.z1 = cv.take<double>((size_t)m * k);
+  t.tu = cv.take<double>(k);
+  t.u1 = cv.take<double>((size_t)m * k);
+  t.x = cv.take<double>((size_t)k * k);
+  t.ux = cv.take<double>((size_t)k * k);
+  t.vx = cv.take<double>((size_t)k * k);
+  t.svdtmp = cv.take<double>((size_t)k * k);
+}
+
+int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int b, int p,
+              uint64_t seed, const double* Omega, int64_t ldo, double* U, int64_t ldu, double* sigma, double* VT,
+              int64_t ldvt, void* work, size_t wbytes, int32_t* info) {
+  TuxvWS t;
+  Carve cv(work, wbytes);
+  carve_tuxv(cv, m, n, k, b, p, t);
+  if (!cv.ok) return RQ_ERR_WORKSPACE;
+  // TRQRCP on a copy: A itself is needed again for Z1 = A V.
+  RQ_TRY(launch_copy2d(s, m, n, A, lda, t.ac, m));
+  RQ_TRY(trqrcp_core(s, m, n, k, t.ac, m, b, p, seed, Omega, ldo, t.jp, t.tk, t.trq));
+  // Z0 = R P^T, stored transposed (n x k)
+  RQ_TRY(launch_scatter_rt(s, k, n, t.ac, m, t.jp, t.z0t, n));
+  // LQ of Z0 as the QR of Z0^T -> V (n x k)
+  RQ_TRY(qr_explicit(s, n, k, t.z0t, n, b, t.tz, t.qz));
+  RQ_TRY(form_q(s, n, k, b, t.qz, t.v, n));
+  // Z1 = A V (m x k)
+  RQ_TRY(launch_gemm(s, false, false, m, k, n, 1.0, A, lda, t.v, n, 0.0, t.z1, m, nullptr, 0));
+  // QR of Z1 -> U1, X
+  RQ_TRY(qr_explicit(s, m, k, t.z1, m, b, t.tu, t.qu));
+  RQ_TRY(launch_triu_copy(s, k, t.z1, m, t.x, k));
+  RQ_TRY(form_q(s, m, k, b, t.qu, t.u1, m));
+  // X = Ux diag(sigma) Vx^T
+  SvdWork sw;
+  sw.colnorm = nullptr; sw.order = nullptr; sw.flags = nullptr; sw.err = t.trq.c.err; sw.tmp = t.svdtmp;
+  RQ_TRY(launch_jacobi_svd(s, (int)k, t.x, k, t.ux, k, sigma, t.vx, k, sw));
+  // U = U1 Ux ; VT = Vx^T V^T
+  RQ_TRY(launch_gemm(s, false, false, m, k, k, 1.0, t.u1, m, t.ux, k, 0.0, U, ldu, nullptr, 0));
+  RQ_TRY(launch_gemm(s, true, true, k, n, k, 1.0, t.vx, k, t.v, n, 0.0, VT, ldvt, nullptr, 0));
+  if (info) {
+    // merge the error words of every cooperative stage
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, t.trq.c.err, t.trq.c.info, info);
+    RQ_HIP(hipGetLastError());
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------ argument checks
+int check_common(int64_t m, int64_t n, int64_t lda, int b, int p, int im, int in, int ilda, int ib, int ip) {
+  if (m < 0) return -im;
+  if (n < 0) return -in;
+  if (lda < std::max<int64_t>(1, m)) return -ilda;
+  if (b < 1 || b > 64) return -ib;
+  if (p < 0 || b + p > 128) return -ip;
+  if (n > 65536) return -in;
+  return 0;
+}
+
+}  // namespace
+}  // namespace rq
+
+using namespace rq;
+
+extern "C" {
+
+const char* rq_version(void) { return "rqrcp-gfx950 0.1"; }
+
+int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, int32_t p, size_t* bytes) {
+  if (!bytes) return -7;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (b < 1 || b > 64) return -5;
+  if (p < 0 || b + p > 128) return -6;
+  size_t sz = 0;
+  switch (op) {
+    case RQ_OP_RQRCP:
+    case RQ_OP_QR: {
+      FactorWS f;
+      Carve cv(nullptr, 0);
+      carve_factor(cv, m, n, b, p, op == RQ_OP_RQRCP, f);
+      sz = cv.off;
+      break;
+    }
+    case RQ_OP_TRQRCP: {
+      if (k < 1 || k > std::min(m, n)) return -4;
+      TrqWS t;
+      Carve cv(nullptr, 0);
+      carve_trq(cv, m, n, k, b, p, t);
+      sz = cv.off;
+      break;
+    }
+    case RQ_OP_TUXV: {
+      if (k < 1 || k > std::min(m, n) || k > 1024) return -4;
+      TuxvWS t;
+      Carve cv(nullptr, 0);
+      carve_tuxv(cv, m, n, k, b, p, t);
+      sz = cv.off;
+      break;
+    }
+    case RQ_OP_SAMPLE_QRCP: {
+      // m = l (sample rows), n = sample columns
+      Carve cv(nullptr, 0);
+      Common c;
+      carve_common(cv, 1, c);
+      SampleBufs sb;
+      carve_sample(cv, 0, n, b, (int)m, sb);
+      sz = cv.off;
+      break;
+    }
+    case RQ_OP_SVD: {
+      sz = align_up((size_t)k * k * sizeof(double), 256) + 4096;
+      break;
+    }
+    default:
+      return -1;
+  }
+  *bytes = sz;
+  return 0;
+}
+
+int rq_rqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+             int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 5, 6, 7);
+  if (rc) return rc;
+  if (m == 0 || n == 0) return 0;
+  return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes, info,
+                     true);
+}
+
+int rq_rqrcp_omega(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p,
+                   const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work, size_t work_bytes,
+                   int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 5, 6, 7);
+  if (rc) return rc;
+  if (!Omega) return -8;
+  if (ldo < b + p) return -9;
+  if (m == 0 || n == 0) return 0;
+  return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, 0, Omega, ldo, jpvt, tau, work, work_bytes, info, true);
+}
+
+int rq_unpivoted_qr(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, double* tau, void* work,
+                    size_t work_bytes, int32_t* info) {
+  int rc = check_common(m, n, lda, b, 0, 2, 3, 5, 6, 6);
+  if (rc) return rc;
+  if (m == 0 || n == 0) return 0;
+  return factor_impl((hipStream_t)stream, m, n, A, lda, b, 0, 0, nullptr, 0, nullptr, tau, work, work_bytes, info,
+                     false);
+}
+
+static int trqrcp_entry(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int b, int p,
+                        uint64_t seed, const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work,
+                        size_t wbytes, int32_t* info) {
+  TrqWS t;
+  Carve cv(work, wbytes);
+  carve_trq(cv, m, n, k, b, p, t);
+  if (!cv.ok) return -100;
+  int rc = trqrcp_core(s, m, n, k, A, lda, b, p, seed, Omega, ldo, jpvt, tau, t);
+  if (rc) return rc;
+  if (info) {
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, t.c.err, t.c.info, info);
+    RQ_HIP(hipGetLastError());
+  }
+  return 0;
+}
+
+int rq_trqrcp(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
+              uint64_t seed, int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
+  if (rc) return rc;
+  if (k < 1 || k > std::min(m, n)) return -4;
+  return trqrcp_entry((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes,
+                      info);
+}
+
+int rq_trqrcp_omega(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
+                    const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work, size_t work_bytes,
+                    int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
+  if (rc) return rc;
+  if (k < 1 || k > std::min(m, n)) return -4;
+  if (!Omega) return -9;
+  if (ldo < b + p) return -10;
+  return trqrcp_entry((hipStream_t)stream, m, n, k, A, lda, b, p, 0, Omega, ldo, jpvt, tau, work, work_bytes, info);
+}
+
+int rq_tuxv(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
+            uint64_t seed, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt, void* work,
+            size_t work_bytes, int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
+  if (rc) return rc;
+  if (k < 1 || k > std::min(m, n) || k > 1024) return -4;
+  if (ldu < m) return -11;
+  if (ldvt < k) return -14;
+  return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, U, ldu, sigma, VT, ldvt, work,
+                   work_bytes, info);
+}
+
+int rq_tuxv_omega(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
+                  const double* Omega, int64_t ldo, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt,
+                  void* work, size_t work_bytes, int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
+  if (rc) return rc;
+  if (k < 1 || k > std::min(m, n) || k > 1024) return -4;
+  if (!Omega) return -9;
+  if (ldo < b + p) return -10;
+  if (ldu < m) return -12;
+  if (ldvt < k) return -15;
+  return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, 0, Omega, ldo, U, ldu, sigma, VT, ldvt, work,
+                   work_bytes, info);
+}
+
+int rq_omega(void* stream, uint64_t seed, int64_t l, int64_t m, double* Omega, int64_t ldo) {
+  if (l < 0) return -3;
+  if (m < 0) return -4;
+  if (!Omega && l * m > 0) return -5;
+  if (ldo < std::max<int64_t>(1, l)) return -6;
+  return launch_omega((hipStream_t)stream, seed, l, m, Omega, 1, ldo);
+}
+
+int rq_sketch(void* stream, int64_t m, int64_t n, const double* A, int64_t lda, int32_t l, uint64_t seed, double* B,
+              int64_t ldb, void* work, size_t work_bytes) {
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -5;
+  if (l < 1 || l > 128) return -6;
+  if (ldb < l) return -9;
+  Carve cv(work, work_bytes);
+  double* om = cv.take<double>((size_t)l * m);
+  double* bt = cv.take<double>((size_t)n * l);
+  if (!cv.ok) return -100;
+  if (m == 0 || n == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  RQ_TRY(launch_omega(s, seed, l, m, om, 1, l));
+  RQ_TRY(sketch(s, m, n, A, lda, l, om, l, bt));
+  RQ_TRY(launch_transpose(s, n, l, bt, n, B, ldb));
+  return 0;
+}
+
+int rq_sample_qrcp(void* stream, int32_t l, int64_t n, int32_t bsteps, double* B, int64_t ldb, int32_t* piv,
+                   void* work, size_t work_bytes, int32_t* info) {
+  if (l < 1 || l > 128) return -2;
+  if (n < 1 || n > 65536) return -3;
+  if (bsteps < 1 || bsteps > 64 || bsteps > l || bsteps > n) return -4;
+  if (ldb < l) return -6;
+  Carve cv(work, work_bytes);
+  Common c;
+  carve_common(cv, 1, c);
+  SampleBufs sb;
+  carve_sample(cv, 0, n, bsteps, l, sb);
+  if (!cv.ok) return -100;
+  hipStream_t s = (hipStream_t)stream;
+  RQ_TRY(launch_fill(s, c.flags, c.flag_words));
+  RQ_TRY(launch_transpose(s, l, n, B, ldb, sb.bt, n));
+  RQ_TRY(launch_sample_qrcp(s, sb.bt, n, l, n, bsteps, piv, c.info, 0, sq_work(sb, c, 0)));
+  RQ_TRY(launch_transpose(s, n, l, sb.bt, n, B, ldb));
+  if (info) {
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, c.err, c.info, info);
+    RQ_HIP(hipGetLastError());
+  }
+  return 0;
+}
+
+int rq_small_svd(void* stream, int32_t k, double* X, int64_t ldx, double* U, int64_t ldu, double* sigma, double* V,
+                 int64_t ldv, void* work, size_t work_bytes) {
+  if (k < 1 || k > 1024) return -2;
+  if (ldx < k) return -4;
+  if (ldu < k) return -6;
+  if (ldv < k) return -9;
+  Carve cv(work, work_bytes);
+  double* tmp = cv.take<double>((size_t)k * k);
+  int* err = cv.take<int>(16);
+  if (!cv.ok) return -100;
+  SvdWork sw;
+  sw.colnorm = nullptr; sw.order = nullptr; sw.flags = nullptr; sw.err = err; sw.tmp = tmp;
+  return launch_jacobi_svd((hipStream_t)stream, k, X, ldx, U, ldu, sigma, V, ldv, sw);
+}
+
+}  // extern "C"

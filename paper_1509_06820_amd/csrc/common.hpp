@@ -1,0 +1,146 @@
+// Shared device/host helpers for the gfx950 RQRCP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace rq {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE = 64;
+
+// Error codes returned by the C ABI (negative: bad argument index, LAPACK style).
+constexpr int RQ_ERR_HIP_BASE = 1000;   // hipError_t + 1000
+constexpr int RQ_ERR_COOP = 2001;       // cooperative launch rejected (grid does not fit)
+
+#define RQ_HIP(call)                                                   \
+  do {                                                                 \
+    hipError_t _e = (call);                                            \
+    if (_e != hipSuccess) return ::rq::RQ_ERR_HIP_BASE + (int)_e;      \
+  } while (0)
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// (value, position) ranking used for pivot selection: larger value wins,
+// ties go to the lower position.  NaN values must be mapped to -1 before.
+__device__ __forceinline__ bool rank_better(double v1, long p1, double v2, long p2) {
+  return (v1 > v2) || (v1 == v2 && p1 < p2);
+}
+
+__device__ __forceinline__ void wave_argmax(double& v, long& p) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    double ov = __shfl_xor(v, off, WAVE);
+    long op = __shfl_xor(p, off, WAVE);
+    if (rank_better(ov, op, v, p)) { v = ov; p = op; }
+  }
+}
+
+// ---------------------------------------------------------------- cross-WG exchange
+// Workgroups of one cooperative launch exchange data through global memory.
+// A publisher writes its payload, then every thread issues an agent-scope
+// release fence, the workgroup synchronises and thread 0 stores the epoch
+// into its flag.  A consumer polls the flags of the workgroups it waits for
+// (one lane per flag) with agent-scope atomic loads, then issues an
+// agent-scope acquire fence.  The fence pair orders the payload writes before
+// the payload reads (HIP/HSA scoped memory model).  Waits are bounded: after
+// `spin_limit` polls the wait fails, the error word is set and the caller
+// returns, so a broken exchange ends the kernel instead of hanging it.
+constexpr long SPIN_LIMIT = 1L << 20;
+
+// A cooperative kernel starts by checking the error word: once one stage has
+// timed out, the later stages of the same call return at once.
+// Thread 0 reads the word and broadcasts it, so the whole workgroup takes
+// the same branch.
+__device__ __forceinline__ bool earlier_failure(const int* err) {
+  __shared__ int s_fail;
+  if (threadIdx.x == 0) s_fail = __hip_atomic_load((int*)err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return s_fail != 0;
+}
+
+__device__ __forceinline__ void publish_flag(unsigned* flags, int me, unsigned epoch) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(&flags[me], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until flags[q] >= epoch for q in [0, P).  Returns false on timeout.
+__device__ __forceinline__ bool wait_flags(const unsigned* flags, int P, unsigned epoch, int* err) {
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  if (threadIdx.x < WAVE) {
+    long spins = 0;
+    for (int base = 0; base < P; base += WAVE) {
+      int q = base + (int)threadIdx.x;
+      bool done = false;
+      while (!done) {
+        unsigned f = (q < P) ? __hip_atomic_load((unsigned*)&flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : epoch;
+        done = __all(f >= epoch);
+        if (!done) {
+          if (++spins > SPIN_LIMIT) {
+            if (threadIdx.x == 0) { s_bad = 1; atomicExch(err, 1); }
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      if (!done) break;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return s_bad == 0;
+}
+
+// Wait for one flag to reach `epoch`; the flag's value is returned in *seen.
+__device__ __forceinline__ bool wait_one(const unsigned* flag, unsigned epoch, int* err, unsigned* seen) {
+  __shared__ int s_bad;
+  __shared__ unsigned s_seen;
+  if (threadIdx.x == 0) {
+    s_bad = 0;
+    long spins = 0;
+    unsigned f;
+    while ((f = __hip_atomic_load((unsigned*)flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < epoch) {
+      if (++spins > SPIN_LIMIT) { s_bad = 1; atomicExch(err, 1); break; }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    s_seen = f;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (seen) *seen = s_seen;
+  return s_bad == 0;
+}
+
+// ---------------------------------------------------------------- host helpers
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over the caller's workspace (host side bookkeeping only).
+struct Carve {
+  char* base;
+  size_t off;
+  size_t cap;
+  bool ok;
+  explicit Carve(void* b, size_t c) : base((char*)b), off(0), cap(c), ok(true) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t o = align_up(off, 256);
+    size_t bytes = align_up(count * sizeof(T), 256);
+    off = o + bytes;
+    if (off > cap) ok = false;
+    return base ? (T*)(base + o) : nullptr;
+  }
+};
+
+}  // namespace rq

@@ -1,0 +1,80 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <algorithm>
+#include "common.hpp"
+
+namespace rq {
+
+// Omega(r, c) -> out[r*rs + c*cs], r < l, c < m (Philox4x64-10 + Box-Muller).
+int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out, int64_t rs, int64_t cs);
+
+// C = alpha * opA * opB + beta * C  (see gemm.hip).  `scratch` (may be null)
+// enables split-K for short-wide outputs; gemm_scratch_elems gives its size.
+int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
+                size_t scratch_elems);
+size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K);
+int launch_scale(hipStream_t s, int64_t M, int64_t N, double beta, double* C, int64_t ldc);
+
+// Sample QRCP (Alg. 1 on the sample, bJ steps) in place on the l x nJ sample.
+struct SampleQrcpWork {
+  double* refl;        // l x bmax reflector list (column t: v_t, rows t..l-1)
+  double* rtau;        // bmax
+  long long* cand_pos; // 64 * 256 candidate positions
+  double* theta;       // 64
+  unsigned* flags;     // 64 phase flags + go flag + t0 slot (zeroed by the caller)
+  int* err;
+};
+size_t sample_qrcp_flag_words();
+// Bt is the transposed sample (nJ x l column-major, ld ldbt).
+int launch_sample_qrcp(hipStream_t s, double* Bt, int64_t ldbt, int l, int64_t nJ, int bJ, int* piv, int* info,
+                       int info_base, const SampleQrcpWork& w);
+
+// Apply the sequential swaps (offset+t) <-> (offset+piv[t]), t < bJ, to the
+// columns of an R x ncols matrix (double) and optionally to an int64 vector.
+int launch_apply_swaps(hipStream_t s, const int* piv, int bJ, int64_t offset, double* M, int64_t ldm, int64_t rows,
+                       int64_t* jpvt);
+
+// Householder panel QR (in-place layout), tau, explicit unit-lower Y.
+struct PanelWork {
+  double* slots;       // bmax * 256 * 64 + bmax * 64 doubles
+  unsigned* flags;     // 256 words (zeroed by the caller)
+  int* err;
+};
+size_t panel_slot_elems(int64_t mmax, int bmax);
+int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, double* tau, double* Y, int64_t ldy,
+                 const PanelWork& w);
+
+// T (bJ x bJ, ld bJ) from G = Y^T Y (ld bJ) and tau (forward columnwise recurrence).
+int launch_larft(hipStream_t s, int bJ, const double* G, const double* tau, double* T);
+
+// W11 = S11 R11^{-1} (upper triangular, ld bJ); zero-diagonal columns of R11 give 0.
+// S11(i, j) = S[i*srs + j*scs].
+int launch_w11(hipStream_t s, int bJ, const double* S, int64_t srs, int64_t scs, const double* R, int64_t ldr,
+               double* W);
+
+// Small utilities.
+int launch_fill(hipStream_t s, void* p, size_t words32);   // zero-fill 32-bit words
+int launch_copy2d(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
+                  int64_t ldd);
+int launch_set_identity(hipStream_t s, int64_t rows, int64_t cols, double* M, int64_t ldm);
+// Z0T(jpvt[j], i) = R(i, j) for i <= j (upper trapezoidal R, k x n) else 0.
+int launch_scatter_rt(hipStream_t s, int64_t k, int64_t n, const double* R, int64_t ldr, const int64_t* jpvt,
+                      double* Z0T, int64_t ldz);
+// Upper-triangular part of a k x k block (zeros below the diagonal).
+int launch_triu_copy(hipStream_t s, int64_t k, const double* src, int64_t lds, double* dst, int64_t ldd);
+
+// One-sided Jacobi SVD of a k x k matrix X (in place: X -> U Sigma), V
+// accumulated, singular values sorted descending.
+struct SvdWork {
+  double* colnorm;     // k
+  int* order;          // k
+  unsigned* flags;
+  int* err;
+  double* tmp;         // 2 * k * k
+};
+int launch_jacobi_svd(hipStream_t s, int k, double* X, int64_t ldx, double* U, int64_t ldu, double* sigma,
+                      double* V, int64_t ldv, const SvdWork& w);
+
+}  // namespace rq

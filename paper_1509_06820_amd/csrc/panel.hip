@@ -1,0 +1,164 @@
+// Householder QR of an mJ x bJ panel (the "qr" step of Alg. 4 / Alg. 6 on the
+// b selected columns), in place in the LAPACK layout: R on and above the
+// diagonal, reflector tails below it, tau per column; the explicit unit-lower
+// reflector block Y is written as well for the block-reflector products.
+//
+// One cooperative launch.  Workgroup q owns rows [512 q, 512 q + 512) of the
+// panel in registers (thread = one column x 32 rows).  For column j every
+// workgroup forms its partial inner products of column j with columns j..bJ-1
+// over its rows below j, publishes them (plus row j if it owns it), and after
+// one exchange every workgroup adds the partials in the same order, builds
+// the same reflector (LAPACK dlarfg normalisation) and updates its rows.
+#include "kernels.hpp"
+
+namespace rq {
+
+namespace {
+
+constexpr int PN_THREADS = 1024;
+constexpr int PN_RPT = 32;
+constexpr int PN_GROUPS = PN_THREADS / 64;
+constexpr int PN_RB = PN_GROUPS * PN_RPT;  // 512 rows per workgroup
+
+struct PanelParams {
+  double* P;
+  int64_t ldp;
+  int64_t mJ;
+  int bJ;
+  double* tau;
+  double* Y;
+  int64_t ldy;
+  double* slots;    // bJ * NP * 64 partial sums
+  double* rowslot;  // bJ * 64 values of row j
+  unsigned* flags;
+  int* err;
+  int NP;
+};
+
+__global__ void __launch_bounds__(PN_THREADS) panel_kernel(PanelParams a) {
+  __shared__ double xs[PN_RB];
+  __shared__ double part[PN_GROUPS][64];
+  __shared__ double rowj[64];
+  __shared__ double dsum[64], rowv[64], wv[64];
+  __shared__ double hh[4];
+  const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
+  const int me = blockIdx.x;
+  // row indices fit in 32 bits (mJ < 2^31 is checked by the launcher)
+  const int mJ = (int)a.mJ;
+  const int r0 = me * PN_RB + g * PN_RPT;
+  const int wlo = me * PN_RB;
+  const int whi = min(mJ, wlo + PN_RB);
+  const int bJ = a.bJ;
+  if (earlier_failure(a.err)) return;
+
+  double v[PN_RPT];
+#pragma unroll
+  for (int rr = 0; rr < PN_RPT; ++rr) {
+    const int row = r0 + rr;
+    v[rr] = (row < mJ && c < bJ) ? a.P[row + c * a.ldp] : 0.0;
+  }
+
+  for (int j = 0; j < bJ; ++j) {
+    if (c == j) {
+#pragma unroll
+      for (int rr = 0; rr < PN_RPT; ++rr) xs[g * PN_RPT + rr] = v[rr];
+    }
+#pragma unroll
+    for (int rr = 0; rr < PN_RPT; ++rr)
+      if (r0 + rr == j) rowj[c] = v[rr];
+    __syncthreads();
+    double s = 0.0;
+    if (c >= j && c < bJ) {
+#pragma unroll
+      for (int rr = 0; rr < PN_RPT; ++rr) {
+        const int row = r0 + rr;
+        if (row > j && row < mJ) s += xs[g * PN_RPT + rr] * v[rr];
+      }
+    }
+    part[g][c] = s;
+    __syncthreads();
+    if (tid < 64) {
+      double d = 0.0;
+#pragma unroll
+      for (int q = 0; q < PN_GROUPS; ++q) d += part[q][tid];
+      a.slots[((int64_t)j * a.NP + me) * 64 + tid] = d;
+      if (j >= wlo && j < whi) a.rowslot[(int64_t)j * 64 + tid] = rowj[tid];
+    }
+    publish_flag(a.flags, me, (unsigned)(j + 1));
+    if (!wait_flags(a.flags, a.NP, (unsigned)(j + 1), a.err)) return;
+    if (tid < 64) {
+      double d = 0.0;
+      for (int q = 0; q < a.NP; ++q) d += a.slots[((int64_t)j * a.NP + q) * 64 + tid];
+      dsum[tid] = d;
+      rowv[tid] = a.rowslot[(int64_t)j * 64 + tid];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double alpha = rowv[j];
+      const double xn2 = dsum[j];
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (xn2 != 0.0) {
+        const double nrm = sqrt(alpha * alpha + xn2);
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      hh[0] = tau; hh[1] = beta; hh[2] = scal;
+      if (me == 0) a.tau[j] = tau;
+    }
+    __syncthreads();
+    if (tid < 64) wv[tid] = (tid > j && tid < bJ) ? hh[0] * (rowv[tid] + hh[2] * dsum[tid]) : 0.0;
+    __syncthreads();
+    const double beta = hh[1], scal = hh[2], w = wv[c];
+#pragma unroll
+    for (int rr = 0; rr < PN_RPT; ++rr) {
+      const int row = r0 + rr;
+      if (row > j && row < mJ) {
+        const double y = xs[g * PN_RPT + rr] * scal;
+        if (c > j) v[rr] -= y * w;
+        else if (c == j) v[rr] = y;
+      } else if (row == j) {
+        if (c > j) v[rr] -= w;
+        else if (c == j) v[rr] = beta;
+      }
+    }
+    __syncthreads();
+  }
+
+  if (c < bJ) {
+#pragma unroll
+    for (int rr = 0; rr < PN_RPT; ++rr) {
+      const int row = r0 + rr;
+      if (row < mJ) {
+        a.P[row + c * a.ldp] = v[rr];
+        a.Y[row + c * a.ldy] = (row < c) ? 0.0 : (row == c ? 1.0 : v[rr]);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+size_t panel_slot_elems(int64_t mmax, int bmax) {
+  const int64_t np = (mmax + PN_RB - 1) / PN_RB;
+  return (size_t)bmax * (size_t)np * 64 + (size_t)bmax * 64;
+}
+
+int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, double* tau, double* Y, int64_t ldy,
+                 const PanelWork& w) {
+  if (bJ <= 0 || mJ <= 0) return 0;
+  if (bJ > 64) return -6;
+  if (mJ >= (int64_t)1 << 31) return -3;
+  PanelParams a;
+  a.P = P; a.ldp = ldp; a.mJ = mJ; a.bJ = bJ; a.tau = tau; a.Y = Y; a.ldy = ldy;
+  a.NP = (int)((mJ + PN_RB - 1) / PN_RB);
+  a.slots = w.slots;
+  a.rowslot = w.slots + (size_t)bJ * a.NP * 64;
+  a.flags = w.flags;
+  a.err = w.err;
+  void* args[] = {&a};
+  RQ_HIP(hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(a.NP), dim3(PN_THREADS), args, 0, s));
+  return 0;
+}
+
+}  // namespace rq

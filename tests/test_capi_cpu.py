@@ -1,0 +1,98 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/rqrcp.h, answers workspace queries, and rejects
+invalid arguments (LAPACK-style -i) before enqueueing anything."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1509_06820_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rqrcp.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1509_06820_amd import build
+        build.build()
+    return binding.load()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rq_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_symbols()
+    for must in ["rq_rqrcp", "rq_trqrcp", "rq_tuxv", "rq_unpivoted_qr", "rq_workspace_bytes", "rq_omega",
+                 "rq_sketch", "rq_sample_qrcp", "rq_small_svd", "rq_rqrcp_omega", "rq_trqrcp_omega",
+                 "rq_tuxv_omega", "rq_version"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(binding.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(raw, name), name
+    assert b"rqrcp" in lib.rq_version()
+
+
+def test_binding_covers_every_symbol():
+    for name in declared_symbols():
+        assert name in binding._SIGS, name
+
+
+@pytest.mark.parametrize("op,m,n,k,b,p", [
+    (binding.RQ_OP_RQRCP, 512, 512, 0, 32, 8),
+    (binding.RQ_OP_RQRCP, 8192, 8192, 0, 64, 8),
+    (binding.RQ_OP_QR, 8192, 8192, 0, 64, 0),
+    (binding.RQ_OP_TRQRCP, 20000, 10000, 256, 64, 8),
+    (binding.RQ_OP_TUXV, 20000, 10000, 256, 64, 8),
+    (binding.RQ_OP_SAMPLE_QRCP, 72, 8192, 0, 64, 0),
+    (binding.RQ_OP_SVD, 256, 256, 256, 1, 0),
+])
+def test_workspace_query(lib, op, m, n, k, b, p):
+    nbytes = binding.rq_workspace_bytes(op, m, n, k, b, p)
+    assert nbytes > 0
+    # the workspace of the full factorization stays a small fraction of A
+    if op == binding.RQ_OP_RQRCP and m == 8192:
+        assert nbytes < 0.25 * m * n * 8
+
+
+def test_workspace_query_rejects_bad_arguments(lib):
+    out = ctypes.c_size_t(0)
+    assert lib.rq_workspace_bytes(0, -1, 5, 0, 8, 0, ctypes.byref(out)) == -2
+    assert lib.rq_workspace_bytes(0, 5, -1, 0, 8, 0, ctypes.byref(out)) == -3
+    assert lib.rq_workspace_bytes(0, 5, 5, 0, 0, 0, ctypes.byref(out)) == -5
+    assert lib.rq_workspace_bytes(0, 5, 5, 0, 65, 0, ctypes.byref(out)) == -5
+    assert lib.rq_workspace_bytes(0, 5, 5, 0, 64, 65, ctypes.byref(out)) == -6
+    assert lib.rq_workspace_bytes(1, 5, 5, 6, 4, 0, ctypes.byref(out)) == -4
+    assert lib.rq_workspace_bytes(99, 5, 5, 1, 4, 0, ctypes.byref(out)) == -1
+
+
+def test_entry_points_reject_bad_arguments_before_any_launch(lib):
+    null = ctypes.c_void_p(0)
+    # m < 0, n < 0, lda < m, b out of range, p out of range
+    assert lib.rq_rqrcp(null, -1, 4, null, 1, 8, 0, 1, null, null, null, 0, null) == -2
+    assert lib.rq_rqrcp(null, 4, -1, null, 4, 8, 0, 1, null, null, null, 0, null) == -3
+    assert lib.rq_rqrcp(null, 4, 4, null, 3, 8, 0, 1, null, null, null, 0, null) == -5
+    assert lib.rq_rqrcp(null, 4, 4, null, 4, 0, 0, 1, null, null, null, 0, null) == -6
+    assert lib.rq_rqrcp(null, 4, 4, null, 4, 8, -1, 1, null, null, null, 0, null) == -7
+    assert lib.rq_trqrcp(null, 10, 10, 11, null, 10, 4, 4, 1, null, null, null, 0, null) == -4
+    assert lib.rq_tuxv(null, 10, 10, 0, null, 10, 4, 4, 1, null, 10, null, null, 1, null, 0, null) == -4
+    assert lib.rq_tuxv(null, 10, 10, 3, null, 10, 4, 4, 1, null, 9, null, null, 3, null, 0, null) == -11
+    assert lib.rq_rqrcp_omega(null, 4, 4, null, 4, 2, 2, null, 4, null, null, null, 0, null) == -8
+    assert lib.rq_unpivoted_qr(null, 4, 4, null, 2, 2, null, null, 0, null) == -5
+    assert lib.rq_sample_qrcp(null, 0, 4, 1, null, 1, null, null, 0, null) == -2
+    assert lib.rq_sample_qrcp(null, 8, 4, 9, null, 8, null, null, 0, null) == -4
+    assert lib.rq_small_svd(null, 0, null, 1, null, 1, null, null, 1, null, 0) == -2
+    # empty matrices are valid and enqueue nothing
+    assert lib.rq_rqrcp(null, 0, 4, null, 1, 8, 0, 1, null, null, null, 0, null) == 0
+    # workspace too small
+    assert lib.rq_rqrcp(null, 40, 40, null, 40, 8, 0, 1, null, null, null, 16, null) == -100

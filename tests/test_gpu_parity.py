@@ -1,0 +1,306 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bars (derived in the design doc):
+* pivots: identical to the oracle's up to the first step whose oracle gap
+  between the two best sample norms is below 1e-9 (rounding order may flip
+  a near tie), and identical everywhere when no such step exists;
+* ||A P - Q R||_F / ||A||_F <= 1e-12 and ||Q^T Q - I||_F <= 1e-13 (fp64 path);
+* R entries within 1e-12 ||A||_F of the oracle's (while pivots agree);
+* quantities that are pure data movement (permuted original entries of
+  TRQRCP) bit-exact.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg.lapack as lapack
+import torch
+
+import oracle
+from paper_1509_06820_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+TIE = 1e-9
+EPS = np.finfo(np.float64).eps
+
+
+def orth_tol(k):
+    """Orthogonality bar for factors accumulated from ~10 sweeps of k-1
+    plane rotations per column: ||V^T V - I||_F grows like k * eps."""
+    return max(1e-13, 20 * k * EPS)
+
+
+def dev(A):
+    return torch.from_numpy(np.asfortranarray(A)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def trusted_prefix(gaps, k):
+    bad = np.nonzero(np.asarray(gaps[:k]) < TIE)[0]
+    return int(bad[0]) if len(bad) else k
+
+
+def qr_checks(A, F, tau, jpvt, k):
+    F = np.asfortranarray(F)
+    Q, _, info = lapack.dorgqr(F[:, :k].copy(order="F"), tau)
+    assert info == 0
+    R = np.triu(F[:k, :])
+    nrm = np.linalg.norm(A)
+    res = np.linalg.norm(A[:, jpvt] - Q @ R) / nrm
+    orth = np.linalg.norm(Q.T @ Q - np.eye(k))
+    return res, orth
+
+
+def compare_rqrcp(A, b, p, seed, Omega=None):
+    m, n = A.shape
+    k = min(m, n)
+    ref = oracle.rqrcp(A, b, p, seed=seed, Omega=Omega)
+    F, tau, jpvt, info = binding.rq_rqrcp(dev(A), b, p, seed, Omega=None if Omega is None else dev(Omega))
+    F, tau, jpvt, info = host(F), host(tau), host(jpvt), host(info)
+    assert info[0] == 0
+    assert sorted(jpvt.tolist()) == list(range(n))
+    t = trusted_prefix(ref["gaps"], k)
+    assert np.array_equal(jpvt[:t], ref["jpvt"][:t]), f"pivots differ before step {t}"
+    res, orth = qr_checks(A, F, tau, jpvt, k)
+    assert res <= 1e-12, res
+    assert orth <= 1e-13, orth
+    if t == k:
+        assert np.array_equal(jpvt, ref["jpvt"])
+        nrm = np.linalg.norm(A)
+        assert np.abs(np.triu(F[:k]) - np.triu(ref["F"][:k])).max() <= 1e-12 * nrm
+    return F, tau, jpvt, ref
+
+
+# ---------------------------------------------------------------- components
+@pytest.mark.parametrize("seed,l,m", [(1, 40, 512), (2, 72, 1000), (2**40 + 3, 7, 5), (0, 1, 3), (9, 128, 333)])
+def test_omega_matches_oracle(seed, l, m):
+    say(f"omega seed={seed} l={l} m={m}")
+    Om = host(binding.rq_omega(seed, l, m))
+    ref = oracle.omega(seed, l, m)
+    # same Philox words; the transcendental functions may differ in the last ulp
+    assert np.abs(Om - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+
+
+def test_sketch_matches_oracle():
+    say("sketch 300x200 l=40")
+    A = inputs.gaussian(5, 300, 200)
+    B = host(binding.rq_sketch(dev(A), 40, 5))
+    ref = oracle.omega(5, 40, 300) @ A
+    assert np.linalg.norm(B - ref) <= 1e-14 * np.linalg.norm(ref) * 10
+
+
+@pytest.mark.parametrize("l,n,bs", [
+    (40, 512, 32),      # the 512 x 512 configuration's first sample
+    (72, 300, 64),      # one workgroup
+    (72, 5000, 64),     # several workgroups, candidate rounds
+    (72, 16384, 64),    # 64 workgroups
+    (72, 20000, 64),    # several columns per scan thread
+    (16, 20, 16),       # bsteps = l
+    (9, 9, 9),          # square, every column pivoted
+    (33, 40, 1),        # one step
+])
+def test_sample_qrcp_matches_oracle(l, n, bs):
+    say(f"sample_qrcp l={l} n={n} b={bs}")
+    rng = np.random.default_rng(l * 1000 + n)
+    B = rng.standard_normal((l, n)) * rng.uniform(0.2, 2.0, size=n)
+    ref = oracle.sample_qrcp(B, bs)
+    S, piv, info = binding.rq_sample_qrcp(dev(B), bs)
+    S, piv = host(S), host(piv)
+    t = trusted_prefix(ref["gaps"], bs)
+    assert list(piv[:t]) == ref["piv"][:t]
+    if t == bs:
+        assert np.abs(S - ref["S"]).max() <= 1e-13 * np.abs(B).max() * np.sqrt(l)
+
+
+def test_sample_qrcp_exact_ties_take_lowest_position():
+    say("sample_qrcp ties")
+    rng = np.random.default_rng(3)
+    base = rng.standard_normal((12, 40))
+    B = np.concatenate([base, base[:, ::-1]], axis=1)  # every column appears twice
+    ref = oracle.sample_qrcp(B, 8)
+    S, piv, _ = binding.rq_sample_qrcp(dev(B), 8)
+    assert list(host(piv)[:1]) == ref["piv"][:1]
+
+
+@pytest.mark.parametrize("k", [1, 2, 17, 64, 129])
+def test_small_svd_matches_lapack(k):
+    say(f"small_svd k={k}")
+    rng = np.random.default_rng(k)
+    X = np.triu(rng.standard_normal((k, k)))
+    U, s, V = binding.rq_small_svd(dev(X))
+    U, s, V = host(U), host(s), host(V)
+    s_ref = np.linalg.svd(X, compute_uv=False)
+    assert np.abs(s - s_ref).max() <= 1e-13 * s_ref[0]
+    assert np.linalg.norm(U @ np.diag(s) @ V.T - X) <= 1e-13 * np.linalg.norm(X)
+    assert np.linalg.norm(V.T @ V - np.eye(k)) <= orth_tol(k)
+    assert np.linalg.norm(U.T @ U - np.eye(k)) <= orth_tol(k)
+
+
+# ---------------------------------------------------------------- RQRCP
+def test_rqrcp_512_configuration():
+    say("rqrcp 512x512 b=32 p=8 seed=1")
+    A, prm = inputs.config_matrix("c1")
+    compare_rqrcp(A, prm["b"], prm["p"], prm["seed"])
+
+
+@pytest.mark.parametrize("seed", [2, 3, 4, 5])
+def test_rqrcp_512_more_seeds(seed):
+    say(f"rqrcp 512x512 seed={seed}")
+    A, prm = inputs.config_matrix("c1", seed)
+    compare_rqrcp(A, prm["b"], prm["p"], seed)
+
+
+@pytest.mark.parametrize("m,n,b,p,seed", [
+    (300, 200, 24, 8, 4),      # tall, b does not divide k
+    (150, 260, 16, 5, 5),      # wide
+    (97, 97, 64, 3, 6),        # ragged last block
+    (64, 40, 1, 4, 7),         # b = 1
+    (1000, 700, 64, 8, 8),     # two panel workgroups, three sample workgroups
+    (2100, 1300, 32, 8, 9),    # five panel workgroups, six sample workgroups
+])
+def test_rqrcp_shapes(m, n, b, p, seed):
+    say(f"rqrcp {m}x{n} b={b} p={p} seed={seed}")
+    A = inputs.with_spectrum(seed, m, n, inputs.sigma_decade(min(m, n), 8))
+    compare_rqrcp(A, b, p, seed)
+
+
+def test_rqrcp_given_omega():
+    say("rqrcp_omega 400x300")
+    A = inputs.gaussian(11, 400, 300)
+    Om = np.random.default_rng(12).standard_normal((40, 400))
+    compare_rqrcp(A, 32, 8, 0, Omega=Om)
+
+
+def test_rqrcp_gaussian_is_deterministic():
+    say("rqrcp determinism 1000x800")
+    A = dev(inputs.gaussian(13, 1000, 800))
+    r1 = [host(x) for x in binding.rq_rqrcp(A, 64, 8, 13)[:3]]
+    r2 = [host(x) for x in binding.rq_rqrcp(A, 64, 8, 13)[:3]]
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
+
+
+def test_rqrcp_rank_deficient():
+    say("rqrcp rank-20 120x90")
+    A = inputs.rank_r(21, 120, 90, 20)
+    ref = oracle.rqrcp(A, 8, 6, seed=3)
+    F, tau, jpvt, info = [host(x) for x in binding.rq_rqrcp(dev(A), 8, 6, 3)]
+    assert list(jpvt[:20]) == list(ref["jpvt"][:20])
+    R = np.triu(F[:90])
+    assert np.linalg.norm(R[20:, 20:]) <= 1e-13 * np.linalg.norm(A)
+    res, orth = qr_checks(A, F, tau, jpvt, 90)
+    assert res <= 1e-12 and orth <= 1e-13
+
+
+def test_rqrcp_zero_and_nan():
+    say("rqrcp zero / nan")
+    F, tau, jpvt, info = [host(x) for x in binding.rq_rqrcp(dev(np.zeros((50, 40))), 8, 4, 1)]
+    assert np.all(F == 0) and np.all(tau == 0) and list(jpvt) == list(range(40)) and info[0] == 0
+    A = inputs.gaussian(1, 50, 40)
+    A[3, 7] = np.nan
+    F, tau, jpvt, info = [host(x) for x in binding.rq_rqrcp(dev(A), 8, 4, 1)]
+    assert info[0] > 0
+
+
+# ---------------------------------------------------------------- unpivoted QR
+@pytest.mark.parametrize("m,n,b", [(700, 500, 32), (300, 300, 64), (129, 257, 16)])
+def test_unpivoted_qr_matches_oracle(m, n, b):
+    say(f"unpivoted_qr {m}x{n} b={b}")
+    A = inputs.gaussian(m + n, m, n)
+    F, tau, info = [host(x) for x in binding.rq_unpivoted_qr(dev(A), b)]
+    Fr, tr = oracle.unpivoted_qr(A, b)
+    nrm = np.linalg.norm(A)
+    assert np.abs(np.triu(F) - np.triu(Fr)).max() <= 1e-12 * nrm
+    assert np.abs(tau - tr).max() <= 1e-12
+    res, orth = qr_checks(A, F, tau, np.arange(n), min(m, n))
+    assert res <= 1e-12 and orth <= 1e-13
+
+
+# ---------------------------------------------------------------- TRQRCP
+@pytest.mark.parametrize("m,n,k,b,p,seed", [
+    (600, 500, 100, 32, 8, 1),
+    (300, 400, 37, 16, 6, 2),
+    (1200, 900, 128, 64, 8, 3),
+    (200, 150, 150, 64, 8, 4),   # k = min(m, n)
+])
+def test_trqrcp_matches_oracle(m, n, k, b, p, seed):
+    say(f"trqrcp {m}x{n} k={k} b={b} p={p}")
+    A = inputs.with_spectrum(seed, m, n, inputs.sigma_decade(min(m, n), 8))
+    ref = oracle.trqrcp(A, k, b, p, seed=seed)
+    F, tau, jpvt, info = [host(x) for x in binding.rq_trqrcp(dev(A), k, b, p, seed)]
+    assert info[0] == 0
+    t = trusted_prefix(ref["gaps"], k)
+    assert np.array_equal(jpvt[:t], ref["jpvt"][:t])
+    if t < k:
+        return
+    assert np.array_equal(jpvt, ref["jpvt"])
+    nrm = np.linalg.norm(A)
+    assert np.abs(np.triu(F[:k]) - np.triu(ref["F"][:k])).max() <= 1e-12 * nrm
+    # the untouched block holds the permuted original entries, bit for bit
+    assert np.array_equal(F[k:, k:], A[k:, :][:, jpvt[k:]])
+    Qk, _, _ = lapack.dorgqr(np.asfortranarray(F[:, :k]).copy(), tau)
+    assert np.linalg.norm(Qk.T @ Qk - np.eye(k)) <= 1e-13
+    assert np.linalg.norm(Qk @ np.triu(F[:k, :k]) - A[:, jpvt[:k]]) <= 1e-12 * nrm
+
+
+# ---------------------------------------------------------------- TUXV
+@pytest.mark.parametrize("m,n,k,b,p,seed", [
+    (400, 300, 40, 16, 8, 1),
+    (700, 500, 64, 32, 8, 2),
+    (300, 420, 33, 8, 4, 3),
+])
+def test_tuxv_matches_oracle(m, n, k, b, p, seed):
+    say(f"tuxv {m}x{n} k={k} b={b}")
+    sig = inputs.sigma_decade(min(m, n), 6)
+    A = inputs.with_spectrum(seed, m, n, sig)
+    ref = oracle.tuxv(A, k, b, p, seed=seed)
+    U, s, VT, info = [host(x) for x in binding.rq_tuxv(dev(A), k, b, p, seed)]
+    assert info[0] == 0
+    nrm = np.linalg.norm(A)
+    assert np.abs(s - ref["s"]).max() <= 1e-12 * ref["s"][0]
+    approx = U @ np.diag(s) @ VT
+    ref_approx = ref["U"] @ np.diag(ref["s"]) @ ref["VT"]
+    assert np.linalg.norm(approx - ref_approx) <= 1e-12 * nrm
+    assert np.linalg.norm(U.T @ U - np.eye(k)) <= orth_tol(k)
+    assert np.linalg.norm(VT @ VT.T - np.eye(k)) <= orth_tol(k)
+    e = np.linalg.norm(A - approx) / nrm
+    assert inputs.optimal_truncation_error(sig, k) * (1 - 1e-9) <= e
+
+
+# ---------------------------------------------------------------- full size
+def test_rqrcp_8192_full_size_gaussian():
+    """8192 x 8192 i.i.d. N(0,1), b = 64, p = 8, seed 2 (the benchmark launch):
+    pivots of the first two blocks against the oracle (TRQRCP(128) has the
+    same first 128 pivots), residual and orthogonality of the whole GPU
+    factorization checked on the GPU."""
+    say("rqrcp 8192x8192 gaussian b=64 p=8 seed=2")
+    A, prm = inputs.config_matrix("c2_iid")
+    At = dev(A)
+    F, tau, jpvt, info = binding.rq_rqrcp(At, prm["b"], prm["p"], prm["seed"])
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    ref = oracle.trqrcp(A, 128, prm["b"], prm["p"], seed=prm["seed"])
+    jp = host(jpvt)
+    t = trusted_prefix(ref["gaps"], 128)
+    assert np.array_equal(jp[:t], ref["jpvt"][:t])
+    assert sorted(jp.tolist()) == list(range(8192))
+    Q = torch.linalg.householder_product(F, tau)
+    R = torch.triu(F)
+    Ap = At[:, jpvt]
+    res = (torch.linalg.norm(Ap - Q @ R) / torch.linalg.norm(At)).item()
+    orth = torch.linalg.norm(Q.T @ Q - torch.eye(8192, dtype=torch.float64, device="cuda")).item()
+    say(f"8192 residual {res:.3e} orthogonality {orth:.3e}")
+    assert res <= 1e-12
+    assert orth <= 1e-12
