@@ -174,6 +174,22 @@ int rq_sample_qrcp(void* stream, int32_t l, int64_t n, int32_t bsteps, double* B
 int rq_small_svd(void* stream, int32_t k, double* X, int64_t ldx, double* U, int64_t ldu, double* sigma, double* V,
                  int64_t ldv, void* work, size_t work_bytes);
 
+/*
+ * Stage timing (host side, for measurement).  Between rq_profile_start() and
+ * rq_profile_stop() every entry point records a pair of HIP events on its
+ * stream around each stage of the method (classes 0..rq_profile_classes()-1,
+ * named by rq_profile_name), together with the stage's algorithmic bytes
+ * and flops.  rq_profile_stop() waits for the recorded events and
+ * accumulates per class; rq_profile_get() then returns the launch count,
+ * total milliseconds, algorithmic bytes and flops of a class.  Not
+ * reentrant across host threads that profile concurrently.
+ */
+int rq_profile_start(void);
+int rq_profile_stop(void);
+int rq_profile_get(int32_t cls, int64_t* count, double* total_ms, double* bytes, double* flops);
+const char* rq_profile_name(int32_t cls);
+int32_t rq_profile_classes(void);
+
 #ifdef __cplusplus
 }
 #endif

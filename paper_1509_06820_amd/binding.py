@@ -43,6 +43,12 @@ _SIGS = {
     "rq_sketch": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_u64, _c_p, _c_i64, _c_p, _c_sz], ctypes.c_int),
     "rq_sample_qrcp": ([_c_p, _c_i32, _c_i64, _c_i32, _c_p, _c_i64, _c_p, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_small_svd": ([_c_p, _c_i32, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_p, _c_i64, _c_p, _c_sz], ctypes.c_int),
+    "rq_profile_start": ([], ctypes.c_int),
+    "rq_profile_stop": ([], ctypes.c_int),
+    "rq_profile_get": ([_c_i32, ctypes.POINTER(_c_i64), ctypes.POINTER(ctypes.c_double),
+                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "rq_profile_name": ([_c_i32], ctypes.c_char_p),
+    "rq_profile_classes": ([], ctypes.c_int32),
 }
 
 _lib = None
@@ -240,6 +246,24 @@ def rq_small_svd(X, work=None, stream=None):
     _check(load().rq_small_svd(_stream(stream), k, _ptr(Xw), _ld(Xw), _ptr(U), k, _ptr(sig), _ptr(V), k, _ptr(work),
                                work.numel()), "rq_small_svd")
     return U, sig, V
+
+
+def rq_profile_start():
+    _check(load().rq_profile_start(), "rq_profile_start")
+
+
+def rq_profile_stop():
+    """Stop stage timing; returns {name: dict(count, ms, bytes, flops)}."""
+    L = load()
+    _check(L.rq_profile_stop(), "rq_profile_stop")
+    out = {}
+    for c in range(L.rq_profile_classes()):
+        cnt, ms, by, fl = _c_i64(0), ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        _check(L.rq_profile_get(c, ctypes.byref(cnt), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl)),
+               "rq_profile_get")
+        if cnt.value:
+            out[L.rq_profile_name(c).decode()] = dict(count=cnt.value, ms=ms.value, bytes=by.value, flops=fl.value)
+    return out
 
 
 # short aliases

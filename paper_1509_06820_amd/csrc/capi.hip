@@ -4,6 +4,7 @@
 // all intermediate state stay on the device (no host synchronisation).
 #include "rqrcp.h"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace rq {
 
@@ -134,7 +135,12 @@ int64_t nblocks(int64_t k, int b) { return (k + b - 1) / b; }
 int panel_and_t(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t i0, int bJ, double* tau, double* Y,
                 int64_t ldy, const BlockBufs& bb, const Common& c, int64_t J) {
   const int64_t mJ = m - i0;
-  RQ_TRY(launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, panel_work(bb, c, J)));
+  const double dm = (double)mJ, db = (double)bJ;
+  {
+    ProfScope ps(PC_PANEL, s, 24.0 * dm * db, 2.0 * dm * db * db - 2.0 / 3.0 * db * db * db);
+    RQ_TRY(launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, panel_work(bb, c, J)));
+  }
+  ProfScope ps(PC_TFACTOR, s, 8.0 * dm * db, dm * db * db);
   RQ_TRY(launch_gemm(s, true, false, bJ, bJ, mJ, 1.0, Y, ldy, Y, ldy, 0.0, bb.G, bJ, bb.splitk, bb.splitk_elems));
   RQ_TRY(launch_larft(s, bJ, bb.G, tau, bb.T));
   return 0;
@@ -146,8 +152,14 @@ int trailing_update(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t n,
   const int64_t mJ = m - i0, Nt = n - i0 - bJ;
   if (Nt <= 0) return 0;
   double* C = A + i0 + (i0 + bJ) * lda;
-  RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y, ldy, C, lda, 0.0, bb.zbuf, bJ, bb.splitk, bb.splitk_elems));
-  RQ_TRY(launch_gemm(s, true, false, bJ, Nt, bJ, 1.0, bb.T, bJ, bb.zbuf, bJ, 0.0, bb.wt, bJ, nullptr, 0));
+  const double dm = (double)mJ, dn = (double)Nt, db = (double)bJ;
+  {
+    ProfScope ps(PC_GEMM_YTA, s, 8.0 * (dm * dn + dm * db + db * dn), 2.0 * db * dn * dm + 2.0 * db * db * dn);
+    RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y, ldy, C, lda, 0.0, bb.zbuf, bJ, bb.splitk,
+                       bb.splitk_elems));
+    RQ_TRY(launch_gemm(s, true, false, bJ, Nt, bJ, 1.0, bb.T, bJ, bb.zbuf, bJ, 0.0, bb.wt, bJ, nullptr, 0));
+  }
+  ProfScope ps(PC_GEMM_UPDATE, s, 8.0 * (2.0 * dm * dn + dm * db + db * dn), 2.0 * dm * dn * db);
   RQ_TRY(launch_gemm(s, false, false, mJ, Nt, bJ, -1.0, Y, ldy, bb.wt, bJ, 1.0, C, lda, nullptr, 0));
   return 0;
 }
@@ -160,6 +172,8 @@ int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, 
   if (Nt <= 0) return 0;
   const double* R11 = A + i0 + i0 * lda;
   const double* R12 = A + i0 + (i0 + bJ) * lda;
+  const double dn = (double)Nt, db = (double)bJ;
+  ProfScope ps(PC_SAMPLE_UPDATE, s, 8.0 * (3.0 * db * dn + 2.0 * db * db), 2.0 * db * db * dn + db * db * db / 3.0);
   RQ_TRY(launch_w11(s, bJ, bt_blk, n, 1, R11, lda, sb.w11));
   // Bt(bJ:, 0:bJ) -= R12^T W11^T
   RQ_TRY(launch_gemm(s, true, true, Nt, bJ, bJ, -1.0, R12, lda, sb.w11, bJ, 1.0, bt_blk + bJ, n, nullptr, 0));
@@ -169,6 +183,8 @@ int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, 
 // Sketch: Bt (n x l) = A^T Omega^T with Omega l x m (ld ldo).
 int sketch(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, int l, const double* Omega,
            int64_t ldo, double* bt) {
+  const double dm = (double)m, dn = (double)n, dl = (double)l;
+  ProfScope ps(PC_SKETCH, s, 8.0 * (dm * dn + dl * dm + dl * dn), 2.0 * dl * dm * dn);
   return launch_gemm(s, true, true, n, l, m, 1.0, A, lda, Omega, ldo, 0.0, bt, n, nullptr, 0);
 }
 
@@ -203,6 +219,7 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
     const double* Om = Omega;
     int64_t ldom = ldo;
     if (!Om) {
+      ProfScope ps(PC_OMEGA, s, 8.0 * l * m, 0.0);
       RQ_TRY(launch_omega(s, seed, l, m, f.sb.omega, 1, l));
       Om = f.sb.omega;
       ldom = l;
@@ -215,7 +232,11 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
     (void)mJ;
     double* bt_blk = pivoting ? f.sb.bt + i0 : nullptr;
     if (pivoting) {
-      RQ_TRY(launch_sample_qrcp(s, bt_blk, n, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J)));
+      {
+        ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, 4.0 * l * nJ * bJ);
+        RQ_TRY(launch_sample_qrcp(s, bt_blk, n, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J)));
+      }
+      ProfScope ps(PC_SWAP, s, 32.0 * m * bJ, 0.0);
       RQ_TRY(launch_apply_swaps(s, f.sb.piv, bJ, i0, A, lda, m, jpvt));
     }
     RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J));
@@ -258,6 +279,7 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
   const double* Om = Omega;
   int64_t ldom = ldo;
   if (!Om) {
+    ProfScope ps(PC_OMEGA, s, 8.0 * l * m, 0.0);
     RQ_TRY(launch_omega(s, seed, l, m, t.sb.omega, 1, l));
     Om = t.sb.omega;
     ldom = l;
@@ -267,22 +289,36 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
     const int bJ = (int)std::min<int64_t>(b, k - i0);
     const int64_t mJ = m - i0, nJ = n - i0, Nt = n - i0 - bJ;
     double* bt_blk = t.sb.bt + i0;
-    RQ_TRY(launch_sample_qrcp(s, bt_blk, n, l, nJ, bJ, t.sb.piv, t.c.info, (int)i0, sq_work(t.sb, t.c, J)));
-    RQ_TRY(launch_apply_swaps(s, t.sb.piv, bJ, i0, A, lda, m, jpvt));
-    if (i0 > 0) RQ_TRY(launch_apply_swaps(s, t.sb.piv, bJ, i0, t.wt, k, i0, nullptr));
+    {
+      ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, 4.0 * l * nJ * bJ);
+      RQ_TRY(launch_sample_qrcp(s, bt_blk, n, l, nJ, bJ, t.sb.piv, t.c.info, (int)i0, sq_work(t.sb, t.c, J)));
+    }
+    {
+      ProfScope ps(PC_SWAP, s, 32.0 * (m + i0) * bJ, 0.0);
+      RQ_TRY(launch_apply_swaps(s, t.sb.piv, bJ, i0, A, lda, m, jpvt));
+      if (i0 > 0) RQ_TRY(launch_apply_swaps(s, t.sb.piv, bJ, i0, t.wt, k, i0, nullptr));
+    }
     double* panel = A + i0 + i0 * lda;
     double* Y2 = t.yall + i0 + i0 * m;
     // selected columns: A_hat = A(i0:m, sel) - Y(i0:m, 0:i0) W^T(0:i0, sel)
-    if (i0 > 0)
+    if (i0 > 0) {
+      ProfScope ps(PC_TRQ_PRODUCTS, s, 8.0 * (2.0 * mJ * bJ + mJ * i0 + i0 * bJ), 2.0 * mJ * bJ * i0);
       RQ_TRY(launch_gemm(s, false, false, mJ, bJ, i0, -1.0, t.yall + i0, m, t.wt + i0 * k, k, 1.0, panel, lda,
                          nullptr, 0));
+    }
     RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, Y2, m, t.bb, t.c, J));
     if (Nt > 0) {
       double* Atr = A + i0 + (i0 + bJ) * lda;
       double* wt_tr = t.wt + (i0 + bJ) * k;
       // Z = Y2^T A(i0:m, trail) - (Y2^T Y1) W1^T(:, trail)
-      RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y2, m, Atr, lda, 0.0, t.bb.zbuf, bJ, t.bb.splitk,
-                         t.bb.splitk_elems));
+      {
+        ProfScope ps(PC_GEMM_YTA, s, 8.0 * ((double)mJ * Nt + (double)mJ * bJ + (double)bJ * Nt),
+                     2.0 * bJ * (double)Nt * mJ);
+        RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y2, m, Atr, lda, 0.0, t.bb.zbuf, bJ, t.bb.splitk,
+                           t.bb.splitk_elems));
+      }
+      ProfScope ps(PC_TRQ_PRODUCTS, s, 8.0 * ((double)mJ * (bJ + i0) + 2.0 * (i0 + bJ) * Nt + 3.0 * bJ * Nt),
+                   2.0 * bJ * ((double)i0 * mJ + 2.0 * i0 * Nt + (double)bJ * Nt + (double)bJ * Nt));
       if (i0 > 0) {
         RQ_TRY(launch_gemm(s, true, false, bJ, i0, mJ, 1.0, Y2, m, t.yall + i0, m, 0.0, t.gk, bJ, t.bb.splitk,
                            t.bb.splitk_elems));
@@ -401,7 +437,10 @@ int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, i
   carve_tuxv(cv, m, n, k, b, p, t);
   if (!cv.ok) return RQ_ERR_WORKSPACE;
   // TRQRCP on a copy: A itself is needed again for Z1 = A V.
-  RQ_TRY(launch_copy2d(s, m, n, A, lda, t.ac, m));
+  {
+    ProfScope ps(PC_TUXV_PRODUCTS, s, 16.0 * m * n, 0.0);
+    RQ_TRY(launch_copy2d(s, m, n, A, lda, t.ac, m));
+  }
   RQ_TRY(trqrcp_core(s, m, n, k, t.ac, m, b, p, seed, Omega, ldo, t.jp, t.tk, t.trq));
   // Z0 = R P^T, stored transposed (n x k)
   RQ_TRY(launch_scatter_rt(s, k, n, t.ac, m, t.jp, t.z0t, n));
@@ -409,7 +448,10 @@ int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, i
   RQ_TRY(qr_explicit(s, n, k, t.z0t, n, b, t.tz, t.qz));
   RQ_TRY(form_q(s, n, k, b, t.qz, t.v, n));
   // Z1 = A V (m x k)
-  RQ_TRY(launch_gemm(s, false, false, m, k, n, 1.0, A, lda, t.v, n, 0.0, t.z1, m, nullptr, 0));
+  {
+    ProfScope ps(PC_TUXV_PRODUCTS, s, 8.0 * ((double)m * n + (double)n * k + (double)m * k), 2.0 * m * (double)n * k);
+    RQ_TRY(launch_gemm(s, false, false, m, k, n, 1.0, A, lda, t.v, n, 0.0, t.z1, m, nullptr, 0));
+  }
   // QR of Z1 -> U1, X
   RQ_TRY(qr_explicit(s, m, k, t.z1, m, b, t.tu, t.qu));
   RQ_TRY(launch_triu_copy(s, k, t.z1, m, t.x, k));
@@ -417,7 +459,10 @@ int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, i
   // X = Ux diag(sigma) Vx^T
   SvdWork sw;
   sw.colnorm = nullptr; sw.order = nullptr; sw.flags = nullptr; sw.err = t.trq.c.err; sw.tmp = t.svdtmp;
-  RQ_TRY(launch_jacobi_svd(s, (int)k, t.x, k, t.ux, k, sigma, t.vx, k, sw));
+  {
+    ProfScope ps(PC_SVD, s, 8.0 * 4 * k * k, 0.0);
+    RQ_TRY(launch_jacobi_svd(s, (int)k, t.x, k, t.ux, k, sigma, t.vx, k, sw));
+  }
   // U = U1 Ux ; VT = Vx^T V^T
   RQ_TRY(launch_gemm(s, false, false, m, k, k, 1.0, t.u1, m, t.ux, k, 0.0, U, ldu, nullptr, 0));
   RQ_TRY(launch_gemm(s, true, true, k, n, k, 1.0, t.vx, k, t.v, n, 0.0, VT, ldvt, nullptr, 0));

@@ -45,14 +45,17 @@ __device__ __forceinline__ void wave_argmax(double& v, long& p) {
 
 // ---------------------------------------------------------------- cross-WG exchange
 // Workgroups of one cooperative launch exchange data through global memory.
-// A publisher writes its payload, then every thread issues an agent-scope
-// release fence, the workgroup synchronises and thread 0 stores the epoch
-// into its flag.  A consumer polls the flags of the workgroups it waits for
-// (one lane per flag) with agent-scope atomic loads, then issues an
-// agent-scope acquire fence.  The fence pair orders the payload writes before
-// the payload reads (HIP/HSA scoped memory model).  Waits are bounded: after
-// `spin_limit` polls the wait fails, the error word is set and the caller
-// returns, so a broken exchange ends the kernel instead of hanging it.
+// A publisher writes its payload; every wave waits until its stores are
+// acknowledged, the workgroup synchronises, and wave 0 issues one
+// agent-scope release fence (write-back of the L2 for the other XCDs) before
+// thread 0 stores the epoch into its flag.  A consumer's wave 0 polls the
+// flags (one lane per flag) with agent-scope atomic loads and issues one
+// agent-scope acquire fence (invalidation of this CU's L1 and of stale L2
+// lines) before the workgroup synchronises, so every wave then reads the
+// payload from memory.  Only one wave per workgroup pays for the cache
+// maintenance.  Waits are bounded: after SPIN_LIMIT polls the wait fails, the
+// error word is set and the caller returns, so a broken exchange ends the
+// kernel instead of hanging it.
 constexpr long SPIN_LIMIT = 1L << 20;
 
 // A cooperative kernel starts by checking the error word: once one stage has
@@ -67,9 +70,14 @@ __device__ __forceinline__ bool earlier_failure(const int* err) {
 }
 
 __device__ __forceinline__ void publish_flag(unsigned* flags, int me, unsigned epoch) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  // every wave waits for its own stores to be acknowledged ...
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(&flags[me], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // ... then one wave writes the cache back device-wide and raises the flag
+  if (threadIdx.x < WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) __hip_atomic_store(&flags[me], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Wait until flags[q] >= epoch for q in [0, P).  Returns false on timeout.
@@ -97,8 +105,9 @@ __device__ __forceinline__ bool wait_flags(const unsigned* flags, int P, unsigne
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
+  // the acquire above invalidated this CU's caches; the barrier orders the
+  // other waves' reads after it
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return s_bad == 0;
 }
 
@@ -118,7 +127,6 @@ __device__ __forceinline__ bool wait_one(const unsigned* flag, unsigned epoch, i
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   if (seen) *seen = s_seen;
   return s_bad == 0;
 }

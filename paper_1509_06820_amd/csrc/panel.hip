@@ -3,7 +3,7 @@
 // diagonal, reflector tails below it, tau per column; the explicit unit-lower
 // reflector block Y is written as well for the block-reflector products.
 //
-// One cooperative launch.  Workgroup q owns rows [512 q, 512 q + 512) of the
+// One cooperative launch.  Workgroup q owns rows [256 q, 256 q + 256) of the
 // panel in registers (thread = one column x 32 rows).  For column j every
 // workgroup forms its partial inner products of column j with columns j..bJ-1
 // over its rows below j, publishes them (plus row j if it owns it), and after
@@ -15,10 +15,10 @@ namespace rq {
 
 namespace {
 
-constexpr int PN_THREADS = 1024;
+constexpr int PN_THREADS = 512;
 constexpr int PN_RPT = 32;
 constexpr int PN_GROUPS = PN_THREADS / 64;
-constexpr int PN_RB = PN_GROUPS * PN_RPT;  // 512 rows per workgroup
+constexpr int PN_RB = PN_GROUPS * PN_RPT;  // 256 rows per workgroup
 
 struct PanelParams {
   double* P;
@@ -86,11 +86,19 @@ __global__ void __launch_bounds__(PN_THREADS) panel_kernel(PanelParams a) {
     }
     publish_flag(a.flags, me, (unsigned)(j + 1));
     if (!wait_flags(a.flags, a.NP, (unsigned)(j + 1), a.err)) return;
+    // all partials are loaded at once (row group g reads workgroups g, g+16, ...)
+    {
+      double d = 0.0;
+      for (int q = g; q < a.NP; q += PN_GROUPS) d += a.slots[((int64_t)j * a.NP + q) * 64 + c];
+      part[g][c] = d;
+      if (tid < 64) rowv[tid] = a.rowslot[(int64_t)j * 64 + tid];
+    }
+    __syncthreads();
     if (tid < 64) {
       double d = 0.0;
-      for (int q = 0; q < a.NP; ++q) d += a.slots[((int64_t)j * a.NP + q) * 64 + tid];
+#pragma unroll
+      for (int q = 0; q < PN_GROUPS; ++q) d += part[q][tid];
       dsum[tid] = d;
-      rowv[tid] = a.rowslot[(int64_t)j * 64 + tid];
     }
     __syncthreads();
     if (tid == 0) {

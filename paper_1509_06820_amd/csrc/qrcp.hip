@@ -60,6 +60,8 @@ __device__ __forceinline__ void apply_reflector(double (&col)[LMAX], const doubl
 #pragma unroll
   for (int r = 0; r < LMAX; ++r) dot += v[r] * col[r];
   dot *= tau;
+  // re-read v from LDS below instead of keeping LMAX values live in registers
+  asm volatile("" ::: "memory");
 #pragma unroll
   for (int r = 0; r < LMAX; ++r) col[r] -= dot * v[r];
 }
