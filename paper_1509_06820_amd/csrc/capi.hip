@@ -101,10 +101,12 @@ struct BlockBufs {
   double* wt;         // b x n
   double* splitk;
   size_t splitk_elems;
+  double* cq;         // CholeskyQR scratch
 };
 
 void carve_block(Carve& cv, int64_t m, int64_t n, int b, BlockBufs& bb) {
   bb.panel_slots = cv.take<double>(panel_slot_elems(m, b));
+  bb.cq = cv.take<double>(cholqr_scratch_elems(m, b));
   bb.G = cv.take<double>((size_t)b * b);
   bb.T = cv.take<double>((size_t)b * b);
   bb.zbuf = cv.take<double>((size_t)b * std::max<int64_t>(n, 1));
@@ -113,11 +115,16 @@ void carve_block(Carve& cv, int64_t m, int64_t n, int b, BlockBufs& bb) {
   bb.splitk = cv.take<double>(bb.splitk_elems);
 }
 
+// Words of a block's flag region: [0, 128) sample QRCP, [128, 384) panel
+// fallback, 448 panel status (nonzero: CholeskyQR failed, fallback runs).
+constexpr int FLAG_PANEL_STATUS = 448;
+
 PanelWork panel_work(const BlockBufs& bb, const Common& c, int64_t J) {
   PanelWork w;
   w.slots = bb.panel_slots;
   w.flags = c.flags + (size_t)J * FLAG_STRIDE + 128;
   w.err = c.err;
+  w.gate = (const int*)(c.flags + (size_t)J * FLAG_STRIDE + FLAG_PANEL_STATUS);
   return w;
 }
 
@@ -131,18 +138,21 @@ SampleQrcpWork sq_work(const SampleBufs& sb, const Common& c, int64_t J) {
 int64_t nblocks(int64_t k, int b) { return (k + b - 1) / b; }
 
 // ------------------------------------------------------------------ pieces
-// Panel QR of A(i0:m, i0:i0+bJ) + connection matrix T of its reflectors.
+// Panel QR of A(i0:m, i0:i0+bJ) + connection matrix T of its reflectors:
+// CholeskyQR2 + Householder reconstruction (preconditioned by the sample's
+// S11 when given), with the column-by-column Householder panel as fallback.
 int panel_and_t(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t i0, int bJ, double* tau, double* Y,
-                int64_t ldy, const BlockBufs& bb, const Common& c, int64_t J) {
+                int64_t ldy, const BlockBufs& bb, const Common& c, int64_t J, const double* S11 = nullptr,
+                int64_t srs = 0, int64_t scs = 0) {
   const int64_t mJ = m - i0;
   const double dm = (double)mJ, db = (double)bJ;
-  {
-    ProfScope ps(PC_PANEL, s, 24.0 * dm * db, 2.0 * dm * db * db - 2.0 / 3.0 * db * db * db);
-    RQ_TRY(launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, panel_work(bb, c, J)));
-  }
-  ProfScope ps(PC_TFACTOR, s, 8.0 * dm * db, dm * db * db);
-  RQ_TRY(launch_gemm(s, true, false, bJ, bJ, mJ, 1.0, Y, ldy, Y, ldy, 0.0, bb.G, bJ, bb.splitk, bb.splitk_elems));
-  RQ_TRY(launch_larft(s, bJ, bb.G, tau, bb.T));
+  PanelWork pw = panel_work(bb, c, J);
+  int* st = (int*)pw.gate;
+  ProfScope ps(PC_PANEL, s, 32.0 * dm * db, 6.0 * dm * db * db);
+  RQ_TRY(launch_panel_cholqr(s, A + i0 + i0 * lda, lda, mJ, bJ, S11, srs, scs, tau, Y, ldy, bb.T, bb.cq, bb.splitk,
+                             bb.splitk_elems, st));
+  RQ_TRY(launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, pw));
+  RQ_TRY(launch_larft_gated(s, mJ, bJ, Y, ldy, tau, bb.T, st));
   return 0;
 }
 
@@ -239,7 +249,7 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
       ProfScope ps(PC_SWAP, s, 32.0 * m * bJ, 0.0);
       RQ_TRY(launch_apply_swaps(s, f.sb.piv, bJ, i0, A, lda, m, jpvt));
     }
-    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J));
+    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J, bt_blk, n, 1));
     RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
     if (pivoting && i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, bt_blk, f.sb));
     i0 += bJ;
@@ -306,7 +316,7 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
       RQ_TRY(launch_gemm(s, false, false, mJ, bJ, i0, -1.0, t.yall + i0, m, t.wt + i0 * k, k, 1.0, panel, lda,
                          nullptr, 0));
     }
-    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, Y2, m, t.bb, t.c, J));
+    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, Y2, m, t.bb, t.c, J, bt_blk, n, 1));
     if (Nt > 0) {
       double* Atr = A + i0 + (i0 + bJ) * lda;
       double* wt_tr = t.wt + (i0 + bJ) * k;

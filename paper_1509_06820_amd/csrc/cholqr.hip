@@ -1,0 +1,416 @@
+// Householder panel by CholeskyQR2 and Householder reconstruction.
+//
+// The paper's panel step is "[Q, R11] = qr(A P(:, 1:b))" (Alg. 4, Alg. 6) and
+// its later steps need the Householder form (reflectors Y, tau, connection
+// matrix T).  Instead of b sequential column steps, the mJ x b panel P is
+// orthogonalised with two Cholesky QR passes and the Householder vectors
+// are then recovered from the orthonormal factor (Ballard, Demmel, Grigori,
+// Jacobsen, Knight, Nguyen, "Reconstructing Householder vectors from Tall-
+// Skinny QR", IPDPS 2014): with E = [I; 0], the LU factorisation without
+// pivoting E - Q S = Y U (S diagonal, S_ii = -sign of the current pivot of
+// the elimination) gives the unit lower trapezoidal Y, T = U Y1^-T and
+// tau = diag(U); R = S R_chol.  In exact arithmetic these are the reflectors
+// and R of Householder QR with the LAPACK sign convention.
+//
+// In RQRCP the sample supplies a preconditioner: the sample QRCP's leading
+// block S11 satisfies S11 = W11 R11 (sample update, Sec. 4), so
+// X = P S11^-1 = Q W11^-1 is well conditioned and the first Cholesky pass
+// runs on X.  Q and R are formed from the first pass's output Q1 (never from
+// P times an inverse of S11), so a badly conditioned S11 can make the passes
+// fail but cannot make their result inaccurate.
+//
+// Stages (all on the caller's stream; a device status word `st` records a
+// failure, after which the reconstruction is skipped and the column-by-column
+// Householder panel runs instead):
+//   inv   : M0 = S11^-1                         (1 workgroup)
+//   gemm  : X = P M0 (into Y), G1 = X^T X       (matrix cores, split-K)
+//   chol1 : M1 = chol(G1)^-1                    (1 workgroup)
+//   gemm  : Q1 = X M1, G2 = Q1^T Q1, H = Q1^T P
+//   recon : R2 = chol(G2), Q_top = Q1(0:b, :) R2^-1, LU with sign choice,
+//           T, tau, R = S R2^-T H, Y1, M3 = -R2^-1 S U^-1   (1 workgroup)
+//   gemm  : Y(b:, :) = Q1(b:, :) M3
+//   copy  : Y(b:, :) back into the panel storage (skipped on failure)
+#include "kernels.hpp"
+
+namespace rq {
+
+namespace {
+
+constexpr int SM_T = 1024;   // threads of the small-matrix kernels
+constexpr int SM_N = 64;     // matrices are padded to 64 x 64
+constexpr int SM_LD = 65;    // LDS leading dimension (odd: no bank conflicts along columns)
+
+// status bits
+constexpr int ST_CHOL1 = 1, ST_CHOL2 = 2, ST_ORTH = 4, ST_PIVOT = 8, ST_S11 = 16;
+
+// ---------------------------------------------------------------- LDS helpers
+// Matrices live in LDS as M[i + j * SM_LD] (column-major), 64 x 64, padded
+// with the identity beyond the active size b.
+
+__device__ void sm_load(double* M, const double* G, int64_t rs, int64_t cs, int b, bool upper_only) {
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+    const int i = e % SM_N, j = e / SM_N;
+    double v;
+    if (i < b && j < b) v = (upper_only && i > j) ? 0.0 : G[(int64_t)i * rs + (int64_t)j * cs];
+    else v = (i == j) ? 1.0 : 0.0;
+    M[i + j * SM_LD] = v;
+  }
+}
+
+__device__ void sm_store(const double* M, double* G, int64_t ld, int b) {
+  for (int e = threadIdx.x; e < b * b; e += SM_T) {
+    const int i = e % b, j = e / b;
+    G[i + (int64_t)j * ld] = M[i + j * SM_LD];
+  }
+}
+
+// In-place Cholesky G = R^T R (R upper).  Returns false (uniformly) if a
+// pivot is not positive.
+__device__ bool sm_chol(double* G, int* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  for (int k = 0; k < SM_N; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = G[k + k * SM_LD];
+      if (!(d > 0.0)) *flag = 1;
+      G[k + k * SM_LD] = (d > 0.0) ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    const double r = G[k + k * SM_LD];
+    for (int j = k + 1 + threadIdx.x; j < SM_N; j += SM_T) G[k + j * SM_LD] /= r;
+    __syncthreads();
+    // trailing update of the upper triangle: G(i, j) -= R(k, i) R(k, j), k < i <= j
+    const int m = SM_N - k - 1;
+    for (int e = threadIdx.x; e < m * m; e += SM_T) {
+      const int i = k + 1 + e % m, j = k + 1 + e / m;
+      if (i <= j) G[i + j * SM_LD] -= G[k + i * SM_LD] * G[k + j * SM_LD];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+    const int i = e % SM_N, j = e / SM_N;
+    if (i > j) G[i + j * SM_LD] = 0.0;
+  }
+  __syncthreads();
+  return *flag == 0;
+}
+
+// Inverse of an upper-triangular matrix by recursive doubling:
+// inv([A B; 0 C]) = [inv(A), -inv(A) B inv(C); 0, inv(C)], block size 1, 2, ..., 32.
+// R and Ri must differ; W is scratch (SM_N * SM_LD).  Returns false if a
+// diagonal entry is zero.
+__device__ bool sm_tri_inv(const double* R, double* Ri, double* W, int* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+    const int i = e % SM_N, j = e / SM_N;
+    double v = 0.0;
+    if (i == j) {
+      const double d = R[i + i * SM_LD];
+      if (d == 0.0) *flag = 1;
+      v = (d != 0.0) ? 1.0 / d : 0.0;
+    }
+    Ri[i + j * SM_LD] = v;
+  }
+  __syncthreads();
+  for (int s = 1; s < SM_N; s <<= 1) {
+    // W = B inv(C) for every pair of diagonal blocks of size s
+    const int npair = SM_N / (2 * s);
+    for (int e = threadIdx.x; e < npair * s * s; e += SM_T) {
+      const int q = e / (s * s), r = e % (s * s);
+      const int i = r % s, j = r / s;
+      const int i0 = 2 * s * q, c0 = i0 + s;
+      double acc = 0.0;
+      for (int k = 0; k <= j; ++k) acc += R[(i0 + i) + (c0 + k) * SM_LD] * Ri[(c0 + k) + (c0 + j) * SM_LD];
+      W[(i0 + i) + (c0 + j) * SM_LD] = acc;
+    }
+    __syncthreads();
+    // off-diagonal block of the inverse: -inv(A) W
+    for (int e = threadIdx.x; e < npair * s * s; e += SM_T) {
+      const int q = e / (s * s), r = e % (s * s);
+      const int i = r % s, j = r / s;
+      const int i0 = 2 * s * q, c0 = i0 + s;
+      double acc = 0.0;
+      for (int k = i; k < s; ++k) acc += Ri[(i0 + i) + (i0 + k) * SM_LD] * W[(i0 + k) + (c0 + j) * SM_LD];
+      Ri[(i0 + i) + (c0 + j) * SM_LD] = -acc;
+    }
+    __syncthreads();
+  }
+  return *flag == 0;
+}
+
+// C = A B for upper-triangular A, B (C upper).
+__device__ void sm_mul_uu(const double* A, const double* B, double* C) {
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+    const int i = e % SM_N, j = e / SM_N;
+    double acc = 0.0;
+    if (i <= j)
+      for (int k = i; k <= j; ++k) acc += A[i + k * SM_LD] * B[k + j * SM_LD];
+    C[i + j * SM_LD] = acc;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- kernels
+// M0 = S11^-1 (S11 = S[i*srs + j*scs], upper b x b).  A zero diagonal marks
+// the status word and leaves the preconditioner unused.
+__global__ void __launch_bounds__(SM_T) inv_kernel(int b, const double* S, int64_t srs, int64_t scs, double* M0,
+                                                   int* st) {
+  extern __shared__ double sm[];
+  __shared__ int flag;
+  double* A = sm;
+  double* Ai = sm + SM_N * SM_LD;
+  double* W = sm + 2 * SM_N * SM_LD;
+  sm_load(A, S, srs, scs, b, true);
+  __syncthreads();
+  const bool ok = sm_tri_inv(A, Ai, W, &flag);
+  if (!ok) {
+    if (threadIdx.x == 0) atomicOr(st, ST_S11);
+    return;
+  }
+  sm_store(Ai, M0, b, b);
+}
+
+// M1 = chol(G1)^-1.
+__global__ void __launch_bounds__(SM_T) chol1_kernel(int b, const double* G1, double* M1, int* st) {
+  extern __shared__ double sm[];
+  __shared__ int flag;
+  __shared__ int s_skip;
+  if (threadIdx.x == 0) s_skip = *st;
+  __syncthreads();
+  if (s_skip) return;
+  double* G = sm;
+  double* Ri = sm + SM_N * SM_LD;
+  double* W = sm + 2 * SM_N * SM_LD;
+  sm_load(G, G1, 1, b, b, true);
+  __syncthreads();
+  if (!sm_chol(G, &flag) || !sm_tri_inv(G, Ri, W, &flag)) {
+    if (threadIdx.x == 0) atomicOr(st, ST_CHOL1);
+    return;
+  }
+  sm_store(Ri, M1, b, b);
+}
+
+// Second Cholesky pass, sign-choosing LU of E - Q S on the top block, and
+// the Householder quantities.  Q1 (ld ldq) is the first pass's output,
+// G2 = Q1^T Q1 and H = Q1^T P; with R2 = chol(G2) the orthonormal factor is
+// Q = Q1 R2^-1 and R = S Q^T P = S R2^-T H.  Forming Q and R from Q1 rather
+// than from P keeps the preconditioner's conditioning out of both.
+__global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const double* G2, const double* H,
+                                                     const double* Q1, int64_t ldq, double* P, int64_t ldp, double* Y,
+                                                     int64_t ldy, double* tau, double* T, double* M3, int* st) {
+  extern __shared__ double sm[];
+  __shared__ int flag;
+  __shared__ int s_skip;
+  __shared__ double sgn[SM_N];
+  if (threadIdx.x == 0) s_skip = *st;
+  __syncthreads();
+  if (s_skip) return;
+  double* A = sm;
+  double* B = sm + SM_N * SM_LD;
+  double* C = sm + 2 * SM_N * SM_LD;
+  double* D = sm + 3 * SM_N * SM_LD;
+  // R2 = chol(G2); G2 must be close to the identity after the first pass
+  sm_load(A, G2, 1, b, b, false);
+  __syncthreads();
+  if (threadIdx.x == 0) flag = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < b * b; e += SM_T) {
+    const int i = e % b, j = e / b;
+    if (!(fabs(A[i + j * SM_LD] - (i == j ? 1.0 : 0.0)) <= 0.25)) flag = 1;
+  }
+  __syncthreads();
+  if (flag) {
+    if (threadIdx.x == 0) atomicOr(st, ST_ORTH);
+    return;
+  }
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {  // keep the upper triangle
+    const int i = e % SM_N, j = e / SM_N;
+    if (i > j) A[i + j * SM_LD] = 0.0;
+  }
+  __syncthreads();
+  if (!sm_chol(A, &flag)) {
+    if (threadIdx.x == 0) atomicOr(st, ST_CHOL2);
+    return;
+  }
+  // B = R2^-1 (C scratch)
+  if (!sm_tri_inv(A, B, C, &flag)) {
+    if (threadIdx.x == 0) atomicOr(st, ST_CHOL2);
+    return;
+  }
+  // A = Q_top = Q1(0:b, 0:b) R2^-1 (full b x b)
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+    const int i = e % SM_N, j = e / SM_N;
+    double acc = 0.0;
+    if (i < b && j < b)
+      for (int k = 0; k <= j; ++k) acc += Q1[i + (int64_t)k * ldq] * B[k + j * SM_LD];
+    A[i + j * SM_LD] = acc;
+  }
+  // D = H (full b x b)
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+    const int i = e % SM_N, j = e / SM_N;
+    D[i + j * SM_LD] = (i < b && j < b) ? H[i + (int64_t)j * b] : 0.0;
+  }
+  __syncthreads();
+  // LU of E - Q S by right-looking elimination on Q alone: at step i the
+  // pivot column c = Q'(i:, i); S_ii = -sign(c_0) (sign(0) = +1); pivot
+  // p_i = 1 + |c_0|; L(r, i) = -S_ii Q'(r, i) / p_i; Q'(r, j) -= L(r, i) Q'(i, j).
+  // A column with no row below its diagonal (the last one of a square panel)
+  // is left alone by Householder QR (tau = 0): there S_ii = sign(c_0) and the
+  // pivot is 0.
+  for (int i = 0; i < b; ++i) {
+    if (threadIdx.x == 0) {
+      const double c0 = A[i + i * SM_LD];
+      if (i == mJ - 1) {
+        sgn[i] = (c0 >= 0.0) ? 1.0 : -1.0;
+        A[i + i * SM_LD] = 0.0;
+      } else {
+        sgn[i] = (c0 >= 0.0) ? -1.0 : 1.0;
+        A[i + i * SM_LD] = 1.0 + fabs(c0);  // pivot (= U(i, i))
+      }
+    }
+    __syncthreads();
+    const double s = sgn[i], piv = A[i + i * SM_LD];
+    if (i == mJ - 1) break;  // last step, nothing below
+    for (int r = i + 1 + threadIdx.x; r < b; r += SM_T) A[r + i * SM_LD] = -s * A[r + i * SM_LD] / piv;
+    __syncthreads();
+    const int m = b - i - 1;
+    for (int e = threadIdx.x; e < m * m; e += SM_T) {
+      const int r = i + 1 + e % m, j = i + 1 + e / m;
+      A[r + j * SM_LD] -= A[r + i * SM_LD] * A[i + j * SM_LD];
+    }
+    __syncthreads();
+  }
+  // C = U (U(i, j) = -S_jj Q'(i, j) above the diagonal, pivots on it);
+  // A keeps L1 below the diagonal.  Padding stays identity.
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+    const int i = e % SM_N, j = e / SM_N;
+    double u;
+    if (i < b && j < b) u = (i < j) ? -sgn[j] * A[i + j * SM_LD] : (i == j ? A[i + i * SM_LD] : 0.0);
+    else u = (i == j) ? 1.0 : 0.0;
+    C[i + j * SM_LD] = u;
+  }
+  // outputs of the top block: R(i, j) = S_ii sum_k R2^-1(k, i) H(k, j) on and
+  // above the diagonal, Y1 below it
+  for (int e = threadIdx.x; e < b * b; e += SM_T) {
+    const int i = e % b, j = e / b;
+    if (i <= j) {
+      double acc = 0.0;
+      for (int k = 0; k <= i; ++k) acc += B[k + i * SM_LD] * D[k + j * SM_LD];
+      P[i + (int64_t)j * ldp] = sgn[i] * acc;
+      Y[i + (int64_t)j * ldy] = (i == j) ? 1.0 : 0.0;
+    } else {
+      const double y = A[i + j * SM_LD];
+      P[i + (int64_t)j * ldp] = y;
+      Y[i + (int64_t)j * ldy] = y;
+    }
+  }
+  __syncthreads();
+  // B = -R2^-1 S (columns scaled), kept in the global M3 scratch meanwhile
+  for (int e = threadIdx.x; e < b * b; e += SM_T) {
+    const int i = e % b, j = e / b;
+    M3[i + (int64_t)j * b] = (i <= j) ? -sgn[j] * B[i + j * SM_LD] : 0.0;
+  }
+  for (int i = threadIdx.x; i < b; i += SM_T) tau[i] = C[i + i * SM_LD];
+  // D = Y1^T (unit upper) padded
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+    const int i = e % SM_N, j = e / SM_N;
+    double v;
+    if (i < b && j < b) v = (i < j) ? A[j + i * SM_LD] : (i == j ? 1.0 : 0.0);
+    else v = (i == j) ? 1.0 : 0.0;
+    D[i + j * SM_LD] = v;
+  }
+  __syncthreads();
+  sm_tri_inv(D, A, B, &flag);   // A = inv(Y1^T) (unit diagonal: never singular)
+  // T = U inv(Y1^T)
+  sm_mul_uu(C, A, D);
+  sm_store(D, T, b, b);
+  if (mJ == b) return;  // no rows below the top block
+  // M3 = -R2^-1 S inv(U): A = inv(U) (D scratch), B = -R2^-1 S
+  if (!sm_tri_inv(C, A, D, &flag)) {  // pivots are >= 1 here: cannot happen
+    if (threadIdx.x == 0) atomicOr(st, ST_PIVOT);
+    return;
+  }
+  sm_load(B, M3, 1, b, b, true);
+  __syncthreads();
+  sm_mul_uu(B, A, D);
+  sm_store(D, M3, b, b);
+}
+
+// Copy Y(b:mJ, :) into the panel storage below the top block, unless the
+// reconstruction failed.
+__global__ void __launch_bounds__(256) ycopy_kernel(int64_t mJ, int b, const double* Y, int64_t ldy, double* P,
+                                                    int64_t ldp, const int* st) {
+  if (*st) return;
+  const int64_t rows = mJ - b;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * b) return;
+  const int64_t j = idx / rows, i = b + (idx - j * rows);
+  P[i + j * ldp] = Y[i + j * ldy];
+}
+
+constexpr size_t SM_LDS = 4 * SM_N * SM_LD * sizeof(double);
+
+int set_lds(const void* fn) {
+  RQ_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)SM_LDS));
+  return 0;
+}
+
+}  // namespace
+
+size_t cholqr_scratch_elems(int64_t mmax, int bmax) {
+  // Q1 (mmax x b), G1, G2, H, M0, M1, M3 (b x b each)
+  return (size_t)mmax * bmax + 6 * (size_t)bmax * bmax;
+}
+
+// Panel (mJ x bJ, ld ldp) -> in-place Householder layout, tau, explicit Y
+// (ld ldy) and T (bJ x bJ).  S11 (optional): the sample's leading block,
+// element (i, j) at S11[i*srs + j*scs].  `st` is a device status word the
+// caller zeroes; nonzero on return means the fallback must run.  Y doubles
+// as the first pass's X = P S11^-1.
+int launch_panel_cholqr(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, const double* S11, int64_t srs,
+                        int64_t scs, double* tau, double* Y, int64_t ldy, double* T, double* scratch,
+                        double* splitk, size_t splitk_elems, int* st) {
+  static bool init = false;
+  if (!init) {
+    RQ_TRY_RAW(set_lds((const void*)inv_kernel));
+    RQ_TRY_RAW(set_lds((const void*)chol1_kernel));
+    RQ_TRY_RAW(set_lds((const void*)recon_kernel));
+    init = true;
+  }
+  const int b = bJ;
+  double* Q1 = scratch;
+  double* G1 = Q1 + mJ * (int64_t)b;
+  double* G2 = G1 + b * b;
+  double* H = G2 + b * b;
+  double* M0 = H + b * b;
+  double* M1 = M0 + b * b;
+  double* M3 = M1 + b * b;
+  const double* X = P;
+  int64_t ldx = ldp;
+  if (S11) {
+    hipLaunchKernelGGL(inv_kernel, dim3(1), dim3(SM_T), SM_LDS, s, b, S11, srs, scs, M0, st);
+    RQ_HIP(hipGetLastError());
+    RQ_TRY_RAW(launch_gemm(s, false, false, mJ, b, b, 1.0, P, ldp, M0, b, 0.0, Y, ldy, nullptr, 0));
+    X = Y;
+    ldx = ldy;
+  }
+  RQ_TRY_RAW(launch_gemm(s, true, false, b, b, mJ, 1.0, X, ldx, X, ldx, 0.0, G1, b, splitk, splitk_elems));
+  hipLaunchKernelGGL(chol1_kernel, dim3(1), dim3(SM_T), SM_LDS, s, b, G1, M1, st);
+  RQ_HIP(hipGetLastError());
+  RQ_TRY_RAW(launch_gemm(s, false, false, mJ, b, b, 1.0, X, ldx, M1, b, 0.0, Q1, mJ, nullptr, 0));
+  RQ_TRY_RAW(launch_gemm(s, true, false, b, b, mJ, 1.0, Q1, mJ, Q1, mJ, 0.0, G2, b, splitk, splitk_elems));
+  RQ_TRY_RAW(launch_gemm(s, true, false, b, b, mJ, 1.0, Q1, mJ, P, ldp, 0.0, H, b, splitk, splitk_elems));
+  hipLaunchKernelGGL(recon_kernel, dim3(1), dim3(SM_T), SM_LDS, s, b, mJ, G2, H, Q1, mJ, P, ldp, Y, ldy, tau, T, M3,
+                     st);
+  RQ_HIP(hipGetLastError());
+  if (mJ > b) {
+    RQ_TRY_RAW(launch_gemm(s, false, false, mJ - b, b, b, 1.0, Q1 + b, mJ, M3, b, 0.0, Y + b, ldy, nullptr, 0));
+    const int64_t tot = (mJ - b) * b;
+    hipLaunchKernelGGL(ycopy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, mJ, b, Y, ldy, P, ldp, st);
+    RQ_HIP(hipGetLastError());
+  }
+  return 0;
+}
+
+}  // namespace rq

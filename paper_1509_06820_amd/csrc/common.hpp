@@ -21,6 +21,12 @@ constexpr int RQ_ERR_COOP = 2001;       // cooperative launch rejected (grid doe
     if (_e != hipSuccess) return ::rq::RQ_ERR_HIP_BASE + (int)_e;      \
   } while (0)
 
+#define RQ_TRY_RAW(x)        \
+  do {                       \
+    int _rc = (x);           \
+    if (_rc) return _rc;     \
+  } while (0)
+
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -36,11 +36,13 @@ int launch_sample_qrcp(hipStream_t s, double* Bt, int64_t ldbt, int l, int64_t n
 int launch_apply_swaps(hipStream_t s, const int* piv, int bJ, int64_t offset, double* M, int64_t ldm, int64_t rows,
                        int64_t* jpvt);
 
-// Householder panel QR (in-place layout), tau, explicit unit-lower Y.
+// Householder panel QR (in-place layout), tau, explicit unit-lower Y, one
+// column at a time.  With `gate` set, the kernel runs only if *gate != 0.
 struct PanelWork {
   double* slots;       // bmax * 256 * 64 + bmax * 64 doubles
   unsigned* flags;     // 256 words (zeroed by the caller)
   int* err;
+  const int* gate;
 };
 size_t panel_slot_elems(int64_t mmax, int bmax);
 int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, double* tau, double* Y, int64_t ldy,
@@ -48,6 +50,15 @@ int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, doub
 
 // T (bJ x bJ, ld bJ) from G = Y^T Y (ld bJ) and tau (forward columnwise recurrence).
 int launch_larft(hipStream_t s, int bJ, const double* G, const double* tau, double* T);
+// Same, forming G = Y^T Y itself; runs only if *gate != 0 (fallback path).
+int launch_larft_gated(hipStream_t s, int64_t mJ, int bJ, const double* Y, int64_t ldy, const double* tau, double* T,
+                       const int* gate);
+
+// Panel by CholeskyQR2 + Householder reconstruction (see cholqr.hip).
+size_t cholqr_scratch_elems(int64_t mmax, int bmax);
+int launch_panel_cholqr(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, const double* S11, int64_t srs,
+                        int64_t scs, double* tau, double* Y, int64_t ldy, double* T, double* scratch,
+                        double* splitk, size_t splitk_elems, int* st);
 
 // W11 = S11 R11^{-1} (upper triangular, ld bJ); zero-diagonal columns of R11 give 0.
 // S11(i, j) = S[i*srs + j*scs].

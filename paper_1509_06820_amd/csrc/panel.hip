@@ -32,6 +32,7 @@ struct PanelParams {
   double* rowslot;  // bJ * 64 values of row j
   unsigned* flags;
   int* err;
+  const int* gate;
   int NP;
 };
 
@@ -49,6 +50,12 @@ __global__ void __launch_bounds__(PN_THREADS) panel_kernel(PanelParams a) {
   const int wlo = me * PN_RB;
   const int whi = min(mJ, wlo + PN_RB);
   const int bJ = a.bJ;
+  if (a.gate) {
+    __shared__ int s_gate;
+    if (threadIdx.x == 0) s_gate = *a.gate;
+    __syncthreads();
+    if (s_gate == 0) return;
+  }
   if (earlier_failure(a.err)) return;
 
   double v[PN_RPT];
@@ -164,6 +171,7 @@ int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, doub
   a.rowslot = w.slots + (size_t)bJ * a.NP * 64;
   a.flags = w.flags;
   a.err = w.err;
+  a.gate = w.gate;
   void* args[] = {&a};
   RQ_HIP(hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(a.NP), dim3(PN_THREADS), args, 0, s));
   return 0;
