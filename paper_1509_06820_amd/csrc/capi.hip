@@ -76,7 +76,8 @@ void carve_common(Carve& cv, int64_t nblk, Common& c) {
 
 struct SampleBufs {
   double* omega;      // l x m (ld l)
-  double* bt;         // n x l (ld n): transposed sample
+  double* smp;        // sample, ls x n (ld ls = sample_rows_padded(l)); rows past l are zero
+  int ls;
   SampleQrcpWork sq;
   int* piv;           // b
   double* w11;        // b x b
@@ -84,11 +85,11 @@ struct SampleBufs {
 
 void carve_sample(Carve& cv, int64_t m, int64_t n, int b, int l, SampleBufs& sb) {
   sb.omega = cv.take<double>((size_t)l * m);
-  sb.bt = cv.take<double>((size_t)n * l);
-  sb.sq.refl = cv.take<double>((size_t)l * b);
-  sb.sq.rtau = cv.take<double>(b);
-  sb.sq.cand_pos = cv.take<long long>(64 * 256);
-  sb.sq.theta = cv.take<double>(64);
+  sb.ls = std::max(sample_rows_padded(l), l);
+  sb.smp = cv.take<double>((size_t)n * sb.ls);
+  sb.sq.cand = cv.take<double>(sample_qrcp_cand_elems());
+  sb.sq.cand_idx = cv.take<int>(sample_qrcp_idx_elems());
+  sb.sq.theta = cv.take<double>(sample_qrcp_theta_elems());
   sb.piv = cv.take<int>(b);
   sb.w11 = cv.take<double>((size_t)b * b);
 }
@@ -175,8 +176,8 @@ int trailing_update(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t n,
 }
 
 // Sample update, eq. (update1): B1 = S12 - (S11 R11^-1) R12, B2 = S22, on the
-// transposed sample of this block (Bt + i0, ld n).
-int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, int bJ, double* bt_blk,
+// sample columns of this block (S + i0 * ls, ld ls).
+int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, int bJ, double* s_blk,
                   const SampleBufs& sb) {
   const int64_t Nt = n - i0 - bJ;
   if (Nt <= 0) return 0;
@@ -184,18 +185,21 @@ int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, 
   const double* R12 = A + i0 + (i0 + bJ) * lda;
   const double dn = (double)Nt, db = (double)bJ;
   ProfScope ps(PC_SAMPLE_UPDATE, s, 8.0 * (3.0 * db * dn + 2.0 * db * db), 2.0 * db * db * dn + db * db * db / 3.0);
-  RQ_TRY(launch_w11(s, bJ, bt_blk, n, 1, R11, lda, sb.w11));
-  // Bt(bJ:, 0:bJ) -= R12^T W11^T
-  RQ_TRY(launch_gemm(s, true, true, Nt, bJ, bJ, -1.0, R12, lda, sb.w11, bJ, 1.0, bt_blk + bJ, n, nullptr, 0));
+  RQ_TRY(launch_w11(s, bJ, s_blk, 1, sb.ls, R11, lda, sb.w11));
+  // S(0:bJ, bJ:) -= W11 R12
+  RQ_TRY(launch_gemm(s, false, false, bJ, Nt, bJ, -1.0, sb.w11, bJ, R12, lda, 1.0, s_blk + (int64_t)bJ * sb.ls, sb.ls,
+                     nullptr, 0));
   return 0;
 }
 
-// Sketch: Bt (n x l) = A^T Omega^T with Omega l x m (ld ldo).
+// Sketch: S (l x n, ld ls) = Omega A with Omega l x m (ld ldo); rows l..ls-1
+// of S are zeroed.
 int sketch(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, int l, const double* Omega,
-           int64_t ldo, double* bt) {
+           int64_t ldo, double* S, int ls) {
   const double dm = (double)m, dn = (double)n, dl = (double)l;
   ProfScope ps(PC_SKETCH, s, 8.0 * (dm * dn + dl * dm + dl * dn), 2.0 * dl * dm * dn);
-  return launch_gemm(s, true, true, n, l, m, 1.0, A, lda, Omega, ldo, 0.0, bt, n, nullptr, 0);
+  RQ_TRY(launch_gemm(s, false, false, l, n, m, 1.0, Omega, ldo, A, lda, 0.0, S, ls, nullptr, 0));
+  return launch_zero_rows(s, l, ls, n, S, ls);
 }
 
 // ------------------------------------------------------------------ RQRCP / QR
@@ -234,24 +238,24 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
       Om = f.sb.omega;
       ldom = l;
     }
-    RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, f.sb.bt));
+    RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, f.sb.smp, f.sb.ls));
   }
   for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
     const int bJ = (int)std::min<int64_t>(b, k - i0);
     const int64_t mJ = m - i0, nJ = n - i0;
     (void)mJ;
-    double* bt_blk = pivoting ? f.sb.bt + i0 : nullptr;
+    double* s_blk = pivoting ? f.sb.smp + i0 * f.sb.ls : nullptr;
     if (pivoting) {
       {
         ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, 4.0 * l * nJ * bJ);
-        RQ_TRY(launch_sample_qrcp(s, bt_blk, n, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J)));
+        RQ_TRY(launch_sample_qrcp(s, s_blk, f.sb.ls, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J)));
       }
       ProfScope ps(PC_SWAP, s, 32.0 * m * bJ, 0.0);
       RQ_TRY(launch_apply_swaps(s, f.sb.piv, bJ, i0, A, lda, m, jpvt));
     }
-    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J, bt_blk, n, 1));
+    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J, s_blk, 1, f.sb.ls));
     RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
-    if (pivoting && i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, bt_blk, f.sb));
+    if (pivoting && i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb));
     i0 += bJ;
   }
   if (info) {
@@ -294,14 +298,14 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
     Om = t.sb.omega;
     ldom = l;
   }
-  RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, t.sb.bt));
+  RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, t.sb.smp, t.sb.ls));
   for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
     const int bJ = (int)std::min<int64_t>(b, k - i0);
     const int64_t mJ = m - i0, nJ = n - i0, Nt = n - i0 - bJ;
-    double* bt_blk = t.sb.bt + i0;
+    double* s_blk = t.sb.smp + i0 * t.sb.ls;
     {
       ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, 4.0 * l * nJ * bJ);
-      RQ_TRY(launch_sample_qrcp(s, bt_blk, n, l, nJ, bJ, t.sb.piv, t.c.info, (int)i0, sq_work(t.sb, t.c, J)));
+      RQ_TRY(launch_sample_qrcp(s, s_blk, t.sb.ls, l, nJ, bJ, t.sb.piv, t.c.info, (int)i0, sq_work(t.sb, t.c, J)));
     }
     {
       ProfScope ps(PC_SWAP, s, 32.0 * (m + i0) * bJ, 0.0);
@@ -316,7 +320,7 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
       RQ_TRY(launch_gemm(s, false, false, mJ, bJ, i0, -1.0, t.yall + i0, m, t.wt + i0 * k, k, 1.0, panel, lda,
                          nullptr, 0));
     }
-    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, Y2, m, t.bb, t.c, J, bt_blk, n, 1));
+    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, Y2, m, t.bb, t.c, J, s_blk, 1, t.sb.ls));
     if (Nt > 0) {
       double* Atr = A + i0 + (i0 + bJ) * lda;
       double* wt_tr = t.wt + (i0 + bJ) * k;
@@ -340,7 +344,7 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
       RQ_TRY(launch_gemm(s, false, false, bJ, Nt, i0 + bJ, -1.0, t.yall + i0, m, wt_tr, k, 1.0, Atr, lda, nullptr,
                          0));
     }
-    if (i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, bt_blk, t.sb));
+    if (i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, t.sb));
     i0 += bJ;
   }
   return 0;
@@ -664,14 +668,15 @@ int rq_sketch(void* stream, int64_t m, int64_t n, const double* A, int64_t lda, 
   if (l < 1 || l > 128) return -6;
   if (ldb < l) return -9;
   Carve cv(work, work_bytes);
+  const int ls = std::max(sample_rows_padded(l), (int)l);
   double* om = cv.take<double>((size_t)l * m);
-  double* bt = cv.take<double>((size_t)n * l);
+  double* smp = cv.take<double>((size_t)n * ls);
   if (!cv.ok) return -100;
   if (m == 0 || n == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
   RQ_TRY(launch_omega(s, seed, l, m, om, 1, l));
-  RQ_TRY(sketch(s, m, n, A, lda, l, om, l, bt));
-  RQ_TRY(launch_transpose(s, n, l, bt, n, B, ldb));
+  RQ_TRY(sketch(s, m, n, A, lda, l, om, l, smp, ls));
+  RQ_TRY(launch_copy2d(s, l, n, smp, ls, B, ldb));
   return 0;
 }
 
@@ -689,9 +694,10 @@ int rq_sample_qrcp(void* stream, int32_t l, int64_t n, int32_t bsteps, double* B
   if (!cv.ok) return -100;
   hipStream_t s = (hipStream_t)stream;
   RQ_TRY(launch_fill(s, c.flags, c.flag_words));
-  RQ_TRY(launch_transpose(s, l, n, B, ldb, sb.bt, n));
-  RQ_TRY(launch_sample_qrcp(s, sb.bt, n, l, n, bsteps, piv, c.info, 0, sq_work(sb, c, 0)));
-  RQ_TRY(launch_transpose(s, n, l, sb.bt, n, B, ldb));
+  RQ_TRY(launch_copy2d(s, l, n, B, ldb, sb.smp, sb.ls));
+  RQ_TRY(launch_zero_rows(s, l, sb.ls, n, sb.smp, sb.ls));
+  RQ_TRY(launch_sample_qrcp(s, sb.smp, sb.ls, l, n, bsteps, piv, c.info, 0, sq_work(sb, c, 0)));
+  RQ_TRY(launch_copy2d(s, l, n, sb.smp, sb.ls, B, ldb));
   if (info) {
     hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, c.err, c.info, info);
     RQ_HIP(hipGetLastError());

@@ -156,7 +156,7 @@ __device__ void sm_mul_uu(const double* A, const double* B, double* C) {
 // the status word and leaves the preconditioner unused.
 __global__ void __launch_bounds__(SM_T) inv_kernel(int b, const double* S, int64_t srs, int64_t scs, double* M0,
                                                    int* st) {
-  extern __shared__ double sm[];
+  extern __shared__ __align__(16) double sm[];
   __shared__ int flag;
   double* A = sm;
   double* Ai = sm + SM_N * SM_LD;
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(SM_T) inv_kernel(int b, const double* S, int64
 
 // M1 = chol(G1)^-1.
 __global__ void __launch_bounds__(SM_T) chol1_kernel(int b, const double* G1, double* M1, int* st) {
-  extern __shared__ double sm[];
+  extern __shared__ __align__(16) double sm[];
   __shared__ int flag;
   __shared__ int s_skip;
   if (threadIdx.x == 0) s_skip = *st;
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(SM_T) chol1_kernel(int b, const double* G1, do
 __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const double* G2, const double* H,
                                                      const double* Q1, int64_t ldq, double* P, int64_t ldp, double* Y,
                                                      int64_t ldy, double* tau, double* T, double* M3, int* st) {
-  extern __shared__ double sm[];
+  extern __shared__ __align__(16) double sm[];
   __shared__ int flag;
   __shared__ int s_skip;
   __shared__ double sgn[SM_N];

@@ -72,7 +72,7 @@ __device__ __forceinline__ bool earlier_failure(const int* err) {
   __shared__ int s_fail;
   if (threadIdx.x == 0) s_fail = __hip_atomic_load((int*)err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  return s_fail != 0;
+  return __builtin_amdgcn_readfirstlane(s_fail) != 0;
 }
 
 __device__ __forceinline__ void publish_flag(unsigned* flags, int me, unsigned epoch) {

@@ -19,16 +19,22 @@ int launch_scale(hipStream_t s, int64_t M, int64_t N, double beta, double* C, in
 
 // Sample QRCP (Alg. 1 on the sample, bJ steps) in place on the l x nJ sample.
 struct SampleQrcpWork {
-  double* refl;        // l x bmax reflector list (column t: v_t, rows t..l-1)
-  double* rtau;        // bmax
-  long long* cand_pos; // 64 * 256 candidate positions
-  double* theta;       // 64
-  unsigned* flags;     // 64 phase flags + go flag + t0 slot (zeroed by the caller)
+  double* cand;        // sample_qrcp_cand_elems(): candidate columns (double buffered)
+  int* cand_idx;       // sample_qrcp_idx_elems(): their positions and physical columns
+  double* theta;       // sample_qrcp_theta_elems(): best left-out norm per workgroup
+  unsigned* flags;     // arrival counter (zeroed by the caller)
   int* err;
 };
 size_t sample_qrcp_flag_words();
-// Bt is the transposed sample (nJ x l column-major, ld ldbt).
-int launch_sample_qrcp(hipStream_t s, double* Bt, int64_t ldbt, int l, int64_t nJ, int bJ, int* piv, int* info,
+// Rows of the sample as the sample QRCP stores it (l rounded up to its
+// register tile: 32, 64, 80 or 128; -1 if l > 128).
+int sample_rows_padded(int l);
+size_t sample_qrcp_cand_elems();
+size_t sample_qrcp_idx_elems();
+size_t sample_qrcp_theta_elems();
+// S is the sample, column-major with ld lds == sample_rows_padded(l) (rows
+// past l zero).
+int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ, int bJ, int* piv, int* info,
                        int info_base, const SampleQrcpWork& w);
 
 // Apply the sequential swaps (offset+t) <-> (offset+piv[t]), t < bJ, to the
@@ -66,7 +72,9 @@ int launch_w11(hipStream_t s, int bJ, const double* S, int64_t srs, int64_t scs,
                double* W);
 
 // Small utilities.
-int launch_fill(hipStream_t s, void* p, size_t words32);   // zero-fill 32-bit words
+int launch_fill(hipStream_t s, void* p, size_t words32);  // zero-fill 32-bit words
+// M(r0:r1, 0:cols) = 0
+int launch_zero_rows(hipStream_t s, int64_t r0, int64_t r1, int64_t cols, double* M, int64_t ldm);
 int launch_copy2d(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
                   int64_t ldd);
 int launch_set_identity(hipStream_t s, int64_t rows, int64_t cols, double* M, int64_t ldm);

@@ -3,9 +3,10 @@
 // matrix T of a reflector block, the W11 = S11 R11^-1 factor of the sample
 // update (eq. update1) and small data-movement kernels.
 //
-// The sample is stored transposed: Bt is nJ x l column-major, so B(r, c) =
-// Bt[c + r*ldbt] and a thread that owns a sample column reads it with
-// coalesced row-by-row loads across the wave.
+// The sample is stored column-major with its rows padded to a register tile
+// (sample_rows_padded(l) = LMAX rows, the rows past l zero): column c is the
+// LMAX contiguous doubles at S + c * LMAX, so a thread that owns a column
+// reads and writes it with 16-byte accesses at immediate offsets.
 #include <float.h>
 #include "kernels.hpp"
 
@@ -13,398 +14,509 @@ namespace rq {
 
 namespace {
 
-constexpr int SQ_THREADS = 1024;
-constexpr int SQ_MAXP = 64;      // workgroups of the sample QRCP launch
-constexpr int SQ_MAXCPT = 4;     // passes over the slab in the scan
-constexpr int SQ_FLAG_GO = 64;   // flags[64]: round released by workgroup 0
-constexpr int SQ_FLAG_T0 = 65;   // flags[65]: pivots certified so far
-constexpr int SQ_BMAX = 64;
+constexpr int SQ_T = 256;      // threads per workgroup = slab width = candidate capacity
+constexpr int SQ_BMAX = 64;    // pivots per call at most
+constexpr int SQ_MAXP = 256;   // workgroups (slabs) at most, so nJ <= 65536
+constexpr int SQ_LCAP = 128;   // rows of a candidate buffer
 
 struct SqParams {
-  double* Bt;
-  int64_t ldbt;
+  double* S;        // sample, column c at S + c * LMAX
   int l;
   int64_t nJ;
   int bJ;
   int* piv;
   int* info;
   int info_base;
-  double* refl;
-  double* rtau;
-  long long* cand_pos;
-  double* theta;
-  unsigned* flags;
+  double* cand;     // 2 buffers of SQ_T columns of SQ_LCAP rows; column of slot i at [buf][i * LMAX]
+  int* cand_idx;    // 2 buffers of 2 x SQ_T: logical position (-1: empty slot), physical column
+  double* theta;    // 2 buffers of SQ_MAXP
+  unsigned* flags;  // [0]: arrival counter (zeroed by the caller)
   int* err;
   int P;
   int K;
 };
 
+template <int LMAX>
+struct SqLds {
+  // Reflector of step t in raw form: vraw[t] is the pivot column as it was
+  // when chosen; with scal = 1 / (alpha - beta) the Householder vector is
+  // v = e_t + scal * (rows > t of vraw[t]).  Rows < t are the pivot's R
+  // entries, so vraw also yields the final sample column (beta on row t).
+  double vraw[SQ_BMAX * LMAX];
+  double wcol[2][SQ_T / WAVE][LMAX];  // each wave's best candidate column (double buffered by step)
+  double wsc[2][SQ_T / WAVE][4];      // its tau, scal, beta
+  double taus[SQ_BMAX];
+  double scals[SQ_BMAX];
+  double betas[SQ_BMAX];
+  double kv[SQ_T];                    // sort keys: value, position, lane
+  int kp[SQ_T];
+  int kl[SQ_T];
+  int rank_of[SQ_T];
+  int plog[SQ_BMAX];                  // position of the pivot chosen at step t
+  int pphys[SQ_BMAX];                 // its physical column
+  double rv[2][SQ_T / WAVE];          // per-wave argmax
+  int rp[2][SQ_T / WAVE];
+  double theta;
+  int bad;
+};
+
 __device__ __forceinline__ double ranked(double nu) { return (nu != nu) ? -1.0 : nu; }
 
-// A sample column is held by LANES adjacent lanes; lane `sub` owns rows
-// sub*RPL .. sub*RPL+RPL-1 (rows >= l are zero).
-template <int LANES>
-__device__ __forceinline__ double grp_sum(double v) {
-#pragma unroll
-  for (int off = 1; off < LANES; off <<= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
-}
-
-template <int LMAX, int LANES>
-__device__ __forceinline__ void sq_load(const SqParams& a, int64_t c, int sub, double (&col)[LMAX / LANES]) {
-  constexpr int RPL = LMAX / LANES;
-#pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    const int r = sub * RPL + i;
-    col[i] = (r < a.l) ? a.Bt[c + (int64_t)r * a.ldbt] : 0.0;
-  }
-}
-
-// Squared norm over rows >= from.  Lane partial sums run in increasing row
-// order and are combined pairwise, so every lane of the group -- and the scan
-// and the candidate steps -- get bitwise identical values.
-template <int LMAX, int LANES>
-__device__ __forceinline__ double sq_norm2(const double (&col)[LMAX / LANES], int sub, int from) {
-  constexpr int RPL = LMAX / LANES;
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < RPL; ++i) s += (sub * RPL + i >= from) ? col[i] * col[i] : 0.0;
-  return grp_sum<LANES>(s);
-}
-
-// col <- (I - tau v v^T) col, v in LDS (zero above its first row and below row l).
-template <int LMAX, int LANES>
-__device__ __forceinline__ void sq_apply(double (&col)[LMAX / LANES], int sub, const double* v, double tau) {
-  constexpr int RPL = LMAX / LANES;
-  double d = 0.0;
-#pragma unroll
-  for (int i = 0; i < RPL; ++i) d += v[sub * RPL + i] * col[i];
-  d = grp_sum<LANES>(d) * tau;
-  asm volatile("" ::: "memory");
-#pragma unroll
-  for (int i = 0; i < RPL; ++i) col[i] -= d * v[sub * RPL + i];
-}
-
-__device__ __forceinline__ bool key_before(double v1, long long p1, double v2, long long p2) {
+__device__ __forceinline__ bool better(double v1, int p1, double v2, int p2) {
   return (v1 > v2) || (v1 == v2 && p1 < p2);
 }
 
-// Block-wide argmax over (value, position), SQ_THREADS threads.
-__device__ __forceinline__ void block_argmax(double& v, long long& p, double* sv, long long* sp) {
-#pragma unroll
-  for (int off = 1; off < WAVE; off <<= 1) {
-    const double ov = __shfl_xor(v, off, WAVE);
-    const long long op = __shfl_xor(p, off, WAVE);
-    if (key_before(ov, op, v, p)) { v = ov; p = op; }
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { sv[w] = v; sp[w] = p; }
-  __syncthreads();
-  if (threadIdx.x < WAVE) {
-    constexpr int NW = SQ_THREADS / WAVE;
-    double bv = (threadIdx.x < NW) ? sv[threadIdx.x] : -INFINITY;
-    long long bp = (threadIdx.x < NW) ? sp[threadIdx.x] : LLONG_MAX;
-#pragma unroll
-    for (int off = 1; off < NW; off <<= 1) {
-      const double ov = __shfl_xor(bv, off, WAVE);
-      const long long op = __shfl_xor(bp, off, WAVE);
-      if (key_before(ov, op, bv, bp)) { bv = ov; bp = op; }
-    }
-    if (threadIdx.x == 0) { sv[NW] = bv; sp[NW] = bp; }
-  }
-  __syncthreads();
-  v = sv[SQ_THREADS / WAVE];
-  p = sp[SQ_THREADS / WAVE];
+// Values every thread reads from the same LDS word are uniform, but the
+// compiler cannot know it; taking them from the first lane lets it keep the
+// step index and everything derived from it in scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
 
-// Sort n (power of two) keys in LDS: descending value, ascending position.
-__device__ void bitonic_sort_keys(double* kv, long long* kp, int n) {
-  for (int size = 2; size <= n; size <<= 1) {
+// LDS rows are read 8 at a time (four 16-byte reads) into a register chunk,
+// two chunks ahead of their use.  The address of each read is made to depend
+// on the result of an earlier chunk (an empty asm statement with that value
+// as input), so the compiler cannot hoist all reads to the top of the pass
+// and hold the whole reflector in registers next to the column.
+__device__ __forceinline__ void lds_chunk(double (&buf)[8], const double* __restrict__ p) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 w = q[i];
+    buf[2 * i] = w.x;
+    buf[2 * i + 1] = w.y;
+  }
+}
+
+__device__ __forceinline__ const double* after(const double* p, double dep) {
+  int z = 0;
+  asm volatile("" : "+v"(z) : "v"(dep));
+  return p + z;
+}
+
+// x <- (I - tau v v^T) x for the reflector of step s given in raw form (xw,
+// scal; see SqLds::vraw).  Rows above s are untouched and the 8-row chunks
+// entirely above row s are skipped; s is uniform, so every branch is scalar.
+// With NORM, returns the squared norm of the updated rows > s.
+template <int LMAX, bool NORM>
+__device__ __forceinline__ double sq_apply(double (&x)[LMAX], const double* xw, double tau, double scal, int s) {
+  constexpr int NC = LMAX / 8;
+  const int k0 = s >> 3;
+  double vb[3][8];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double xs = 0.0;
+#pragma unroll
+  for (int j = -2; j < NC; ++j) {
+    if (j >= 0 && j >= k0) {
+      if (j == k0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int r = 8 * j + i;
+          xs += (r == s) ? x[r] : 0.0;
+          acc[i & 3] += (r > s) ? vb[j % 3][i] * x[r] : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i & 3] = fma(vb[j % 3][i], x[8 * j + i], acc[i & 3]);
+      }
+    }
+    const int c = j + 2;
+    if (c < NC && c >= k0) lds_chunk(vb[c % 3], (j >= 0 && j >= k0 ? after(xw, acc[0]) : xw) + 8 * c);
+  }
+  const double d = tau * (xs + scal * ((acc[0] + acc[1]) + (acc[2] + acc[3])));
+  const double ds = d * scal;
+  const double* xw2 = after(xw, d);
+  double nrm[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = -2; j < NC; ++j) {
+    if (j >= 0 && j >= k0) {
+      if (j == k0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int r = 8 * j + i;
+          const double upd = fma(-ds, vb[j % 3][i], x[r]);
+          x[r] = (r > s) ? upd : ((r == s) ? x[r] - d : x[r]);
+          if (NORM) nrm[i & 3] += (r > s) ? x[r] * x[r] : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int r = 8 * j + i;
+          x[r] = fma(-ds, vb[j % 3][i], x[r]);
+          if (NORM) nrm[i & 3] = fma(x[r], x[r], nrm[i & 3]);
+        }
+      }
+    }
+    const int c = j + 2;
+    if (c < NC && c >= k0) lds_chunk(vb[c % 3], (j >= 0 && j >= k0 ? after(xw2, x[8 * (j < 0 ? 0 : j)]) : xw2) + 8 * c);
+  }
+  return NORM ? (nrm[0] + nrm[1]) + (nrm[2] + nrm[3]) : 0.0;
+}
+
+// Squared norm of rows >= from (uniform); whole chunks by branch, the chunk
+// holding row `from` row by row.
+template <int LMAX>
+__device__ __forceinline__ double sq_norm2(const double (&x)[LMAX], int from) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < LMAX / 8; ++k) {
+    if (8 * k >= from) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s[i & 3] = fma(x[8 * k + i], x[8 * k + i], s[i & 3]);
+    } else if (8 * k + 8 > from) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s[i & 3] += (8 * k + i >= from) ? x[8 * k + i] * x[8 * k + i] : 0.0;
+    }
+  }
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// x[t] for a uniform t.
+template <int LMAX>
+__device__ __forceinline__ double row_at(const double (&x)[LMAX], int t) {
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < LMAX / 8; ++k)
+    if (8 * k <= t && t < 8 * k + 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a += (8 * k + i == t) ? x[8 * k + i] : 0.0;
+    }
+  return a;
+}
+
+// Maximum over the wave by DPP moves within rows of 16 lanes, then the four
+// row results read as scalars.
+__device__ __forceinline__ double dpp_pull(double v, int ctrl_id) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  switch (ctrl_id) {
+    case 0:  // quad_perm [1, 0, 3, 2]
+      lo = __builtin_amdgcn_update_dpp(lo, lo, 0xB1, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(hi, hi, 0xB1, 0xF, 0xF, false);
+      break;
+    case 1:  // quad_perm [2, 3, 0, 1]
+      lo = __builtin_amdgcn_update_dpp(lo, lo, 0x4E, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(hi, hi, 0x4E, 0xF, 0xF, false);
+      break;
+    case 2:  // row_half_mirror
+      lo = __builtin_amdgcn_update_dpp(lo, lo, 0x141, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(hi, hi, 0x141, 0xF, 0xF, false);
+      break;
+    default:  // row_mirror
+      lo = __builtin_amdgcn_update_dpp(lo, lo, 0x140, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(hi, hi, 0x140, 0xF, 0xF, false);
+      break;
+  }
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_pull(v, 0));
+  v = fmax(v, dpp_pull(v, 1));
+  v = fmax(v, dpp_pull(v, 2));
+  v = fmax(v, dpp_pull(v, 3));
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+}
+
+// Wave-level (value, position) argmax: the largest value, ties to the lowest
+// position.  Values must not be NaN.  Uniform result.
+__device__ __forceinline__ void wave_argmax_vp(double v, int p, double& bv, int& bp) {
+  bv = wave_max(v);
+  unsigned long long m = __ballot(v == bv && p != INT_MAX);
+  int best = INT_MAX;
+  while (m) {
+    const int ln = __builtin_ctzll(m);
+    m &= m - 1;
+    best = min(best, __builtin_amdgcn_readlane(p, ln));
+  }
+  bp = best;
+}
+
+// Sort the SQ_T keys in LDS: larger value first, ties by lower position.
+template <int LMAX>
+__device__ void sq_sort(SqLds<LMAX>& L) {
+  for (int size = 2; size <= SQ_T; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = threadIdx.x; t < n / 2; t += SQ_THREADS) {
+      const int t = threadIdx.x;
+      if (t < SQ_T / 2) {
         const int lo = 2 * stride * (t / stride) + (t % stride);
         const int hi = lo + stride;
-        const bool up = ((lo & size) == 0);  // this run sorted "best first"
-        const double v1 = kv[lo], v2 = kv[hi];
-        const long long p1 = kp[lo], p2 = kp[hi];
-        const bool swap = up ? key_before(v2, p2, v1, p1) : key_before(v1, p1, v2, p2);
-        if (swap) { kv[lo] = v2; kv[hi] = v1; kp[lo] = p2; kp[hi] = p1; }
+        const bool up = ((lo & size) == 0);
+        const double v1 = L.kv[lo], v2 = L.kv[hi];
+        const int p1 = L.kp[lo], p2 = L.kp[hi];
+        const bool swap = up ? better(v2, p2, v1, p1) : better(v1, p1, v2, p2);
+        if (swap) {
+          const int l1 = L.kl[lo];
+          L.kv[lo] = v2; L.kv[hi] = v1;
+          L.kp[lo] = p2; L.kp[hi] = p1;
+          L.kl[lo] = L.kl[hi]; L.kl[hi] = l1;
+        }
       }
       __syncthreads();
     }
   }
 }
 
-struct SqShared {
-  double* vs;       // reflectors of the scan, SQ_BMAX x LMAX (aliases vlog)
-  double* vlog;     // reflectors found in this round (SQ_BMAX x LMAX)
-  double* slog;     // S columns of this round's pivots (SQ_BMAX x LMAX)
-  double* vsh;      // 2 x LMAX current reflector (double buffered)
-  double* kv;       // sort keys (values)
-  long long* kp;    // sort keys (positions)
-  double* sv;
-  long long* sp;
-  double* scal;     // tau log (SQ_BMAX) + current tau (2)
-  int* plog;        // pivot log (SQ_BMAX)
-  int* misc;
-};
-
-// Scan: apply reflectors [a0, t0) to every unselected column (positions >=
-// t0) of this workgroup's slab and write it back; if `select`, rank the slab
-// by trailing norm over rows >= t0, publish the K best positions as
-// candidates and theta = the best norm left out.
-template <int LMAX, int LANES>
-__device__ void sq_scan(const SqParams& a, int me, int a0, int t0, bool select, const SqShared& sh) {
-  constexpr int RPL = LMAX / LANES;
-  constexpr int COLS = SQ_THREADS / LANES;
-  const int tid = threadIdx.x, sub = tid % LANES, grp = tid / LANES;
-  const int nr = t0 - a0;
-  for (int e = tid; e < nr * LMAX; e += SQ_THREADS) {
-    const int s = e / LMAX, r = e - s * LMAX;
-    sh.vs[e] = (r < a.l) ? a.refl[r + (int64_t)(a0 + s) * a.l] : 0.0;
-  }
-  for (int s = tid; s < nr; s += SQ_THREADS) sh.scal[s] = a.rtau[a0 + s];
-  __syncthreads();
-
-  const int64_t rem = a.nJ - t0;
-  const int64_t w = (rem + a.P - 1) / a.P;
-  const int64_t lo = t0 + (int64_t)me * w;
-  const int64_t hi = min(a.nJ, lo + w);
-  const int cnt = (int)max<int64_t>(0, hi - lo);
-  bool bad = false;
-  for (int e0 = 0; e0 < cnt; e0 += COLS) {
-    const int e = e0 + grp;
-    const bool have = e < cnt;
-    const int64_t c = lo + (have ? e : 0);
-    double col[RPL];
-    sq_load<LMAX, LANES>(a, c, sub, col);
-    for (int s = 0; s < nr; ++s) sq_apply<LMAX, LANES>(col, sub, sh.vs + s * LMAX, sh.scal[s]);
-    if (have && nr > 0) {
+// One pass over this workgroup's slab (one column per thread): apply the
+// reflectors of steps [a0, t0), write the column back (on the last pass, a
+// column whose position changed goes to its final position), and, if
+// `select`, publish the K best columns by trailing norm over rows >= t0 as
+// candidates together with theta = the best norm left out.  The sample has
+// LMAX rows (rows past l are zero and stay zero).
+template <int LMAX>
+__device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t0, bool select, int buf,
+                        int pos_s, bool sel_s) {
+  const int tid = threadIdx.x;
+  const int64_t c = (int64_t)me * SQ_T + tid;
+  const bool mine = c < a.nJ && !sel_s;
+  double x[LMAX];
+  if (mine) {
+    const double2* col = reinterpret_cast<const double2*>(a.S + c * LMAX);
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = sub * RPL + i;
-        if (r >= a0 && r < a.l) a.Bt[c + (int64_t)r * a.ldbt] = col[i];
-      }
+    for (int i = 0; i < LMAX / 2; ++i) {
+      const double2 w = col[i];
+      x[2 * i] = w.x;
+      x[2 * i + 1] = w.y;
     }
-    if (select) {
-      const double x = sq_norm2<LMAX, LANES>(col, sub, t0);
-      if (have && !(x <= DBL_MAX)) bad = true;
-      if (have && sub == 0) { sh.kv[e] = ranked(x); sh.kp[e] = c; }
-    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < LMAX; ++r) x[r] = 0.0;
+  }
+  for (int s = a0; s < t0; ++s) sq_apply<LMAX, false>(x, L.vraw + s * LMAX, uni(L.taus[s]), uni(L.scals[s]), s);
+  const bool move = !select && pos_s != c;
+  if (mine && (move || t0 > a0)) {
+    double2* col = reinterpret_cast<double2*>(a.S + (move ? (int64_t)pos_s : c) * LMAX);
+#pragma unroll
+    for (int i = 0; i < LMAX / 2; ++i) col[i] = make_double2(x[2 * i], x[2 * i + 1]);
   }
   if (!select) return;
-  if (bad && a.info) atomicCAS(a.info, 0, a.info_base + t0 + 1);
-  long long* cand = a.cand_pos + (int64_t)me * a.K;
-  if (a.K >= cnt) {
-    __syncthreads();
-    for (int e = tid; e < a.K; e += SQ_THREADS) cand[e] = (e < cnt) ? sh.kp[e] : -1;
-    if (tid == 0) a.theta[me] = -INFINITY;
-    return;
-  }
-  int n2 = 1;
-  while (n2 < cnt) n2 <<= 1;
-  for (int e = cnt + tid; e < n2; e += SQ_THREADS) { sh.kv[e] = -INFINITY; sh.kp[e] = LLONG_MAX; }
+  const double nu = mine ? sq_norm2<LMAX>(x, t0) : 0.0;
+  if (tid == 0) L.bad = 0;
+  L.kv[tid] = mine ? ranked(nu) : -INFINITY;
+  L.kp[tid] = mine ? pos_s : INT_MAX;
+  L.kl[tid] = tid;
+  L.rank_of[tid] = -1;
   __syncthreads();
-  bitonic_sort_keys(sh.kv, sh.kp, n2);
-  for (int e = tid; e < a.K; e += SQ_THREADS) cand[e] = sh.kp[e];
-  if (tid == 0) a.theta[me] = sh.kv[a.K];
-}
-
-// Candidate steps (workgroup 0): greedy QRCP on the gathered candidates as
-// long as the winner provably beats every column left out of the candidate
-// set (its norm exceeds the largest left-out norm at the start of the round,
-// which bounds all later ones).  Nothing is written to global memory inside
-// the loop; the round's pivots, reflectors, S columns and column moves are
-// written at the end.  Returns the number of pivots fixed so far.
-template <int LMAX, int LANES>
-__device__ int sq_steps(const SqParams& a, int t0, const SqShared& sh) {
-  constexpr int RPL = LMAX / LANES;
-  const int tid = threadIdx.x, sub = tid % LANES, grp = tid / LANES;
-  const int C = a.P * a.K;
-  double col[RPL];
-  long long pos = (grp < C) ? a.cand_pos[grp] : -1;
-  bool active = pos >= 0;
-  sq_load<LMAX, LANES>(a, active ? pos : 0, sub, col);
-  double theta = -INFINITY;
-  for (int q = 0; q < a.P; ++q) theta = fmax(theta, a.theta[q]);
-  const double bound = (theta > 0.0) ? theta * (1.0 + 1e-12) : theta;
-
-  int t = t0;
-  while (t < a.bJ) {
-    double nu = active ? ranked(sq_norm2<LMAX, LANES>(col, sub, t)) : -INFINITY;
-    long long p = active ? pos : LLONG_MAX;
-    block_argmax(nu, p, sh.sv, sh.sp);
-    if ((t > t0 && !(nu > bound)) || p == LLONG_MAX) break;
-    const bool winner = active && pos == p;
-    double* vsh = sh.vsh + (t & 1) * LMAX;
-    if (winner) {
-      // Householder reflector of rows t..l-1 (LAPACK dlarfg normalisation)
-      double alpha_part = 0.0, xn2 = 0.0;
+  if (mine && !(nu <= DBL_MAX)) L.bad = 1;
+  sq_sort<LMAX>(L);
+  if (tid < a.K && L.kp[tid] != INT_MAX) L.rank_of[L.kl[tid]] = tid;
+  __syncthreads();
+  if (L.bad && tid == 0 && a.info) atomicCAS(a.info, 0, a.info_base + t0 + 1);
+  const int rank = L.rank_of[tid];
+  double* cb = a.cand + (size_t)buf * SQ_LCAP * SQ_T;
+  int* ib = a.cand_idx + (size_t)buf * 2 * SQ_T;
+  if (rank >= 0) {
+    const int slot = me * a.K + rank;
+    double2* col = reinterpret_cast<double2*>(cb + (size_t)slot * LMAX);
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = sub * RPL + i;
-        alpha_part += (r == t) ? col[i] : 0.0;
-        xn2 += (r > t) ? col[i] * col[i] : 0.0;
+    for (int i = 0; i < LMAX / 2; ++i) col[i] = make_double2(x[2 * i], x[2 * i + 1]);
+    ib[slot] = pos_s;
+    ib[SQ_T + slot] = (int)c;
+  }
+  if (tid < a.K && L.kp[tid] == INT_MAX) ib[me * a.K + tid] = -1;
+  if (tid == 0)
+    a.theta[(size_t)buf * SQ_MAXP + me] = (a.K < SQ_T && L.kp[a.K] != INT_MAX) ? L.kv[a.K] : -INFINITY;
+}
+
+// Arrival barrier over the P workgroups: every workgroup adds one to the
+// counter after its candidates are visible device-wide and waits until the
+// counter reaches round * P.  Bounded: on timeout the error word is set.
+__device__ bool sq_barrier(const SqParams& a, unsigned round) {
+  __shared__ int s_bad;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x < WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) {
+      __hip_atomic_fetch_add(&a.flags[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned target = round * (unsigned)a.P;
+      long spins = 0;
+      int bad = 0;
+      while (__hip_atomic_load(&a.flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > SPIN_LIMIT) { bad = 1; atomicExch(a.err, 1); break; }
+        __builtin_amdgcn_s_sleep(1);
       }
-      const double alpha = grp_sum<LANES>(alpha_part);
-      xn2 = grp_sum<LANES>(xn2);
-      double tau = 0.0, beta = alpha, scal = 0.0;
-      if (xn2 != 0.0) {
-        const double nrm = sqrt(alpha * alpha + xn2);
-        beta = (alpha >= 0.0) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      const int slot = t - t0;
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = sub * RPL + i;
-        const double v = (r == t) ? 1.0 : ((r > t) ? col[i] * scal : 0.0);
-        vsh[r] = v;
-        sh.vlog[slot * LMAX + r] = v;
-        sh.slog[slot * LMAX + r] = (r < t) ? col[i] : ((r == t) ? beta : 0.0);
-      }
-      if (sub == 0) {
-        sh.scal[SQ_BMAX + (t & 1)] = tau;
-        sh.scal[slot] = tau;
-        sh.plog[slot] = (int)p;
-      }
-      active = false;
+      s_bad = bad;
     }
-    // sequential swap t <-> p: a candidate sitting at position t moves to p
-    if (active && pos == t) pos = p;
-    __syncthreads();
-    if (active) sq_apply<LMAX, LANES>(col, sub, vsh, sh.scal[SQ_BMAX + (t & 1)]);
-    ++t;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  const int tn = t;
-  const int nt = tn - t0;
-  // pivots, reflectors
-  for (int e = tid; e < nt * a.l; e += SQ_THREADS) {
-    const int s = e / a.l, r = e - s * a.l;
-    a.refl[r + (int64_t)(t0 + s) * a.l] = sh.vlog[s * LMAX + r];
-  }
-  for (int s = tid; s < nt; s += SQ_THREADS) {
-    a.rtau[t0 + s] = sh.scal[s];
-    a.piv[t0 + s] = sh.plog[s];
-  }
-  // Column moves of this round: position q >= tn named as a partner receives
-  // the round-start column found by undoing the swaps from the last one.
-  int* dst = sh.misc;           // SQ_BMAX destinations
-  int* src = sh.misc + SQ_BMAX; // their sources
-  int* nmv = sh.misc + 2 * SQ_BMAX;
-  if (tid == 0) *nmv = 0;
-  __syncthreads();
-  if (tid < nt) {
-    const int q = sh.plog[tid];
-    bool first = q >= tn;
-    for (int s2 = 0; s2 < tid && first; ++s2)
-      if (sh.plog[s2] == q) first = false;
-    if (first) {
-      int x = q;
-      for (int s2 = nt - 1; s2 >= 0; --s2) {
-        const int ps = sh.plog[s2], ts = t0 + s2;
-        if (x == ts) x = ps;
-        else if (x == ps) x = ts;
-      }
-      const int k = atomicAdd(nmv, 1);
-      dst[k] = q;
-      src[k] = x;
-    }
-  }
-  __syncthreads();
-  const int nm = *nmv;
-  double* stage = sh.vlog;  // reused: reflectors are already written out
-  for (int e = tid; e < nm * a.l; e += SQ_THREADS) {
-    const int k = e / a.l, r = e - k * a.l;
-    stage[k * LMAX + r] = a.Bt[src[k] + (int64_t)r * a.ldbt];
-  }
-  __syncthreads();
-  for (int e = tid; e < nm * a.l; e += SQ_THREADS) {
-    const int k = e / a.l, r = e - k * a.l;
-    a.Bt[dst[k] + (int64_t)r * a.ldbt] = stage[k * LMAX + r];
-  }
-  for (int e = tid; e < nt * a.l; e += SQ_THREADS) {
-    const int s = e / a.l, r = e - s * a.l;
-    a.Bt[(t0 + s) + (int64_t)r * a.ldbt] = sh.slog[s * LMAX + r];
-  }
-  return tn;
+  return __builtin_amdgcn_readfirstlane(s_bad) == 0;
 }
 
-// LDS: [vlog = vs] [slog | sort keys] [vsh] [argmax] [tau log] [pivot log] [moves]
-// (the sort keys live only in the scan, the S-column log only in the steps)
-template <int LMAX, int LANES>
-constexpr size_t sq_region_b() {
-  constexpr size_t slog = (size_t)SQ_BMAX * LMAX * 8;
-  constexpr size_t keys = (size_t)(SQ_THREADS / LANES) * SQ_MAXCPT * 16;
-  return slog > keys ? slog : keys;
-}
-
-template <int LMAX, int LANES>
-constexpr size_t sq_lds_bytes() {
-  return (size_t)SQ_BMAX * LMAX * 8 + sq_region_b<LMAX, LANES>() + 2 * LMAX * 8 + 64 * 8 + (SQ_BMAX + 4) * 8 +
-         SQ_BMAX * 4 + 3 * SQ_BMAX * 4 + 64;
-}
-
-template <int LMAX, int LANES>
-__global__ void __launch_bounds__(SQ_THREADS) sample_qrcp_kernel(SqParams a) {
-  extern __shared__ double smem[];
-  SqShared sh;
-  char* base = (char*)smem;
-  sh.vlog = (double*)base; base += (size_t)SQ_BMAX * LMAX * 8;
-  sh.vs = sh.vlog;
-  sh.slog = (double*)base;
-  sh.kv = (double*)base;
-  sh.kp = (long long*)(base + (size_t)(SQ_THREADS / LANES) * SQ_MAXCPT * 8);
-  base += sq_region_b<LMAX, LANES>();
-  sh.vsh = (double*)base; base += 2 * LMAX * 8;
-  sh.sv = (double*)base; base += 32 * 8;
-  sh.sp = (long long*)base; base += 32 * 8;
-  sh.scal = (double*)base; base += (SQ_BMAX + 4) * 8;
-  sh.plog = (int*)base; base += SQ_BMAX * 4;
-  sh.misc = (int*)base;
-  const int me = blockIdx.x;
+// Sample QRCP (Alg. 1 for bJ steps, Alg. 4) by certified candidate rounds.
+// Each round every workgroup updates its slab of 256 columns and proposes its
+// K best columns; all workgroups then run the same greedy steps on the
+// gathered candidates (so they all hold the round's reflectors without a
+// second exchange) for as long as the winner provably beats every column
+// left out: its trailing norm must exceed theta, the largest left-out norm at
+// the start of the round, which bounds the left-out norms later in the round
+// (they only shrink) -- with a relative margin of 1e-12 for rounding.  The
+// steps are the sequential ones of the algorithm: swap of positions t and p,
+// Householder reflector of the pivot column (LAPACK normalisation), update of
+// the remaining candidates.  Within a step, each wave's best candidate forms
+// its reflector and stores its column before the one barrier of the step, so
+// the winner's reflector is ready as soon as the winner is known.  Columns
+// are never moved during the rounds; each thread tracks the logical position
+// of its slab column.
+template <int LMAX>
+__global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
+  extern __shared__ __align__(16) double smem[];
+  SqLds<LMAX>& L = *reinterpret_cast<SqLds<LMAX>*>(smem);
+  const int me = blockIdx.x, tid = threadIdx.x, wv_id = tid / WAVE;
   if (earlier_failure(a.err)) return;
+  const int64_t c_s = (int64_t)me * SQ_T + tid;
+  int pos_s = (int)c_s;   // logical position of this thread's slab column
+  bool sel_s = false;     // selected as a pivot
   int a0 = 0, t0 = 0;
   for (unsigned round = 1;; ++round) {
     const bool select = t0 < a.bJ;
-    sq_scan<LMAX, LANES>(a, me, a0, t0, select, sh);
+    const int buf = round & 1;
+    sq_scan<LMAX>(a, L, me, a0, t0, select, buf, pos_s, sel_s);
     if (!select) break;
-    publish_flag(a.flags, me, round);
-    if (me == 0) {
-      if (!wait_flags(a.flags, a.P, round, a.err)) return;
-      const int tn = sq_steps<LMAX, LANES>(a, t0, sh);
-      if (threadIdx.x == 0) a.flags[SQ_FLAG_T0] = (unsigned)tn;
-      publish_flag(a.flags + SQ_FLAG_GO, 0, round);
+    if (!sq_barrier(a, round)) return;
+
+    // gather the candidates (identical in every workgroup)
+    const int C = a.P * a.K;
+    const double* cb = a.cand + (size_t)buf * SQ_LCAP * SQ_T;
+    const int* ib = a.cand_idx + (size_t)buf * 2 * SQ_T;
+    int pos = (tid < C) ? ib[tid] : -1;
+    const int phys = (tid < C) ? ib[SQ_T + tid] : -1;
+    bool active = pos >= 0;
+    if (!active) pos = INT_MAX;
+    double x[LMAX];
+    if (active) {
+      const double2* col = reinterpret_cast<const double2*>(cb + (size_t)tid * LMAX);
+#pragma unroll
+      for (int i = 0; i < LMAX / 2; ++i) {
+        const double2 w = col[i];
+        x[2 * i] = w.x;
+        x[2 * i + 1] = w.y;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < LMAX; ++r) x[r] = 0.0;
     }
-    if (!wait_one(a.flags + SQ_FLAG_GO, round, a.err, nullptr)) return;
-    const int tn = (int)__hip_atomic_load(&a.flags[SQ_FLAG_T0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a0 = t0;
-    t0 = tn;
+    if (tid < WAVE) {
+      double th = -INFINITY;
+      for (int q = tid; q < a.P; q += WAVE) th = fmax(th, a.theta[(size_t)buf * SQ_MAXP + q]);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) th = fmax(th, __shfl_xor(th, off, WAVE));
+      if (tid == 0) L.theta = th;
+    }
     __syncthreads();
+    const double theta = uni(L.theta);
+    const double bound = (theta > 0.0) ? theta * (1.0 + 1e-12) : theta;
+
+    int t = t0;
+    double nu = active ? sq_norm2<LMAX>(x, t) : 0.0;
+    while (t < a.bJ) {
+      t = uni(t);
+      const int par = t & 1;
+      double v;
+      int p;
+      wave_argmax_vp(active ? ranked(nu) : -INFINITY, active ? pos : INT_MAX, v, p);
+      if (active && pos == p) {
+        // this wave's best candidate: Householder reflector of rows t..l-1
+        // (dlarfg normalisation), stored with the column in case it wins
+        const double alpha = row_at<LMAX>(x, t);
+        const double xn2 = sq_norm2<LMAX>(x, t + 1);
+        double tau = 0.0, beta = alpha, scal = 0.0;
+        if (xn2 != 0.0) {
+          const double nrm = sqrt(alpha * alpha + xn2);
+          beta = (alpha >= 0.0) ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        double2* dst = reinterpret_cast<double2*>(L.wcol[par][wv_id]);
+#pragma unroll
+        for (int i = 0; i < LMAX / 2; ++i) dst[i] = make_double2(x[2 * i], x[2 * i + 1]);
+        L.wsc[par][wv_id][0] = tau;
+        L.wsc[par][wv_id][1] = scal;
+        L.wsc[par][wv_id][2] = beta;
+      }
+      if ((tid & (WAVE - 1)) == 0) { L.rv[par][wv_id] = v; L.rp[par][wv_id] = p; }
+      __syncthreads();
+      v = uni(L.rv[par][0]);
+      p = uni(L.rp[par][0]);
+      int ws = 0;
+#pragma unroll
+      for (int w = 1; w < SQ_T / WAVE; ++w) {
+        const double vw = uni(L.rv[par][w]);
+        const int pw = uni(L.rp[par][w]);
+        if (better(vw, pw, v, p)) { v = vw; p = pw; ws = w; }
+      }
+      if ((t > t0 && !(v > bound)) || p == INT_MAX) break;
+      const double tau = uni(L.wsc[par][ws][0]);
+      const double scal = uni(L.wsc[par][ws][1]);
+      const double* xw = L.wcol[par][ws];
+      if (active && pos == p) {
+        active = false;
+        L.pphys[t] = phys;
+      } else if (active && pos == t) {
+        pos = p;  // sequential swap: the column at position t moves to p
+      }
+      if (tid < LMAX / 2)
+        reinterpret_cast<double2*>(L.vraw + t * LMAX)[tid] = reinterpret_cast<const double2*>(xw)[tid];
+      if (tid == 0) {
+        L.taus[t] = tau;
+        L.scals[t] = scal;
+        L.betas[t] = uni(L.wsc[par][ws][2]);
+        L.plog[t] = p;
+      }
+      if (active) nu = sq_apply<LMAX, true>(x, xw, tau, scal, t);
+      ++t;
+    }
+    const int tn = t;
+    __syncthreads();
+    for (int s = t0; s < tn; ++s) {
+      if (c_s == L.pphys[s]) sel_s = true;
+      else if (pos_s == s) pos_s = L.plog[s];
+    }
+    if (me == 0 && tid >= t0 && tid < tn) a.piv[tid] = L.plog[tid];
+    if (tn == t0) {  // no candidate left although steps remain: cannot happen for bJ <= nJ
+      if (tid == 0) atomicExch(a.err, 1);
+      return;
+    }
+    a0 = uni(t0);
+    t0 = uni(tn);
+  }
+  // the pivot columns of the sample go to positions 0..bJ-1 (workgroup 0
+  // owns those physical columns, and its own reads of them are done): rows
+  // above the pivot row from the stored column, beta on it, zeros below
+  if (me == 0) {
+    __syncthreads();
+    for (int e = tid; e < a.bJ * LMAX; e += SQ_T) {
+      const int tt = e / LMAX, r = e - tt * LMAX;
+      a.S[e] = (r < tt) ? L.vraw[e] : ((r == tt) ? L.betas[tt] : 0.0);
+    }
   }
 }
 
-template <int LMAX, int LANES>
+template <int LMAX>
 int launch_sq(hipStream_t s, SqParams& a) {
-  constexpr int COLS = SQ_THREADS / LANES;
-  int64_t P = (a.nJ + COLS - 1) / COLS;
-  if (P > SQ_MAXP) P = SQ_MAXP;
-  if ((a.nJ + P - 1) / P > (int64_t)COLS * SQ_MAXCPT) return -4;  // n too large for this kernel
+  const int64_t P = (a.nJ + SQ_T - 1) / SQ_T;
+  if (P > SQ_MAXP) return -4;  // n too large for this kernel
   a.P = (int)P;
-  a.K = (P == 1) ? COLS : std::max(1, COLS / (int)P);
-  const size_t lds = sq_lds_bytes<LMAX, LANES>();
-  static_assert(sq_lds_bytes<LMAX, LANES>() <= 160 * 1024, "LDS budget");
+  a.K = SQ_T / a.P;
+  constexpr size_t lds = sizeof(SqLds<LMAX>);
+  static_assert(lds <= 160 * 1024, "LDS budget");
   static bool attr_set = false;
   if (!attr_set) {
-    RQ_HIP(hipFuncSetAttribute((const void*)sample_qrcp_kernel<LMAX, LANES>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    RQ_HIP(hipFuncSetAttribute((const void*)sample_qrcp_kernel<LMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
     attr_set = true;
   }
   void* args[] = {&a};
-  RQ_HIP(hipLaunchCooperativeKernel((const void*)sample_qrcp_kernel<LMAX, LANES>, dim3(a.P), dim3(SQ_THREADS), args,
-                                    lds, s));
+  RQ_HIP(hipLaunchCooperativeKernel((const void*)sample_qrcp_kernel<LMAX>, dim3(a.P), dim3(SQ_T), args, lds, s));
   return 0;
 }
 
@@ -557,6 +669,14 @@ __global__ void fill_kernel(unsigned* p, size_t n) {
   if (i < n) p[i] = 0u;
 }
 
+__global__ void zero_rows_kernel(int64_t r0, int64_t r1, int64_t cols, double* M, int64_t ldm) {
+  const int64_t rows = r1 - r0;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = r0 + (idx - j * rows);
+  M[i + j * ldm] = 0.0;
+}
+
 __global__ void copy2d_kernel(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
                               double* __restrict__ dst, int64_t ldd) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -593,18 +713,23 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 }  // namespace
 
 size_t sample_qrcp_flag_words() { return 128; }
+int sample_rows_padded(int l) { return l <= 32 ? 32 : l <= 64 ? 64 : l <= 80 ? 80 : l <= 128 ? 128 : -1; }
+size_t sample_qrcp_cand_elems() { return 2 * (size_t)SQ_LCAP * SQ_T; }
+size_t sample_qrcp_idx_elems() { return 2 * 2 * (size_t)SQ_T; }
+size_t sample_qrcp_theta_elems() { return 2 * (size_t)SQ_MAXP; }
 
-int launch_sample_qrcp(hipStream_t s, double* Bt, int64_t ldbt, int l, int64_t nJ, int bJ, int* piv, int* info,
+int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ, int bJ, int* piv, int* info,
                        int info_base, const SampleQrcpWork& w) {
   if (bJ <= 0 || nJ <= 0) return 0;
-  if (bJ > SQ_BMAX) return -5;
+  if (bJ > SQ_BMAX || bJ > nJ) return -5;
+  if (lds != sample_rows_padded(l)) return -6;
   SqParams a;
-  a.Bt = Bt; a.ldbt = ldbt; a.l = l; a.nJ = nJ; a.bJ = bJ; a.piv = piv; a.info = info; a.info_base = info_base;
-  a.refl = w.refl; a.rtau = w.rtau; a.cand_pos = w.cand_pos; a.theta = w.theta; a.flags = w.flags; a.err = w.err;
-  if (l <= 32) return launch_sq<32, 4>(s, a);
-  if (l <= 64) return launch_sq<64, 4>(s, a);
-  if (l <= 80) return launch_sq<80, 4>(s, a);
-  if (l <= 128) return launch_sq<128, 8>(s, a);
+  a.S = S; a.l = l; a.nJ = nJ; a.bJ = bJ; a.piv = piv; a.info = info; a.info_base = info_base;
+  a.cand = w.cand; a.cand_idx = w.cand_idx; a.theta = w.theta; a.flags = w.flags; a.err = w.err;
+  if (l <= 32) return launch_sq<32>(s, a);
+  if (l <= 64) return launch_sq<64>(s, a);
+  if (l <= 80) return launch_sq<80>(s, a);
+  if (l <= 128) return launch_sq<128>(s, a);
   return -7;
 }
 
@@ -640,6 +765,13 @@ int launch_w11(hipStream_t s, int bJ, const double* S, int64_t srs, int64_t scs,
 int launch_fill(hipStream_t s, void* p, size_t words) {
   if (!words) return 0;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (unsigned*)p, words);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_zero_rows(hipStream_t s, int64_t r0, int64_t r1, int64_t cols, double* M, int64_t ldm) {
+  if (r1 <= r0 || cols <= 0) return 0;
+  hipLaunchKernelGGL(zero_rows_kernel, dim3(blocks_for((r1 - r0) * cols, 256)), dim3(256), 0, s, r0, r1, cols, M, ldm);
   RQ_HIP(hipGetLastError());
   return 0;
 }
