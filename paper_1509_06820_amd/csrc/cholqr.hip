@@ -36,7 +36,7 @@ namespace rq {
 
 namespace {
 
-constexpr int SM_T = 1024;   // threads of the small-matrix kernels
+constexpr int SM_T = 256;    // threads of the small-matrix kernels (thread = row r, column group cg)
 constexpr int SM_N = 64;     // matrices are padded to 64 x 64
 constexpr int SM_LD = 65;    // LDS leading dimension (odd: no bank conflicts along columns)
 
@@ -47,9 +47,14 @@ constexpr int ST_CHOL1 = 1, ST_CHOL2 = 2, ST_ORTH = 4, ST_PIVOT = 8, ST_S11 = 16
 // Matrices live in LDS as M[i + j * SM_LD] (column-major), 64 x 64, padded
 // with the identity beyond the active size b.
 
-__device__ void sm_load(double* M, const double* G, int64_t rs, int64_t cs, int b, bool upper_only) {
-  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
-    const int i = e % SM_N, j = e / SM_N;
+// Element loops map thread t to row t & 63 and columns (t >> 6) + 4q: no
+// integer division in the step loops.
+__device__ __forceinline__ int sm_r() { return threadIdx.x & 63; }
+__device__ __forceinline__ int sm_cg() { return threadIdx.x >> 6; }
+
+__device__ __forceinline__ void sm_load(double* M, const double* G, int64_t rs, int64_t cs, int b, bool upper_only) {
+  const int i = sm_r();
+  for (int j = sm_cg(); j < SM_N; j += SM_T / SM_N) {
     double v;
     if (i < b && j < b) v = (upper_only && i > j) ? 0.0 : G[(int64_t)i * rs + (int64_t)j * cs];
     else v = (i == j) ? 1.0 : 0.0;
@@ -57,97 +62,194 @@ __device__ void sm_load(double* M, const double* G, int64_t rs, int64_t cs, int 
   }
 }
 
-__device__ void sm_store(const double* M, double* G, int64_t ld, int b) {
-  for (int e = threadIdx.x; e < b * b; e += SM_T) {
-    const int i = e % b, j = e / b;
-    G[i + (int64_t)j * ld] = M[i + j * SM_LD];
-  }
+__device__ __forceinline__ void sm_store(const double* M, double* G, int64_t ld, int b) {
+  const int i = sm_r();
+  if (i < b)
+    for (int j = sm_cg(); j < b; j += SM_T / SM_N) G[i + (int64_t)j * ld] = M[i + j * SM_LD];
 }
 
-// In-place Cholesky G = R^T R (R upper).  Returns false (uniformly) if a
-// pivot is not positive.
-__device__ bool sm_chol(double* G, int* flag) {
+// ---------------------------------------------------------------- one-wave factorisations
+// The Cholesky and the sign-choosing LU are chains of 64 dependent steps.
+// They run in wave 0 alone, without workgroup barriers: lane j holds column j
+// in registers (the step loop is unrolled, so every register index is a
+// constant), and a value another lane holds is read with v_readlane into
+// scalar registers.  The other waves wait at the closing barrier.
+
+__device__ __forceinline__ double lane_val(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// In-place Cholesky G = R^T R of the upper triangle of G (64 x 64, LDS;
+// R upper, lower part zeroed).  Returns false (uniformly) if a pivot is not
+// positive.
+__device__ __forceinline__ bool sm_chol(double* G, int* flag) {
   if (threadIdx.x == 0) *flag = 0;
   __syncthreads();
-  for (int k = 0; k < SM_N; ++k) {
-    if (threadIdx.x == 0) {
-      const double d = G[k + k * SM_LD];
-      if (!(d > 0.0)) *flag = 1;
-      G[k + k * SM_LD] = (d > 0.0) ? sqrt(d) : 1.0;
+  if (threadIdx.x < SM_N) {
+    const int j = threadIdx.x;
+    double g[SM_N];
+#pragma unroll
+    for (int i = 0; i < SM_N; ++i) g[i] = (i <= j) ? G[i + j * SM_LD] : 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < SM_N; ++k) {
+      const double d = lane_val(g[k], k);
+      ok = ok && (d > 0.0);
+      const double dd = (d > 0.0) ? d : 1.0;
+      const double sd = sqrt(dd), isd = 1.0 / sd;
+      const double rkj = (j > k) ? g[k] * isd : ((j == k) ? sd : 0.0);  // R(k, j)
+      g[k] = rkj;
+#pragma unroll
+      for (int i = k + 1; i < SM_N; ++i) g[i] = fma(-lane_val(rkj, i), rkj, g[i]);
     }
-    __syncthreads();
-    const double r = G[k + k * SM_LD];
-    for (int j = k + 1 + threadIdx.x; j < SM_N; j += SM_T) G[k + j * SM_LD] /= r;
-    __syncthreads();
-    // trailing update of the upper triangle: G(i, j) -= R(k, i) R(k, j), k < i <= j
-    const int m = SM_N - k - 1;
-    for (int e = threadIdx.x; e < m * m; e += SM_T) {
-      const int i = k + 1 + e % m, j = k + 1 + e / m;
-      if (i <= j) G[i + j * SM_LD] -= G[k + i * SM_LD] * G[k + j * SM_LD];
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
-    const int i = e % SM_N, j = e / SM_N;
-    if (i > j) G[i + j * SM_LD] = 0.0;
+#pragma unroll
+    for (int i = 0; i < SM_N; ++i) G[i + j * SM_LD] = (i <= j) ? g[i] : 0.0;
+    if (j == 0 && !ok) *flag = 1;
   }
   __syncthreads();
   return *flag == 0;
+}
+
+// LU without pivoting of E - Q S on the top b x b block (in A, 64 x 64 LDS,
+// identity padded), with the sign choice of Householder reconstruction: at
+// step i with c0 = Q'(i, i), S_ii = -sign(c0) (sign(0) = +1), U(i, i) =
+// 1 + |c0|, L(r, i) = -S_ii Q'(r, i) / U(i, i), Q'(r, c) -= L(r, i) Q'(i, c).
+// The last column of a square panel (i = mJ - 1) has no row below: there
+// S_ii = sign(c0) and U(i, i) = 0.  On return A holds L (unit, below the
+// diagonal), U(i, i) on the diagonal and Q' above it; sgn[i] = S_ii.
+__device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_t mJ) {
+  if (threadIdx.x < SM_N) {
+    const int j = threadIdx.x;
+    double a[SM_N];
+#pragma unroll
+    for (int i = 0; i < SM_N; ++i) a[i] = A[i + j * SM_LD];
+#pragma unroll
+    for (int i = 0; i < SM_N; ++i) {
+      if (i < b) {
+        const double c0 = lane_val(a[i], i);
+        if (i == mJ - 1) {
+          if (j == 0) sgn[i] = (c0 >= 0.0) ? 1.0 : -1.0;
+          if (j == i) a[i] = 0.0;
+        } else {
+          const double sg = (c0 >= 0.0) ? -1.0 : 1.0;
+          const double piv = 1.0 + fabs(c0);
+          const double f = -sg / piv;
+          // column i (lane i) becomes L(:, i); every lane right of it takes
+          // the rank-1 update with its own row-i entry
+          const double aij = a[i];
+#pragma unroll
+          for (int r = i + 1; r < SM_N; ++r) {
+            const double l = lane_val(a[r], i) * f;
+            a[r] = (j == i) ? l : ((j > i) ? fma(-l, aij, a[r]) : a[r]);
+          }
+          if (j == i) a[i] = piv;
+          if (j == 0) sgn[i] = sg;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SM_N; ++i) A[i + j * SM_LD] = a[i];
+  }
+  __syncthreads();
+}
+
+// Products of LDS matrices on the matrix cores: for each of nb batches
+// (pointers advanced by boff), the M x N result of op(A) B (K inner, M and N
+// multiples of 16, K of 4) is handed element by element to epi(i, j, value).
+// TA: op(A)(i, k) = A[k + i * SM_LD], else A[i + k * SM_LD].  16 x 16 tiles
+// are dealt to the waves in turn; the operand layout follows the gemm
+// kernel's (v_mfma_f64_16x16x4 with swapped operands, lane l / register r
+// holding element (l % 16, 4r + l / 16) of the tile).  No barrier inside:
+// the caller synchronises before reading what epi wrote.
+template <bool TA, class Epi>
+__device__ __forceinline__ void sm_mm(const double* A, const double* B, int M, int N, int K, int nb, int boff,
+                                      Epi epi) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tm = M >> 4, tn = N >> 4, per = tm * tn;
+  for (int t = w; t < nb * per; t += SM_T / 64) {
+    const int bi = t / per, tt = t - bi * per;
+    const int i0 = (tt % tm) * 16, j0 = (tt / tm) * 16;
+    const double* Ab = A + bi * boff;
+    const double* Bb = B + bi * boff;
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    const int ia = i0 + (lane & 15), jb = j0 + (lane & 15);
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int ka = k0 + (lane >> 4);
+      const double af = TA ? Ab[ka + ia * SM_LD] : Ab[ia + ka * SM_LD];
+      const double bf = Bb[ka + jb * SM_LD];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bf, af, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) epi(bi, ia, j0 + 4 * r + (lane >> 4), acc[r]);
+  }
 }
 
 // Inverse of an upper-triangular matrix by recursive doubling:
 // inv([A B; 0 C]) = [inv(A), -inv(A) B inv(C); 0, inv(C)], block size 1, 2, ..., 32.
-// R and Ri must differ; W is scratch (SM_N * SM_LD).  Returns false if a
-// diagonal entry is zero.
-__device__ bool sm_tri_inv(const double* R, double* Ri, double* W, int* flag) {
+// Blocks of 1..8 by scalar loops, 16 and 32 on the matrix cores.  R and Ri
+// must differ; W is scratch (SM_N * SM_LD).  Returns false if a diagonal
+// entry is zero.
+__device__ __forceinline__ bool sm_tri_inv(const double* R, double* Ri, double* W, int* flag) {
+  const int r = sm_r(), cg = sm_cg();
   if (threadIdx.x == 0) *flag = 0;
   __syncthreads();
-  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
-    const int i = e % SM_N, j = e / SM_N;
+  for (int c = cg; c < SM_N; c += SM_T / SM_N) {
     double v = 0.0;
-    if (i == j) {
-      const double d = R[i + i * SM_LD];
+    if (r == c) {
+      const double d = R[r + r * SM_LD];
       if (d == 0.0) *flag = 1;
       v = (d != 0.0) ? 1.0 / d : 0.0;
     }
-    Ri[i + j * SM_LD] = v;
+    Ri[r + c * SM_LD] = v;
   }
   __syncthreads();
-  for (int s = 1; s < SM_N; s <<= 1) {
-    // W = B inv(C) for every pair of diagonal blocks of size s
-    const int npair = SM_N / (2 * s);
-    for (int e = threadIdx.x; e < npair * s * s; e += SM_T) {
-      const int q = e / (s * s), r = e % (s * s);
-      const int i = r % s, j = r / s;
-      const int i0 = 2 * s * q, c0 = i0 + s;
+#pragma unroll
+  for (int ls = 0; ls < 4; ++ls) {
+    constexpr int dummy = 0;
+    (void)dummy;
+    const int sz = 1 << ls;
+    const int nel = (SM_N / 2) * sz;  // pairs * sz * sz
+    for (int e = threadIdx.x; e < nel; e += SM_T) {
+      const int i = e & (sz - 1), j = (e >> ls) & (sz - 1), q = e >> (2 * ls);
+      const int i0 = 2 * sz * q, c0 = i0 + sz;
       double acc = 0.0;
-      for (int k = 0; k <= j; ++k) acc += R[(i0 + i) + (c0 + k) * SM_LD] * Ri[(c0 + k) + (c0 + j) * SM_LD];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k <= j && k < sz) acc += R[(i0 + i) + (c0 + k) * SM_LD] * Ri[(c0 + k) + (c0 + j) * SM_LD];
       W[(i0 + i) + (c0 + j) * SM_LD] = acc;
     }
     __syncthreads();
-    // off-diagonal block of the inverse: -inv(A) W
-    for (int e = threadIdx.x; e < npair * s * s; e += SM_T) {
-      const int q = e / (s * s), r = e % (s * s);
-      const int i = r % s, j = r / s;
-      const int i0 = 2 * s * q, c0 = i0 + s;
+    for (int e = threadIdx.x; e < nel; e += SM_T) {
+      const int i = e & (sz - 1), j = (e >> ls) & (sz - 1), q = e >> (2 * ls);
+      const int i0 = 2 * sz * q, c0 = i0 + sz;
       double acc = 0.0;
-      for (int k = i; k < s; ++k) acc += Ri[(i0 + i) + (i0 + k) * SM_LD] * W[(i0 + k) + (c0 + j) * SM_LD];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k >= i && k < sz) acc += Ri[(i0 + i) + (i0 + k) * SM_LD] * W[(i0 + k) + (c0 + j) * SM_LD];
       Ri[(i0 + i) + (c0 + j) * SM_LD] = -acc;
     }
+    __syncthreads();
+  }
+  for (int sz = 16; sz <= 32; sz <<= 1) {
+    const int nb = SM_N / (2 * sz), boff = 2 * sz * (1 + SM_LD);
+    // W = B inv(C) for each pair of diagonal blocks
+    sm_mm<false>(R + sz * SM_LD, Ri + sz * (1 + SM_LD), sz, sz, sz, nb, boff,
+                 [&](int bi, int i, int j, double v) { W[bi * boff + i + (sz + j) * SM_LD] = v; });
+    __syncthreads();
+    // off-diagonal block = -inv(A) W
+    sm_mm<false>(Ri, W + sz * SM_LD, sz, sz, sz, nb, boff,
+                 [&](int bi, int i, int j, double v) { Ri[bi * boff + i + (sz + j) * SM_LD] = -v; });
     __syncthreads();
   }
   return *flag == 0;
 }
 
-// C = A B for upper-triangular A, B (C upper).
-__device__ void sm_mul_uu(const double* A, const double* B, double* C) {
-  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
-    const int i = e % SM_N, j = e / SM_N;
-    double acc = 0.0;
-    if (i <= j)
-      for (int k = i; k <= j; ++k) acc += A[i + k * SM_LD] * B[k + j * SM_LD];
-    C[i + j * SM_LD] = acc;
-  }
+// C = A B (all 64 x 64 in LDS, C distinct from A and B).
+__device__ void sm_mul(const double* A, const double* B, double* C) {
+  sm_mm<false>(A, B, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) { C[i + j * SM_LD] = v; });
   __syncthreads();
 }
 
@@ -238,14 +340,12 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
     if (threadIdx.x == 0) atomicOr(st, ST_CHOL2);
     return;
   }
-  // A = Q_top = Q1(0:b, 0:b) R2^-1 (full b x b)
-  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
-    const int i = e % SM_N, j = e / SM_N;
-    double acc = 0.0;
-    if (i < b && j < b)
-      for (int k = 0; k <= j; ++k) acc += Q1[i + (int64_t)k * ldq] * B[k + j * SM_LD];
-    A[i + j * SM_LD] = acc;
-  }
+  // A = Q_top = Q1(0:b, 0:b) R2^-1 (full b x b); Q1's top block is staged
+  // in C first so the products read LDS only
+  sm_load(C, Q1, 1, ldq, b, false);
+  __syncthreads();
+  sm_mm<false>(C, B, SM_N, SM_N, SM_N, 1, 0,
+               [&](int, int i, int j, double v) { A[i + j * SM_LD] = (i < b && j < b) ? v : 0.0; });
   // D = H (full b x b)
   for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
     const int i = e % SM_N, j = e / SM_N;
@@ -258,29 +358,7 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
   // A column with no row below its diagonal (the last one of a square panel)
   // is left alone by Householder QR (tau = 0): there S_ii = sign(c_0) and the
   // pivot is 0.
-  for (int i = 0; i < b; ++i) {
-    if (threadIdx.x == 0) {
-      const double c0 = A[i + i * SM_LD];
-      if (i == mJ - 1) {
-        sgn[i] = (c0 >= 0.0) ? 1.0 : -1.0;
-        A[i + i * SM_LD] = 0.0;
-      } else {
-        sgn[i] = (c0 >= 0.0) ? -1.0 : 1.0;
-        A[i + i * SM_LD] = 1.0 + fabs(c0);  // pivot (= U(i, i))
-      }
-    }
-    __syncthreads();
-    const double s = sgn[i], piv = A[i + i * SM_LD];
-    if (i == mJ - 1) break;  // last step, nothing below
-    for (int r = i + 1 + threadIdx.x; r < b; r += SM_T) A[r + i * SM_LD] = -s * A[r + i * SM_LD] / piv;
-    __syncthreads();
-    const int m = b - i - 1;
-    for (int e = threadIdx.x; e < m * m; e += SM_T) {
-      const int r = i + 1 + e % m, j = i + 1 + e / m;
-      A[r + j * SM_LD] -= A[r + i * SM_LD] * A[i + j * SM_LD];
-    }
-    __syncthreads();
-  }
+  sm_lu_sign(A, sgn, b, mJ);
   // C = U (U(i, j) = -S_jj Q'(i, j) above the diagonal, pivots on it);
   // A keeps L1 below the diagonal.  Padding stays identity.
   for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
@@ -292,19 +370,18 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
   }
   // outputs of the top block: R(i, j) = S_ii sum_k R2^-1(k, i) H(k, j) on and
   // above the diagonal, Y1 below it
-  for (int e = threadIdx.x; e < b * b; e += SM_T) {
-    const int i = e % b, j = e / b;
-    if (i <= j) {
-      double acc = 0.0;
-      for (int k = 0; k <= i; ++k) acc += B[k + i * SM_LD] * D[k + j * SM_LD];
-      P[i + (int64_t)j * ldp] = sgn[i] * acc;
-      Y[i + (int64_t)j * ldy] = (i == j) ? 1.0 : 0.0;
-    } else {
-      const double y = A[i + j * SM_LD];
-      P[i + (int64_t)j * ldp] = y;
-      Y[i + (int64_t)j * ldy] = y;
+  sm_mm<true>(B, D, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
+    if (i < b && j < b) {
+      if (i <= j) {
+        P[i + (int64_t)j * ldp] = sgn[i] * v;
+        Y[i + (int64_t)j * ldy] = (i == j) ? 1.0 : 0.0;
+      } else {
+        const double y = A[i + j * SM_LD];
+        P[i + (int64_t)j * ldp] = y;
+        Y[i + (int64_t)j * ldy] = y;
+      }
     }
-  }
+  });
   __syncthreads();
   // B = -R2^-1 S (columns scaled), kept in the global M3 scratch meanwhile
   for (int e = threadIdx.x; e < b * b; e += SM_T) {
@@ -323,8 +400,10 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
   __syncthreads();
   sm_tri_inv(D, A, B, &flag);   // A = inv(Y1^T) (unit diagonal: never singular)
   // T = U inv(Y1^T)
-  sm_mul_uu(C, A, D);
-  sm_store(D, T, b, b);
+  sm_mm<false>(C, A, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
+    if (i < b && j < b) T[i + (int64_t)j * b] = v;
+  });
+  __syncthreads();
   if (mJ == b) return;  // no rows below the top block
   // M3 = -R2^-1 S inv(U): A = inv(U) (D scratch), B = -R2^-1 S
   if (!sm_tri_inv(C, A, D, &flag)) {  // pivots are >= 1 here: cannot happen
@@ -333,8 +412,41 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
   }
   sm_load(B, M3, 1, b, b, true);
   __syncthreads();
-  sm_mul_uu(B, A, D);
-  sm_store(D, M3, b, b);
+  sm_mm<false>(B, A, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
+    if (i < b && j < b) M3[i + (int64_t)j * b] = v;
+  });
+}
+
+// W11 = S11 R11^-1 of the sample update (eq. update1), b x b upper
+// triangular.  A zero pivot R11(j, j) gives a zero column j of W11 and takes
+// row j of R11 out of the later columns; that is W11 = S~ R~^-1 with column j
+// of S~ zeroed and row and column j of R~ replaced by the unit vector.
+__global__ void __launch_bounds__(SM_T) w11_kernel(int b, const double* S, int64_t srs, int64_t scs, const double* R,
+                                                   int64_t ldr, double* W) {
+  extern __shared__ __align__(16) double sm[];
+  __shared__ int flag;
+  double* Rt = sm;
+  double* Ri = sm + SM_N * SM_LD;
+  double* Wk = sm + 2 * SM_N * SM_LD;
+  double* St = sm + 3 * SM_N * SM_LD;
+  __shared__ int zero_piv[SM_N];
+  sm_load(Rt, R, 1, ldr, b, true);
+  sm_load(St, S, srs, scs, b, true);
+  __syncthreads();
+  if (threadIdx.x < SM_N) zero_piv[threadIdx.x] = Rt[threadIdx.x + threadIdx.x * SM_LD] == 0.0;
+  __syncthreads();
+  {
+    const int r = sm_r();
+    for (int c = sm_cg(); c < SM_N; c += SM_T / SM_N) {
+      if (zero_piv[c]) St[r + c * SM_LD] = 0.0;
+      if (zero_piv[c] || zero_piv[r]) Rt[r + c * SM_LD] = (r == c) ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  sm_tri_inv(Rt, Ri, Wk, &flag);
+  sm_mm<false>(St, Ri, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
+    if (i < b && j < b) W[i + (int64_t)j * b] = (i <= j) ? v : 0.0;
+  });
 }
 
 // Copy Y(b:mJ, :) into the panel storage below the top block, unless the
@@ -357,6 +469,18 @@ int set_lds(const void* fn) {
 }
 
 }  // namespace
+
+int launch_w11(hipStream_t s, int bJ, const double* S, int64_t srs, int64_t scs, const double* R, int64_t ldr,
+               double* W) {
+  static bool init = false;
+  if (!init) {
+    RQ_TRY_RAW(set_lds((const void*)w11_kernel));
+    init = true;
+  }
+  hipLaunchKernelGGL(w11_kernel, dim3(1), dim3(SM_T), SM_LDS, s, bJ, S, srs, scs, R, ldr, W);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
 
 size_t cholqr_scratch_elems(int64_t mmax, int bmax) {
   // Q1 (mmax x b), G1, G2, H, M0, M1, M3 (b x b each)

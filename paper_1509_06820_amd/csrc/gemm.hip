@@ -153,6 +153,33 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(int64_t M, int64_t N
   *c = v;
 }
 
+// Same sum for many splits: a workgroup reduces 16 consecutive outputs; its
+// 16 thread groups each add every 16th partial (128-byte coalesced reads),
+// then the 16 group sums are added in LDS in a fixed order.
+__global__ void __launch_bounds__(256) splitk_reduce_many_kernel(int64_t M, int64_t N, int splits,
+                                                                 const double* __restrict__ P, double alpha,
+                                                                 double beta, double* __restrict__ C, int64_t ldc) {
+  __shared__ double part[16][17];
+  const int64_t total = M * N;
+  const int ol = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t o = (int64_t)blockIdx.x * 16 + ol;
+  double s = 0.0;
+  if (o < total)
+    for (int z = g; z < splits; z += 16) s += P[(int64_t)z * total + o];
+  part[g][ol] = s;
+  __syncthreads();
+  if (threadIdx.x < 16 && o < total) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += part[q][ol];
+    const int64_t j = o / M, i = o - j * M;
+    double v = alpha * acc;
+    double* c = C + i + j * ldc;
+    if (beta != 0.0) v += beta * (*c);
+    *c = v;
+  }
+}
+
 template <int BM, int BN, int BK, int WM, int WN>
 int launch_tiles(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                  int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int splits,
@@ -177,10 +204,23 @@ int launch_tiles(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t 
 
 }  // namespace
 
+// Small outputs with a long reduction (Gram matrices of tall panels, b x n
+// products with n short) are split along K: "gram mode" for outputs of at
+// most 64 x 128 (up to 256 splits of >= 32 rows), the general split for
+// short-and-wide outputs (up to 8 splits).
+constexpr int GRAM_MAXS = 256;
+constexpr int64_t GRAM_MINK = 32;
+
+bool gram_mode(int64_t M, int64_t N, int64_t K) { return M <= 64 && N <= 128 && K >= 256; }
+
 size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K) {
-  // split-K is used for short-and-wide outputs with a long reduction
-  if (M <= 128 && K >= 1024) return (size_t)M * (size_t)N * 8;
-  return 0;
+  size_t e = 0;
+  if (M <= 128 && K >= 1024) e = (size_t)M * (size_t)N * 8;
+  if (gram_mode(M, N, K)) {
+    const int64_t s = std::min<int64_t>(GRAM_MAXS, (K + GRAM_MINK - 1) / GRAM_MINK);
+    e = std::max(e, (size_t)M * (size_t)N * (size_t)s);
+  }
+  return e;
 }
 
 int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
@@ -195,23 +235,39 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
   constexpr int BM = 64, BN = 64, BK = 16;
   const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   int splits = 1;
-  if (scratch && M <= 128 && K >= 1024) {
+  int64_t kchunk = K;
+  bool many = false;
+  if (scratch && gram_mode(M, N, K)) {
+    kchunk = std::max<int64_t>(GRAM_MINK, (K + GRAM_MAXS - 1) / GRAM_MAXS);
+    kchunk = (kchunk + BK - 1) / BK * BK;
+    splits = (int)((K + kchunk - 1) / kchunk);
+    while (splits > 1 && (size_t)splits * (size_t)M * (size_t)N > scratch_elems) {
+      kchunk *= 2;
+      splits = (int)((K + kchunk - 1) / kchunk);
+    }
+    many = true;
+  } else if (scratch && M <= 128 && K >= 1024) {
     // aim for >= 1024 workgroups, at least 512 reduction steps per split
     int64_t want = (1024 + tiles - 1) / tiles;
     int64_t maxs = K / 512;
     splits = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, 8}));
     while (splits > 1 && (size_t)splits * (size_t)M * (size_t)N > scratch_elems) --splits;
+    kchunk = (K + splits - 1) / splits;
+    kchunk = (kchunk + BK - 1) / BK * BK;
   }
   if (splits == 1)
     return launch_tiles<BM, BN, BK, 2, 2>(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 1, K, 0);
-  int64_t kchunk = (K + splits - 1) / splits;
-  kchunk = (kchunk + BK - 1) / BK * BK;
   int rc = launch_tiles<BM, BN, BK, 2, 2>(s, ta, tb, M, N, K, 1.0, A, lda, B, ldb, 0.0, scratch, M, splits, kchunk,
                                           M * N);
   if (rc) return rc;
   const int64_t total = M * N;
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, M, N, splits,
-                     (const double*)scratch, alpha, beta, C, ldc);
+  if (many) {
+    hipLaunchKernelGGL(splitk_reduce_many_kernel, dim3((unsigned)((total + 15) / 16)), dim3(256), 0, s, M, N, splits,
+                       (const double*)scratch, alpha, beta, C, ldc);
+  } else {
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, M, N, splits,
+                       (const double*)scratch, alpha, beta, C, ldc);
+  }
   RQ_HIP(hipGetLastError());
   return 0;
 }

@@ -635,34 +635,6 @@ __global__ void __launch_bounds__(256) larft_gated_kernel(int64_t mJ, int bJ, co
   for (int e = threadIdx.x; e < bJ * bJ; e += 256) T[e] = Ts[e];
 }
 
-// ------------------------------------------------------------------ W11
-// Row i of W solves W R = S: W(i, j) = (S(i, j) - sum_{i<=q<j} W(i,q) R(q,j)) / R(j,j),
-// with column j of W set to zero when R(j, j) == 0.
-__global__ void __launch_bounds__(64) w11_kernel(int bJ, const double* __restrict__ S, int64_t srs, int64_t scs,
-                                                 const double* __restrict__ R, int64_t ldr, double* __restrict__ W) {
-  __shared__ double Rs[64 * 64];
-  __shared__ double Ws[64 * 65];
-  const int i = threadIdx.x;
-  for (int e = i; e < bJ * bJ; e += 64) {
-    const int rr = e % bJ, cc = e / bJ;
-    Rs[e] = (rr <= cc) ? R[rr + cc * ldr] : 0.0;
-  }
-  __syncthreads();
-  if (i < bJ) {
-    for (int j = 0; j < bJ; ++j) {
-      double v = 0.0;
-      const double d = Rs[j + j * bJ];
-      if (j >= i && d != 0.0) {
-        double acc = S[(int64_t)i * srs + (int64_t)j * scs];
-        for (int q = i; q < j; ++q) acc -= Ws[i + q * 65] * Rs[q + j * bJ];
-        v = acc / d;
-      }
-      Ws[i + j * 65] = v;
-    }
-    for (int j = 0; j < bJ; ++j) W[i + j * bJ] = Ws[i + j * 65];
-  }
-}
-
 // ------------------------------------------------------------------ utilities
 __global__ void fill_kernel(unsigned* p, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -751,13 +723,6 @@ int launch_larft(hipStream_t s, int bJ, const double* G, const double* tau, doub
 int launch_larft_gated(hipStream_t s, int64_t mJ, int bJ, const double* Y, int64_t ldy, const double* tau, double* T,
                        const int* gate) {
   hipLaunchKernelGGL(larft_gated_kernel, dim3(1), dim3(256), 0, s, mJ, bJ, Y, ldy, tau, T, gate);
-  RQ_HIP(hipGetLastError());
-  return 0;
-}
-
-int launch_w11(hipStream_t s, int bJ, const double* S, int64_t srs, int64_t scs, const double* R, int64_t ldr,
-               double* W) {
-  hipLaunchKernelGGL(w11_kernel, dim3(1), dim3(64), 0, s, bJ, S, srs, scs, R, ldr, W);
   RQ_HIP(hipGetLastError());
   return 0;
 }
