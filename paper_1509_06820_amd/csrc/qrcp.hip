@@ -38,32 +38,57 @@ struct SqParams {
 
 template <int LMAX>
 struct SqLds {
-  // Reflector of step t in raw form: vraw[t] is the pivot column as it was
-  // when chosen; with scal = 1 / (alpha - beta) the Householder vector is
-  // v = e_t + scal * (rows > t of vraw[t]).  Rows < t are the pivot's R
-  // entries, so vraw also yields the final sample column (beta on row t).
-  double vraw[SQ_BMAX * LMAX];
-  double wcol[2][SQ_T / WAVE][LMAX];  // each wave's best candidate column (double buffered by step)
-  double wsc[2][SQ_T / WAVE][4];      // its tau, scal, beta
+  double vlog[SQ_BMAX * LMAX];        // reflector of step t (zero above row t, one at row t)
+  double slog[SQ_BMAX * LMAX];        // final sample column of pivot t
+  double wv[2][SQ_T / WAVE][LMAX];    // each wave's best candidate column (double buffered by step)
+  double wsc[2][SQ_T / WAVE][4];      // its tau, beta, 1 / (alpha - beta)
+  // Row masks: ge0[LMAX + d] = (d >= 0), eq0[LMAX + d] = (d == 0); ge1, eq1
+  // are the same tables shifted by one element, so that the mask of any
+  // row offset can be read with 16-byte aligned accesses.
+  double ge0[2 * LMAX], ge1[2 * LMAX], eq0[2 * LMAX], eq1[2 * LMAX];
   double taus[SQ_BMAX];
-  double scals[SQ_BMAX];
-  double betas[SQ_BMAX];
-  double kv[SQ_T];                    // sort keys: value, position, lane
+  double kv[SQ_T];                    // ranking keys sorted per wave: trailing norm, position
   int kp[SQ_T];
-  int kl[SQ_T];
-  int rank_of[SQ_T];
+  int rk[SQ_T];                       // rank of each lane's column
   int plog[SQ_BMAX];                  // position of the pivot chosen at step t
   int pphys[SQ_BMAX];                 // its physical column
   double rv[2][SQ_T / WAVE];          // per-wave argmax
   int rp[2][SQ_T / WAVE];
   double theta;
   int bad;
+  int nvalid;
 };
+
+// m with m[r] = (r >= f) for 0 <= f <= LMAX, 16-byte aligned.
+template <int LMAX>
+__device__ __forceinline__ const double* mask_ge(const SqLds<LMAX>& L, int f) {
+  return ((LMAX - f) & 1) ? L.ge1 + (LMAX - f - 1) : L.ge0 + (LMAX - f);
+}
+// m with m[r] = (r == f).
+template <int LMAX>
+__device__ __forceinline__ const double* mask_eq(const SqLds<LMAX>& L, int f) {
+  return ((LMAX - f) & 1) ? L.eq1 + (LMAX - f - 1) : L.eq0 + (LMAX - f);
+}
 
 __device__ __forceinline__ double ranked(double nu) { return (nu != nu) ? -1.0 : nu; }
 
+// 1 / a for a > 0: hardware reciprocal estimate and two Newton steps
+// (within an ulp or so of the rounded quotient).
+__device__ __forceinline__ double rcp_nr(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(r, fma(-a, r, 1.0), r);
+  r = fma(r, fma(-a, r, 1.0), r);
+  return r;
+}
+
 __device__ __forceinline__ bool better(double v1, int p1, double v2, int p2) {
   return (v1 > v2) || (v1 == v2 && p1 < p2);
+}
+
+// The same test without short-circuit evaluation (both operands loaded and
+// compared unconditionally, no branch): 0 or 1.
+__device__ __forceinline__ int beats(double v1, int p1, double v2, int p2) {
+  return (int)(v1 > v2) | ((int)(v1 == v2) & (int)(p1 < p2));
 }
 
 // Values every thread reads from the same LDS word are uniform, but the
@@ -97,81 +122,62 @@ __device__ __forceinline__ const double* after(const double* p, double dep) {
   return p + z;
 }
 
-// x <- (I - tau v v^T) x for the reflector of step s given in raw form (xw,
-// scal; see SqLds::vraw).  Rows above s are untouched and the 8-row chunks
-// entirely above row s are skipped; s is uniform, so every branch is scalar.
-// With NORM, returns the squared norm of the updated rows > s.
-template <int LMAX, bool NORM>
-__device__ __forceinline__ double sq_apply(double (&x)[LMAX], const double* xw, double tau, double scal, int s) {
+// d = tau v^T x
+template <int LMAX>
+__device__ __forceinline__ double sq_dot(const double (&x)[LMAX], const double* v, double tau) {
   constexpr int NC = LMAX / 8;
-  const int k0 = s >> 3;
   double vb[3][8];
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  double xs = 0.0;
+  double d[4] = {0.0, 0.0, 0.0, 0.0};
+  lds_chunk(vb[0], v);
+  lds_chunk(vb[1], v + 8);
 #pragma unroll
-  for (int j = -2; j < NC; ++j) {
-    if (j >= 0 && j >= k0) {
-      if (j == k0) {
+  for (int k = 0; k < NC; ++k) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int r = 8 * j + i;
-          xs += (r == s) ? x[r] : 0.0;
-          acc[i & 3] += (r > s) ? vb[j % 3][i] * x[r] : 0.0;
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i & 3] = fma(vb[j % 3][i], x[8 * j + i], acc[i & 3]);
-      }
-    }
-    const int c = j + 2;
-    if (c < NC && c >= k0) lds_chunk(vb[c % 3], (j >= 0 && j >= k0 ? after(xw, acc[0]) : xw) + 8 * c);
+    for (int i = 0; i < 8; ++i) d[i & 3] = fma(vb[k % 3][i], x[8 * k + i], d[i & 3]);
+    if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v, d[0]) + 8 * (k + 2));
   }
-  const double d = tau * (xs + scal * ((acc[0] + acc[1]) + (acc[2] + acc[3])));
-  const double ds = d * scal;
-  const double* xw2 = after(xw, d);
-  double nrm[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int j = -2; j < NC; ++j) {
-    if (j >= 0 && j >= k0) {
-      if (j == k0) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int r = 8 * j + i;
-          const double upd = fma(-ds, vb[j % 3][i], x[r]);
-          x[r] = (r > s) ? upd : ((r == s) ? x[r] - d : x[r]);
-          if (NORM) nrm[i & 3] += (r > s) ? x[r] * x[r] : 0.0;
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int r = 8 * j + i;
-          x[r] = fma(-ds, vb[j % 3][i], x[r]);
-          if (NORM) nrm[i & 3] = fma(x[r], x[r], nrm[i & 3]);
-        }
-      }
-    }
-    const int c = j + 2;
-    if (c < NC && c >= k0) lds_chunk(vb[c % 3], (j >= 0 && j >= k0 ? after(xw2, x[8 * (j < 0 ? 0 : j)]) : xw2) + 8 * c);
-  }
-  return NORM ? (nrm[0] + nrm[1]) + (nrm[2] + nrm[3]) : 0.0;
+  return tau * ((d[0] + d[1]) + (d[2] + d[3]));
 }
 
-// Squared norm of rows >= from (uniform); whole chunks by branch, the chunk
-// holding row `from` row by row.
+// x <- x - d v
+template <int LMAX>
+__device__ __forceinline__ void sq_axpy(double (&x)[LMAX], const double* v, double d) {
+  constexpr int NC = LMAX / 8;
+  const double* v2 = after(v, d);
+  double vb[3][8];
+  lds_chunk(vb[0], v2);
+  lds_chunk(vb[1], v2 + 8);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[8 * k + i] = fma(-d, vb[k % 3][i], x[8 * k + i]);
+    if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v2, x[8 * k]) + 8 * (k + 2));
+  }
+}
+
+// x <- (I - tau v v^T) x; full rows, branch free (v is zero above its first row).
+template <int LMAX>
+__device__ __forceinline__ void sq_apply(double (&x)[LMAX], const double* v, double tau) {
+  sq_axpy<LMAX>(x, v, sq_dot<LMAX>(x, v, tau));
+}
+
+// Squared norm of rows >= from (uniform): whole 8-row chunks are taken or
+// skipped by scalar branch, only the chunk holding row `from` is masked row
+// by row (no LDS traffic).
 template <int LMAX>
 __device__ __forceinline__ double sq_norm2(const double (&x)[LMAX], int from) {
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  double n[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < LMAX / 8; ++k) {
     if (8 * k >= from) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) s[i & 3] = fma(x[8 * k + i], x[8 * k + i], s[i & 3]);
+      for (int i = 0; i < 8; ++i) n[i & 3] = fma(x[8 * k + i], x[8 * k + i], n[i & 3]);
     } else if (8 * k + 8 > from) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) s[i & 3] += (8 * k + i >= from) ? x[8 * k + i] * x[8 * k + i] : 0.0;
+      for (int i = 0; i < 8; ++i) n[i & 3] += (8 * k + i >= from) ? x[8 * k + i] * x[8 * k + i] : 0.0;
     }
   }
-  return (s[0] + s[1]) + (s[2] + s[3]);
+  return (n[0] + n[1]) + (n[2] + n[3]);
 }
 
 // x[t] for a uniform t.
@@ -240,31 +246,6 @@ __device__ __forceinline__ void wave_argmax_vp(double v, int p, double& bv, int&
   bp = best;
 }
 
-// Sort the SQ_T keys in LDS: larger value first, ties by lower position.
-template <int LMAX>
-__device__ void sq_sort(SqLds<LMAX>& L) {
-  for (int size = 2; size <= SQ_T; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const int t = threadIdx.x;
-      if (t < SQ_T / 2) {
-        const int lo = 2 * stride * (t / stride) + (t % stride);
-        const int hi = lo + stride;
-        const bool up = ((lo & size) == 0);
-        const double v1 = L.kv[lo], v2 = L.kv[hi];
-        const int p1 = L.kp[lo], p2 = L.kp[hi];
-        const bool swap = up ? better(v2, p2, v1, p1) : better(v1, p1, v2, p2);
-        if (swap) {
-          const int l1 = L.kl[lo];
-          L.kv[lo] = v2; L.kv[hi] = v1;
-          L.kp[lo] = p2; L.kp[hi] = p1;
-          L.kl[lo] = L.kl[hi]; L.kl[hi] = l1;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 // One pass over this workgroup's slab (one column per thread): apply the
 // reflectors of steps [a0, t0), write the column back (on the last pass, a
 // column whose position changed goes to its final position), and, if
@@ -290,7 +271,7 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
 #pragma unroll
     for (int r = 0; r < LMAX; ++r) x[r] = 0.0;
   }
-  for (int s = a0; s < t0; ++s) sq_apply<LMAX, false>(x, L.vraw + s * LMAX, uni(L.taus[s]), uni(L.scals[s]), s);
+  for (int s = a0; s < t0; ++s) sq_apply<LMAX>(x, L.vlog + s * LMAX, uni(L.taus[s]));
   const bool move = !select && pos_s != c;
   if (mine && (move || t0 > a0)) {
     double2* col = reinterpret_cast<double2*>(a.S + (move ? (int64_t)pos_s : c) * LMAX);
@@ -299,21 +280,66 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
   }
   if (!select) return;
   const double nu = mine ? sq_norm2<LMAX>(x, t0) : 0.0;
-  if (tid == 0) L.bad = 0;
-  L.kv[tid] = mine ? ranked(nu) : -INFINITY;
-  L.kp[tid] = mine ? pos_s : INT_MAX;
-  L.kl[tid] = tid;
-  L.rank_of[tid] = -1;
+  const double kv = mine ? ranked(nu) : -INFINITY;
+  const int kp = mine ? pos_s : INT_MAX;
+  if (tid == 0) { L.bad = 0; L.nvalid = SQ_T; }
+  // rank of this column among the slab: the number of columns that beat it
+  // (larger trailing norm, ties to the lower position); the K best become
+  // candidates and the one of rank K gives theta.  Each wave sorts its 64
+  // keys (bitonic network over lanes), then an entry's rank is its index in
+  // its wave plus, for each other wave, the length of that wave's sorted
+  // prefix that beats it (binary search in LDS).
+  {
+    const int lane = tid & (WAVE - 1), w = tid / WAVE;
+    double sv = kv;
+    int sp = kp, sl = tid;
+#pragma unroll
+    for (int size = 2; size <= WAVE; size <<= 1) {
+#pragma unroll
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const double ov = __shfl_xor(sv, stride, WAVE);
+        const int op = __shfl_xor(sp, stride, WAVE);
+        const int ol = __shfl_xor(sl, stride, WAVE);
+        // in a best-first run the lower lane of a pair keeps the better key,
+        // in a best-last run the worse one
+        const bool lower = (lane & stride) == 0;
+        const bool best_first = (lane & size) == 0;
+        const bool ob = beats(ov, op, sv, sp) != 0;
+        const bool take = (lower == best_first) ? ob : !ob && (ov != sv || op != sp);
+        if (take) { sv = ov; sp = op; sl = ol; }
+      }
+    }
+    L.kv[tid] = sv;
+    L.kp[tid] = sp;
+    __syncthreads();
+    if (mine && !(nu <= DBL_MAX)) L.bad = 1;
+    int rk = lane;
+#pragma unroll
+    for (int w2 = 0; w2 < SQ_T / WAVE; ++w2) {
+      if (w2 == w) continue;
+      // number of entries of wave w2 that beat (sv, sp): first index whose key does not
+      int lo = 0, hi = WAVE;
+#pragma unroll
+      for (int it = 0; it < 7; ++it) {
+        if (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          const int q = w2 * WAVE + mid;
+          if (beats(L.kv[q], L.kp[q], sv, sp)) lo = mid + 1;
+          else hi = mid;
+        }
+      }
+      rk += lo;
+    }
+    L.rk[sl] = rk;
+    if (sp == INT_MAX) atomicMin(&L.nvalid, rk);  // empty entries rank after all valid ones
+  }
   __syncthreads();
-  if (mine && !(nu <= DBL_MAX)) L.bad = 1;
-  sq_sort<LMAX>(L);
-  if (tid < a.K && L.kp[tid] != INT_MAX) L.rank_of[L.kl[tid]] = tid;
-  __syncthreads();
+  const int rank = L.rk[tid];
   if (L.bad && tid == 0 && a.info) atomicCAS(a.info, 0, a.info_base + t0 + 1);
-  const int rank = L.rank_of[tid];
+  const int nvalid = L.nvalid;  // min over empty entries of their rank, or SQ_T
   double* cb = a.cand + (size_t)buf * SQ_LCAP * SQ_T;
   int* ib = a.cand_idx + (size_t)buf * 2 * SQ_T;
-  if (rank >= 0) {
+  if (mine && rank < a.K) {
     const int slot = me * a.K + rank;
     double2* col = reinterpret_cast<double2*>(cb + (size_t)slot * LMAX);
 #pragma unroll
@@ -321,9 +347,9 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
     ib[slot] = pos_s;
     ib[SQ_T + slot] = (int)c;
   }
-  if (tid < a.K && L.kp[tid] == INT_MAX) ib[me * a.K + tid] = -1;
-  if (tid == 0)
-    a.theta[(size_t)buf * SQ_MAXP + me] = (a.K < SQ_T && L.kp[a.K] != INT_MAX) ? L.kv[a.K] : -INFINITY;
+  if (tid < a.K && tid >= nvalid) ib[me * a.K + tid] = -1;
+  if (mine && rank == a.K) a.theta[(size_t)buf * SQ_MAXP + me] = kv;
+  if (tid == 0 && a.K >= nvalid) a.theta[(size_t)buf * SQ_MAXP + me] = -INFINITY;
 }
 
 // Arrival barrier over the P workgroups: every workgroup adds one to the
@@ -359,24 +385,31 @@ __device__ bool sq_barrier(const SqParams& a, unsigned round) {
 // second exchange) for as long as the winner provably beats every column
 // left out: its trailing norm must exceed theta, the largest left-out norm at
 // the start of the round, which bounds the left-out norms later in the round
-// (they only shrink) -- with a relative margin of 1e-12 for rounding.  The
+// (they only shrink) -- with a relative margin of 1e-10 for rounding.  The
 // steps are the sequential ones of the algorithm: swap of positions t and p,
 // Householder reflector of the pivot column (LAPACK normalisation), update of
 // the remaining candidates.  Within a step, each wave's best candidate forms
-// its reflector and stores its column before the one barrier of the step, so
-// the winner's reflector is ready as soon as the winner is known.  Columns
-// are never moved during the rounds; each thread tracks the logical position
-// of its slab column.
+// its reflector and stores it before the one barrier of the step, so the
+// winner's reflector is ready as soon as the winner is known.  Columns are
+// never moved during the rounds; each thread tracks the logical position of
+// its slab column.
 template <int LMAX>
 __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
   extern __shared__ __align__(16) double smem[];
   SqLds<LMAX>& L = *reinterpret_cast<SqLds<LMAX>*>(smem);
   const int me = blockIdx.x, tid = threadIdx.x, wv_id = tid / WAVE;
   if (earlier_failure(a.err)) return;
+  for (int e = tid; e < 2 * LMAX; e += SQ_T) {
+    L.ge0[e] = (e >= LMAX) ? 1.0 : 0.0;
+    L.ge1[e] = (e + 1 >= LMAX) ? 1.0 : 0.0;
+    L.eq0[e] = (e == LMAX) ? 1.0 : 0.0;
+    L.eq1[e] = (e + 1 == LMAX) ? 1.0 : 0.0;
+  }
   const int64_t c_s = (int64_t)me * SQ_T + tid;
   int pos_s = (int)c_s;   // logical position of this thread's slab column
   bool sel_s = false;     // selected as a pivot
   int a0 = 0, t0 = 0;
+  __syncthreads();
   for (unsigned round = 1;; ++round) {
     const bool select = t0 < a.bJ;
     const int buf = round & 1;
@@ -414,10 +447,18 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
     }
     __syncthreads();
     const double theta = uni(L.theta);
-    const double bound = (theta > 0.0) ? theta * (1.0 + 1e-12) : theta;
+    const double bound = (theta > 0.0) ? theta * (1.0 + 1e-10) : theta;
 
-    int t = t0;
+    int t = t0, won = -1;
+    double beta_w = 0.0;
+    // trailing squared norm (rows >= t) and the pivot-row entry x[t].  The
+    // norm is downdated after each step (the reflector leaves the norm of
+    // rows >= t unchanged, so rows > t keep it minus the new row-t entry
+    // squared) and recomputed once it has fallen below a tenth of its last
+    // exact value, which bounds its relative error by about 64 eps * 10.
     double nu = active ? sq_norm2<LMAX>(x, t) : 0.0;
+    double nu_ref = nu;
+    double alpha = row_at<LMAX>(x, t);
     while (t < a.bJ) {
       t = uni(t);
       const int par = t & 1;
@@ -426,22 +467,34 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
       wave_argmax_vp(active ? ranked(nu) : -INFINITY, active ? pos : INT_MAX, v, p);
       if (active && pos == p) {
         // this wave's best candidate: Householder reflector of rows t..l-1
-        // (dlarfg normalisation), stored with the column in case it wins
-        const double alpha = row_at<LMAX>(x, t);
-        const double xn2 = sq_norm2<LMAX>(x, t + 1);
+        // (dlarfg normalisation; an exactly zero tail gives tau = 0); the
+        // column is stored raw and normalised below once the winner is known
+        const double xn2 = sq_norm2<LMAX>(x, t + 1);  // exact tail norm
         double tau = 0.0, beta = alpha, scal = 0.0;
         if (xn2 != 0.0) {
+          // beta = -sign(alpha) nrm, so with q = |alpha| + nrm (no
+          // cancellation): tau = (beta - alpha) / beta = q / nrm and
+          // 1 / (alpha - beta) = sign(alpha) / q -- two independent
+          // reciprocals instead of two dependent divisions
           const double nrm = sqrt(alpha * alpha + xn2);
-          beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau = (beta - alpha) / beta;
-          scal = 1.0 / (alpha - beta);
+          const double sg = (alpha >= 0.0) ? 1.0 : -1.0;
+          const double q = fabs(alpha) + nrm;
+          beta = -sg * nrm;
+          tau = q * rcp_nr(nrm);
+          scal = sg * rcp_nr(q);
         }
-        double2* dst = reinterpret_cast<double2*>(L.wcol[par][wv_id]);
+        // the reflector is zero above row t: only the chunks from row t on
+        // are stored
+        double2* dst = reinterpret_cast<double2*>(L.wv[par][wv_id]);
 #pragma unroll
-        for (int i = 0; i < LMAX / 2; ++i) dst[i] = make_double2(x[2 * i], x[2 * i + 1]);
+        for (int k = 0; k < LMAX / 8; ++k)
+          if (8 * k + 8 > t) {
+#pragma unroll
+            for (int i = 4 * k; i < 4 * k + 4; ++i) dst[i] = make_double2(x[2 * i], x[2 * i + 1]);
+          }
         L.wsc[par][wv_id][0] = tau;
-        L.wsc[par][wv_id][1] = scal;
-        L.wsc[par][wv_id][2] = beta;
+        L.wsc[par][wv_id][1] = beta;
+        L.wsc[par][wv_id][2] = scal;
       }
       if ((tid & (WAVE - 1)) == 0) { L.rv[par][wv_id] = v; L.rp[par][wv_id] = p; }
       __syncthreads();
@@ -456,26 +509,49 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
       }
       if ((t > t0 && !(v > bound)) || p == INT_MAX) break;
       const double tau = uni(L.wsc[par][ws][0]);
-      const double scal = uni(L.wsc[par][ws][1]);
-      const double* xw = L.wcol[par][ws];
+      double* vt = L.vlog + t * LMAX;
       if (active && pos == p) {
         active = false;
+        won = t;
+        beta_w = L.wsc[par][ws][1];
         L.pphys[t] = phys;
       } else if (active && pos == t) {
         pos = p;  // sequential swap: the column at position t moves to p
       }
-      if (tid < LMAX / 2)
-        reinterpret_cast<double2*>(L.vraw + t * LMAX)[tid] = reinterpret_cast<const double2*>(xw)[tid];
+      if (tid < LMAX) {  // the winner's reflector, one row per thread
+        const double xr = L.wv[par][ws][tid];
+        vt[tid] = (tid < t) ? 0.0 : ((tid == t) ? 1.0 : xr * L.wsc[par][ws][2]);
+      }
       if (tid == 0) {
         L.taus[t] = tau;
-        L.scals[t] = scal;
-        L.betas[t] = uni(L.wsc[par][ws][2]);
         L.plog[t] = p;
       }
-      if (active) nu = sq_apply<LMAX, true>(x, xw, tau, scal, t);
+      __syncthreads();
+      if (active) {
+        const double d = sq_dot<LMAX>(x, vt, tau);
+        sq_axpy<LMAX>(x, vt, d);
+        const double xt = alpha - d;  // new row-t entry (v[t] = 1)
+        nu -= xt * xt;
+        if (!(nu >= 0.1 * nu_ref)) {
+          nu = sq_norm2<LMAX>(x, t + 1);
+          nu_ref = nu;
+        }
+        alpha = row_at<LMAX>(x, t + 1);
+      }
       ++t;
     }
     const int tn = t;
+    if (won >= 0) {
+      // S column of this round's pivot: rows above the pivot row as they
+      // were when it was chosen, beta on it, zeros below
+      const double* __restrict__ ml = mask_ge(L, won);
+      const double* __restrict__ mq = mask_eq(L, won);
+      double2* st = reinterpret_cast<double2*>(L.slog + won * LMAX);
+#pragma unroll
+      for (int i = 0; i < LMAX / 2; ++i)
+        st[i] = make_double2(fma(x[2 * i], 1.0 - ml[2 * i], beta_w * mq[2 * i]),
+                             fma(x[2 * i + 1], 1.0 - ml[2 * i + 1], beta_w * mq[2 * i + 1]));
+    }
     __syncthreads();
     for (int s = t0; s < tn; ++s) {
       if (c_s == L.pphys[s]) sel_s = true;
@@ -490,14 +566,10 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
     t0 = uni(tn);
   }
   // the pivot columns of the sample go to positions 0..bJ-1 (workgroup 0
-  // owns those physical columns, and its own reads of them are done): rows
-  // above the pivot row from the stored column, beta on it, zeros below
+  // owns those physical columns, and its own reads of them are done)
   if (me == 0) {
     __syncthreads();
-    for (int e = tid; e < a.bJ * LMAX; e += SQ_T) {
-      const int tt = e / LMAX, r = e - tt * LMAX;
-      a.S[e] = (r < tt) ? L.vraw[e] : ((r == tt) ? L.betas[tt] : 0.0);
-    }
+    for (int e = tid; e < a.bJ * LMAX; e += SQ_T) a.S[e] = L.slog[e];
   }
 }
 
@@ -685,7 +757,9 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 }  // namespace
 
 size_t sample_qrcp_flag_words() { return 128; }
-int sample_rows_padded(int l) { return l <= 32 ? 32 : l <= 64 ? 64 : l <= 80 ? 80 : l <= 128 ? 128 : -1; }
+int sample_rows_padded(int l) {
+  return l <= 32 ? 32 : l <= 64 ? 64 : l <= 72 ? 72 : l <= 80 ? 80 : l <= 128 ? 128 : -1;
+}
 size_t sample_qrcp_cand_elems() { return 2 * (size_t)SQ_LCAP * SQ_T; }
 size_t sample_qrcp_idx_elems() { return 2 * 2 * (size_t)SQ_T; }
 size_t sample_qrcp_theta_elems() { return 2 * (size_t)SQ_MAXP; }
@@ -700,6 +774,7 @@ int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ,
   a.cand = w.cand; a.cand_idx = w.cand_idx; a.theta = w.theta; a.flags = w.flags; a.err = w.err;
   if (l <= 32) return launch_sq<32>(s, a);
   if (l <= 64) return launch_sq<64>(s, a);
+  if (l <= 72) return launch_sq<72>(s, a);
   if (l <= 80) return launch_sq<80>(s, a);
   if (l <= 128) return launch_sq<128>(s, a);
   return -7;
