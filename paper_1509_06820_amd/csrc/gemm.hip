@@ -24,19 +24,27 @@ namespace rq {
 
 namespace {
 
+template <int BM, int BN, int BK>
+constexpr size_t gemm_lds_bytes() {
+  return (size_t)2 * BK * ((BM + 2) + (BN + 2)) * sizeof(double);
+}
+
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
-__global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+__global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                    const double* __restrict__ A, int64_t lda,
                                                    const double* __restrict__ B, int64_t ldb, double beta,
                                                    double* __restrict__ C, int64_t ldc, int64_t kchunk,
                                                    int64_t split_stride) {
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int TM = WTM / 16, TN = WTN / 16;
-  constexpr int APAD = 2, BPAD = 2;
+  constexpr int ALD = BM + 2, BLD = BN + 2;  // padded rows: no bank conflicts between k rows
   constexpr int A_PER = BM * BK / 256, B_PER = BK * BN / 256;
   static_assert(A_PER * 256 == BM * BK && B_PER * 256 == BK * BN, "tile/threads mismatch");
-  __shared__ double As[BK][BM + APAD];
-  __shared__ double Bs[BK][BN + BPAD];
+  static_assert(WM * WN == 4, "four waves");
+  // two LDS stages: the tiles of step k+1 are stored while step k computes
+  extern __shared__ __align__(16) double gsm[];
+  double* As = gsm;                   // [2][BK][ALD]
+  double* Bs = gsm + 2 * BK * ALD;    // [2][BK][BLD]
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -47,11 +55,35 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
   const int64_t kend = min(K, kbeg + kchunk);
   double* Cz = C + (int64_t)blockIdx.z * split_stride;
 
+  // The accumulators start from beta * C (lane holds C(i, j) for
+  // i = row0 + lane%16, j = col0 + 4r + lane/16): all C loads are issued
+  // together, ahead of the first operand tiles, and alpha is folded into the
+  // A tile, so the epilogue is stores only.
   double4_t acc[TM][TN];
+  const int64_t ri = i0 + wm * WTM + (lane & 15);
+  const int64_t cj = j0 + wn * WTN + (lane >> 4);
+  if (beta != 0.0) {
 #pragma unroll
-  for (int a = 0; a < TM; ++a)
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < TN; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gi = ri + a * 16, gj = cj + b * 16 + 4 * r;
+          acc[a][b][r] = (gi < M && gj < N) ? Cz[gi + gj * ldc] : 0.0;
+        }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[a][b][r] *= beta;
+  } else {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  }
 
   double ra[A_PER], rb[B_PER];
 
@@ -77,64 +109,63 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
       rb[e] = v;
     }
   };
-  auto store_tiles = [&]() {
+  auto store_tiles = [&](int stage) {
+    double* as = As + stage * BK * ALD;
+    double* bs = Bs + stage * BK * BLD;
 #pragma unroll
     for (int e = 0; e < A_PER; ++e) {
       const int idx = tid + e * 256;
       int ii, kk;
       if (TA) { kk = idx % BK; ii = idx / BK; } else { ii = idx % BM; kk = idx / BM; }
-      As[kk][ii] = ra[e];
+      as[kk * ALD + ii] = alpha * ra[e];
     }
 #pragma unroll
     for (int e = 0; e < B_PER; ++e) {
       const int idx = tid + e * 256;
       int jj, kk;
       if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
-      Bs[kk][jj] = rb[e];
+      bs[kk * BLD + jj] = rb[e];
     }
   };
 
   if (kbeg < kend) {
     load_tiles(kbeg);
+    store_tiles(0);
+    __syncthreads();
+    int stage = 0;
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-      store_tiles();
-      __syncthreads();
-      if (k0 + BK < kend) load_tiles(k0 + BK);
+      const bool more = k0 + BK < kend;
+      if (more) load_tiles(k0 + BK);
+      const double* as = As + stage * BK * ALD;
+      const double* bs = Bs + stage * BK * BLD;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         double af[TM], bf[TN];
 #pragma unroll
-        for (int a = 0; a < TM; ++a) af[a] = As[kk + (lane >> 4)][wm * WTM + a * 16 + (lane & 15)];
+        for (int a = 0; a < TM; ++a) af[a] = as[(kk + (lane >> 4)) * ALD + wm * WTM + a * 16 + (lane & 15)];
 #pragma unroll
-        for (int b = 0; b < TN; ++b) bf[b] = Bs[kk + (lane >> 4)][wn * WTN + b * 16 + (lane & 15)];
+        for (int b = 0; b < TN; ++b) bf[b] = bs[(kk + (lane >> 4)) * BLD + wn * WTN + b * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < TM; ++a)
 #pragma unroll
           for (int b = 0; b < TN; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
       }
+      if (more) store_tiles(stage ^ 1);
       __syncthreads();
+      stage ^= 1;
     }
   }
 
-  // Epilogue: lane holds C(i, j) for i = row0 + lane%16, j = col0 + 4r + lane/16.
 #pragma unroll
-  for (int a = 0; a < TM; ++a) {
-    const int64_t gi = i0 + wm * WTM + a * 16 + (lane & 15);
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < TN; ++b) {
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gj = j0 + wn * WTN + b * 16 + 4 * r + (lane >> 4);
-        if (gi < M && gj < N) {
-          double* p = Cz + gi + gj * ldc;
-          double v = alpha * acc[a][b][r];
-          if (beta != 0.0) v += beta * (*p);
-          *p = v;
-        }
+        const int64_t gi = ri + a * 16, gj = cj + b * 16 + 4 * r;
+        if (gi < M && gj < N) Cz[gi + gj * ldc] = acc[a][b][r];
       }
-    }
-  }
 }
 
 // C = alpha * sum_z P[z] + beta * C   (P[z] is M x N with leading dimension M)
@@ -180,42 +211,61 @@ __global__ void __launch_bounds__(256) splitk_reduce_many_kernel(int64_t M, int6
   }
 }
 
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+int launch_one(hipStream_t s, dim3 grid, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+               const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
+               int64_t split_stride) {
+  constexpr size_t lds = gemm_lds_bytes<BM, BN, BK>();
+  static bool attr = false;
+  if (!attr) {
+    RQ_HIP(hipFuncSetAttribute((const void*)gemm_kernel<BM, BN, BK, WM, WN, TA, TB>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, TA, TB>), grid, dim3(256), lds, s, M, N, K, alpha, A, lda, B,
+                     ldb, beta, C, ldc, kchunk, split_stride);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
+
 template <int BM, int BN, int BK, int WM, int WN>
 int launch_tiles(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                  int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int splits,
                  int64_t kchunk, int64_t split_stride) {
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
-  dim3 block(256);
   if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, false, false>), grid, block, 0, s, M, N, K, alpha, A, lda,
-                       B, ldb, beta, C, ldc, kchunk, split_stride);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, true, false>), grid, block, 0, s, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc, kchunk, split_stride);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, false, true>), grid, block, 0, s, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc, kchunk, split_stride);
-  else
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, true, true>), grid, block, 0, s, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc, kchunk, split_stride);
-  RQ_HIP(hipGetLastError());
-  return 0;
+    return launch_one<BM, BN, BK, WM, WN, false, false>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                                                         split_stride);
+  if (ta && !tb)
+    return launch_one<BM, BN, BK, WM, WN, true, false>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                                                        split_stride);
+  if (!ta && tb)
+    return launch_one<BM, BN, BK, WM, WN, false, true>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                                                        split_stride);
+  return launch_one<BM, BN, BK, WM, WN, true, true>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                                                     split_stride);
 }
 
 }  // namespace
 
-// Small outputs with a long reduction (Gram matrices of tall panels, b x n
-// products with n short) are split along K: "gram mode" for outputs of at
-// most 64 x 128 (up to 256 splits of >= 32 rows), the general split for
-// short-and-wide outputs (up to 8 splits).
+// Small outputs with a long reduction (Gram matrices of tall panels) are
+// split along K: "gram mode" for outputs of at most 64 x 128, up to 256
+// splits of >= 32 rows.
 constexpr int GRAM_MAXS = 256;
 constexpr int64_t GRAM_MINK = 32;
 
 bool gram_mode(int64_t M, int64_t N, int64_t K) { return M <= 64 && N <= 128 && K >= 256; }
 
+// Short-wide outputs with a long reduction (b x n products Y^T A): 64 x 128
+// tiles, up to WIDE_MAXS splits of at least WIDE_MINK rows.
+constexpr int WIDE_MAXS = 16;
+constexpr int64_t WIDE_MINK = 512;
+
+static bool wide_mode(int64_t M, int64_t K) { return M <= 64 && K >= 1024; }
+
 size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K) {
   size_t e = 0;
-  if (M <= 128 && K >= 1024) e = (size_t)M * (size_t)N * 8;
+  if (wide_mode(M, K)) e = (size_t)M * (size_t)N * WIDE_MAXS;
   if (gram_mode(M, N, K)) {
     const int64_t s = std::min<int64_t>(GRAM_MAXS, (K + GRAM_MINK - 1) / GRAM_MINK);
     e = std::max(e, (size_t)M * (size_t)N * (size_t)s);
@@ -232,10 +282,10 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
     if (beta == 1.0) return 0;
     return launch_scale(s, M, N, beta, C, ldc);
   }
-  constexpr int BM = 64, BN = 64, BK = 16;
-  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  constexpr int BK = 16;
   int splits = 1;
   int64_t kchunk = K;
+  enum { SMALL, BIG, WIDE } shape = SMALL;
   bool many = false;
   if (scratch && gram_mode(M, N, K)) {
     kchunk = std::max<int64_t>(GRAM_MINK, (K + GRAM_MAXS - 1) / GRAM_MAXS);
@@ -246,19 +296,35 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
       splits = (int)((K + kchunk - 1) / kchunk);
     }
     many = true;
-  } else if (scratch && M <= 128 && K >= 1024) {
-    // aim for >= 1024 workgroups, at least 512 reduction steps per split
-    int64_t want = (1024 + tiles - 1) / tiles;
-    int64_t maxs = K / 512;
-    splits = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, 8}));
+  } else if (scratch && wide_mode(M, K)) {
+    // aim for >= 512 workgroups (two per CU), at least WIDE_MINK rows per split
+    shape = WIDE;
+    const int64_t tiles = (N + 127) / 128;
+    const int64_t want = (512 + tiles - 1) / tiles;
+    const int64_t maxs = K / WIDE_MINK;
+    splits = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, (int64_t)WIDE_MAXS}));
     while (splits > 1 && (size_t)splits * (size_t)M * (size_t)N > scratch_elems) --splits;
     kchunk = (K + splits - 1) / splits;
     kchunk = (kchunk + BK - 1) / BK * BK;
+    splits = (int)((K + kchunk - 1) / kchunk);
+  } else if (M >= 128 && N >= 128) {
+    shape = BIG;
   }
-  if (splits == 1)
-    return launch_tiles<BM, BN, BK, 2, 2>(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 1, K, 0);
-  int rc = launch_tiles<BM, BN, BK, 2, 2>(s, ta, tb, M, N, K, 1.0, A, lda, B, ldb, 0.0, scratch, M, splits, kchunk,
-                                          M * N);
+  auto tiles = [&](double al, double be, double* out, int64_t ldo, int64_t stride) {
+    switch (shape) {
+      case BIG:
+        return launch_tiles<128, 128, BK, 2, 2>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo, splits, kchunk,
+                                                stride);
+      case WIDE:
+        return launch_tiles<64, 128, BK, 1, 4>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo, splits, kchunk,
+                                               stride);
+      default:
+        return launch_tiles<64, 64, BK, 2, 2>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo, splits, kchunk,
+                                              stride);
+    }
+  };
+  if (splits == 1) return tiles(alpha, beta, C, ldc, 0);
+  int rc = tiles(1.0, 0.0, scratch, M, M * N);
   if (rc) return rc;
   const int64_t total = M * N;
   if (many) {
