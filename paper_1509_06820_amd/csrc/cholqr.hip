@@ -68,93 +68,6 @@ __device__ __forceinline__ void sm_store(const double* M, double* G, int64_t ld,
     for (int j = sm_cg(); j < b; j += SM_T / SM_N) G[i + (int64_t)j * ld] = M[i + j * SM_LD];
 }
 
-// ---------------------------------------------------------------- one-wave factorisations
-// The Cholesky and the sign-choosing LU are chains of 64 dependent steps.
-// They run in wave 0 alone, without workgroup barriers: lane j holds column j
-// in registers (the step loop is unrolled, so every register index is a
-// constant), and a value another lane holds is read with v_readlane into
-// scalar registers.  The other waves wait at the closing barrier.
-
-__device__ __forceinline__ double lane_val(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
-
-// In-place Cholesky G = R^T R of the upper triangle of G (64 x 64, LDS;
-// R upper, lower part zeroed).  Returns false (uniformly) if a pivot is not
-// positive.
-__device__ __forceinline__ bool sm_chol(double* G, int* flag) {
-  if (threadIdx.x == 0) *flag = 0;
-  __syncthreads();
-  if (threadIdx.x < SM_N) {
-    const int j = threadIdx.x;
-    double g[SM_N];
-#pragma unroll
-    for (int i = 0; i < SM_N; ++i) g[i] = (i <= j) ? G[i + j * SM_LD] : 0.0;
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < SM_N; ++k) {
-      const double d = lane_val(g[k], k);
-      ok = ok && (d > 0.0);
-      const double dd = (d > 0.0) ? d : 1.0;
-      const double sd = sqrt(dd), isd = 1.0 / sd;
-      const double rkj = (j > k) ? g[k] * isd : ((j == k) ? sd : 0.0);  // R(k, j)
-      g[k] = rkj;
-#pragma unroll
-      for (int i = k + 1; i < SM_N; ++i) g[i] = fma(-lane_val(rkj, i), rkj, g[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < SM_N; ++i) G[i + j * SM_LD] = (i <= j) ? g[i] : 0.0;
-    if (j == 0 && !ok) *flag = 1;
-  }
-  __syncthreads();
-  return *flag == 0;
-}
-
-// LU without pivoting of E - Q S on the top b x b block (in A, 64 x 64 LDS,
-// identity padded), with the sign choice of Householder reconstruction: at
-// step i with c0 = Q'(i, i), S_ii = -sign(c0) (sign(0) = +1), U(i, i) =
-// 1 + |c0|, L(r, i) = -S_ii Q'(r, i) / U(i, i), Q'(r, c) -= L(r, i) Q'(i, c).
-// The last column of a square panel (i = mJ - 1) has no row below: there
-// S_ii = sign(c0) and U(i, i) = 0.  On return A holds L (unit, below the
-// diagonal), U(i, i) on the diagonal and Q' above it; sgn[i] = S_ii.
-__device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_t mJ) {
-  if (threadIdx.x < SM_N) {
-    const int j = threadIdx.x;
-    double a[SM_N];
-#pragma unroll
-    for (int i = 0; i < SM_N; ++i) a[i] = A[i + j * SM_LD];
-#pragma unroll
-    for (int i = 0; i < SM_N; ++i) {
-      if (i < b) {
-        const double c0 = lane_val(a[i], i);
-        if (i == mJ - 1) {
-          if (j == 0) sgn[i] = (c0 >= 0.0) ? 1.0 : -1.0;
-          if (j == i) a[i] = 0.0;
-        } else {
-          const double sg = (c0 >= 0.0) ? -1.0 : 1.0;
-          const double piv = 1.0 + fabs(c0);
-          const double f = -sg / piv;
-          // column i (lane i) becomes L(:, i); every lane right of it takes
-          // the rank-1 update with its own row-i entry
-          const double aij = a[i];
-#pragma unroll
-          for (int r = i + 1; r < SM_N; ++r) {
-            const double l = lane_val(a[r], i) * f;
-            a[r] = (j == i) ? l : ((j > i) ? fma(-l, aij, a[r]) : a[r]);
-          }
-          if (j == i) a[i] = piv;
-          if (j == 0) sgn[i] = sg;
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < SM_N; ++i) A[i + j * SM_LD] = a[i];
-  }
-  __syncthreads();
-}
-
 // Products of LDS matrices on the matrix cores: for each of nb batches
 // (pointers advanced by boff), the M x N result of op(A) B (K inner, M and N
 // multiples of 16, K of 4) is handed element by element to epi(i, j, value).
@@ -185,6 +98,127 @@ __device__ __forceinline__ void sm_mm(const double* A, const double* B, int M, i
 #pragma unroll
     for (int r = 0; r < 4; ++r) epi(bi, ia, j0 + 4 * r + (lane >> 4), acc[r]);
   }
+}
+
+// ---------------------------------------------------------------- blocked factorisations
+// The Cholesky and the sign-choosing LU run in blocks of 16.  Within a
+// block, wave 0 alone takes the 16 dependent steps without workgroup
+// barriers: its lanes hold a 16-wide band of the matrix in registers (the
+// step loop is unrolled, so every register index is a constant) and a value
+// another lane holds is read with v_readlane into scalar registers.  The
+// rank-16 update of the rest of the matrix runs on the matrix cores in all
+// four waves.
+constexpr int SM_NB = 16;
+
+__device__ __forceinline__ double lane_val(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// In-place Cholesky G = R^T R of the upper triangle of G (64 x 64, LDS;
+// R upper, lower part zeroed).  Returns false (uniformly) if a pivot is not
+// positive.  Block k0: lane c holds G(k0:k0+16, c), the row band of R.
+__device__ __forceinline__ bool sm_chol(double* G, int* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  for (int k0 = 0; k0 < SM_N; k0 += SM_NB) {
+    if (threadIdx.x < SM_N) {
+      const int c = threadIdx.x;
+      double a[SM_NB];
+#pragma unroll
+      for (int i = 0; i < SM_NB; ++i) a[i] = G[(k0 + i) + c * SM_LD];
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < SM_NB; ++i) {
+        const int p = k0 + i;
+        const double d = lane_val(a[i], p);
+        ok = ok && (d > 0.0);
+        const double dd = (d > 0.0) ? d : 1.0;
+        const double sd = sqrt(dd), isd = 1.0 / sd;
+        const double r = (c > p) ? a[i] * isd : ((c == p) ? sd : 0.0);  // R(p, c)
+        a[i] = r;
+#pragma unroll
+        for (int q = i + 1; q < SM_NB; ++q) a[q] = fma(-lane_val(r, k0 + q), r, a[q]);
+      }
+#pragma unroll
+      for (int i = 0; i < SM_NB; ++i) G[(k0 + i) + c * SM_LD] = (c >= k0 + i) ? a[i] : 0.0;
+      if (c == 0 && !ok) *flag = 1;
+    }
+    __syncthreads();
+    const int n2 = SM_N - k0 - SM_NB;
+    if (n2 > 0) {
+      // G22 -= R12^T R12
+      const double* R12 = G + k0 + (k0 + SM_NB) * SM_LD;
+      double* G22 = G + (k0 + SM_NB) * (1 + SM_LD);
+      sm_mm<true>(R12, R12, n2, n2, SM_NB, 1, 0, [&](int, int i, int j, double v) { G22[i + j * SM_LD] -= v; });
+      __syncthreads();
+    }
+  }
+  return *flag == 0;
+}
+
+// LU without pivoting of E - Q S on the top b x b block (in A, 64 x 64 LDS,
+// identity padded), with the sign choice of Householder reconstruction: at
+// step i with c0 = Q'(i, i), S_ii = -sign(c0) (sign(0) = +1), U(i, i) =
+// 1 + |c0|, L(r, i) = -S_ii Q'(r, i) / U(i, i), Q'(r, c) -= L(r, i) Q'(i, c).
+// The last column of a square panel (i = mJ - 1) has no row below: there
+// S_ii = sign(c0) and U(i, i) = 0.  On return A holds L (unit, below the
+// diagonal), U(i, i) on the diagonal and Q' above it; sgn[i] = S_ii.
+// Block k0: lane r holds A(r, k0:k0+16) (the column panel: L and the
+// diagonal block) and A(k0:k0+16, r) for r >= k0 + 16 (the row band of U).
+__device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_t mJ) {
+  for (int k0 = 0; k0 < b; k0 += SM_NB) {
+    if (threadIdx.x < SM_N) {
+      const int r = threadIdx.x;
+      const bool band = r >= k0 + SM_NB;
+      double a[SM_NB], u[SM_NB];
+#pragma unroll
+      for (int j = 0; j < SM_NB; ++j) {
+        a[j] = A[r + (k0 + j) * SM_LD];
+        u[j] = A[(k0 + j) + r * SM_LD];
+      }
+#pragma unroll
+      for (int i = 0; i < SM_NB; ++i) {
+        const int p = k0 + i;
+        if (p < b) {
+          const double c0 = lane_val(a[i], p);
+          if (p == mJ - 1) {
+            if (r == 0) sgn[p] = (c0 >= 0.0) ? 1.0 : -1.0;
+            if (r == p) a[i] = 0.0;
+          } else {
+            const double sg = (c0 >= 0.0) ? -1.0 : 1.0;
+            const double piv = 1.0 + fabs(c0);
+            const double f = -sg / piv;
+            const double l = (r > p) ? a[i] * f : 0.0;  // L(r, p)
+            a[i] = (r > p) ? l : ((r == p) ? piv : a[i]);
+#pragma unroll
+            for (int j = i + 1; j < SM_NB; ++j) a[j] = fma(-l, lane_val(a[j], p), a[j]);
+            // row band: A(k0 + q, c) -= L(k0 + q, p) A(p, c)
+#pragma unroll
+            for (int q = i + 1; q < SM_NB; ++q) u[q] = fma(-lane_val(l, k0 + q), u[i], u[q]);
+            if (r == 0) sgn[p] = sg;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < SM_NB; ++j) {
+        if (r >= k0) A[r + (k0 + j) * SM_LD] = a[j];
+        if (band) A[(k0 + j) + r * SM_LD] = u[j];
+      }
+    }
+    __syncthreads();
+    const int n2 = SM_N - k0 - SM_NB;
+    if (n2 > 0 && k0 + SM_NB < b) {
+      // A22 -= L21 U12
+      const double* L21 = A + (k0 + SM_NB) + k0 * SM_LD;
+      const double* U12 = A + k0 + (k0 + SM_NB) * SM_LD;
+      double* A22 = A + (k0 + SM_NB) * (1 + SM_LD);
+      sm_mm<false>(L21, U12, n2, n2, SM_NB, 1, 0, [&](int, int i, int j, double v) { A22[i + j * SM_LD] -= v; });
+      __syncthreads();
+    }
+  }
+  __syncthreads();
 }
 
 // Inverse of an upper-triangular matrix by recursive doubling:
