@@ -39,9 +39,10 @@ struct SqParams {
 template <int LMAX>
 struct SqLds {
   double vlog[SQ_BMAX * LMAX];        // reflector of step t (zero above row t, one at row t)
-  double slog[SQ_BMAX * LMAX];        // final sample column of pivot t
-  double wv[2][SQ_T / WAVE][LMAX];    // each wave's best candidate column (double buffered by step)
-  double wsc[2][SQ_T / WAVE][4];      // its tau, beta, 1 / (alpha - beta)
+  // Quad layout (row 4 i + q at [q * LMAX / 4 + i]): during a round, the
+  // reflectors of its steps; at its end they are copied to vlog and their
+  // rows take the final sample columns of the round's pivots.
+  double vq[SQ_BMAX * LMAX];
   // Row masks: ge0[LMAX + d] = (d >= 0), eq0[LMAX + d] = (d == 0); ge1, eq1
   // are the same tables shifted by one element, so that the mask of any
   // row offset can be read with 16-byte aligned accesses.
@@ -51,6 +52,8 @@ struct SqLds {
   int kp[SQ_T];
   int rk[SQ_T];                       // rank of each lane's column
   int plog[SQ_BMAX];                  // position of the pivot chosen at step t
+  int wonstep[SQ_T];                  // step at which candidate slot i became a pivot (-1: none)
+  double betas[SQ_BMAX];              // beta of the pivot of step t
   int pphys[SQ_BMAX];                 // its physical column
   double rv[2][SQ_T / WAVE];          // per-wave argmax
   int rp[2][SQ_T / WAVE];
@@ -127,16 +130,16 @@ template <int LMAX>
 __device__ __forceinline__ double sq_dot(const double (&x)[LMAX], const double* v, double tau) {
   constexpr int NC = LMAX / 8;
   double vb[3][8];
-  double d[4] = {0.0, 0.0, 0.0, 0.0};
+  double d[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   lds_chunk(vb[0], v);
   lds_chunk(vb[1], v + 8);
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) d[i & 3] = fma(vb[k % 3][i], x[8 * k + i], d[i & 3]);
+    for (int i = 0; i < 8; ++i) d[i] = fma(vb[k % 3][i], x[8 * k + i], d[i]);
     if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v, d[0]) + 8 * (k + 2));
   }
-  return tau * ((d[0] + d[1]) + (d[2] + d[3]));
+  return tau * (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])));
 }
 
 // x <- x - d v
@@ -153,6 +156,86 @@ __device__ __forceinline__ void sq_axpy(double (&x)[LMAX], const double* v, doub
     for (int i = 0; i < 8; ++i) x[8 * k + i] = fma(-d, vb[k % 3][i], x[8 * k + i]);
     if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v2, x[8 * k]) + 8 * (k + 2));
   }
+}
+
+// The reflector of step t is zero above row t, so the step's products only
+// need the 8-row chunks from t / 8 on.  The suffix length is a template
+// parameter (every register index stays a constant and the chunk reads keep
+// their prefetch ring); *_from dispatch on the uniform first chunk.
+
+// sum over chunks K0.. of v[r] x[r]
+template <int LMAX, int K0>
+__device__ __forceinline__ double sq_dot_k(const double (&x)[LMAX], const double* v) {
+  constexpr int NC = LMAX / 8;
+  double vb[3][8];
+  double d[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  lds_chunk(vb[K0 % 3], v + 8 * K0);
+  if (K0 + 1 < NC) lds_chunk(vb[(K0 + 1) % 3], v + 8 * (K0 + 1));
+#pragma unroll
+  for (int k = K0; k < NC; ++k) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) d[i] = fma(vb[k % 3][i], x[8 * k + i], d[i]);
+    if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v, d[0]) + 8 * (k + 2));
+  }
+  return ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]));
+}
+
+// x <- x - d v over chunks K0.., returning the squared norm of rows >= from
+// (uniform, from >= 8 K0) of the result
+template <int LMAX, int K0>
+__device__ __forceinline__ double sq_axpy_norm_k(double (&x)[LMAX], const double* v, double d, int from) {
+  constexpr int NC = LMAX / 8;
+  const double* v2 = after(v, d);
+  double vb[3][8];
+  double n[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  lds_chunk(vb[K0 % 3], v2 + 8 * K0);
+  if (K0 + 1 < NC) lds_chunk(vb[(K0 + 1) % 3], v2 + 8 * (K0 + 1));
+#pragma unroll
+  for (int k = K0; k < NC; ++k) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[8 * k + i] = fma(-d, vb[k % 3][i], x[8 * k + i]);
+    if (8 * k >= from) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) n[i] = fma(x[8 * k + i], x[8 * k + i], n[i]);
+    } else if (8 * k + 8 > from) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) n[i] += (8 * k + i >= from) ? x[8 * k + i] * x[8 * k + i] : 0.0;
+    }
+    if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v2, x[8 * k]) + 8 * (k + 2));
+  }
+  return ((n[0] + n[1]) + (n[2] + n[3])) + ((n[4] + n[5]) + (n[6] + n[7]));
+}
+
+template <int LMAX, int K>
+__device__ __forceinline__ double sq_dot_from(const double (&x)[LMAX], const double* v, int k0) {
+  if constexpr (K + 1 < LMAX / 8) {
+    if (k0 > K) return sq_dot_from<LMAX, K + 1>(x, v, k0);
+  }
+  return sq_dot_k<LMAX, K>(x, v);
+}
+
+template <int LMAX, int K>
+__device__ __forceinline__ double sq_axpy_norm_from(double (&x)[LMAX], const double* v, double d, int from, int k0) {
+  if constexpr (K + 1 < LMAX / 8) {
+    if (k0 > K) return sq_axpy_norm_from<LMAX, K + 1>(x, v, d, from, k0);
+  }
+  return sq_axpy_norm_k<LMAX, K>(x, v, d, from);
+}
+
+// Householder reflector of a column whose pivot-row entry is alpha and whose
+// rows below have squared norm sig (dlarfg normalisation: beta = -sign(alpha)
+// ||x||, tau = (beta - alpha) / beta, v = x / (alpha - beta) below the pivot
+// row; an exactly zero tail gives tau = 0 and beta = alpha).  With
+// q = |alpha| + ||x|| (no cancellation), tau = q / ||x|| and
+// 1 / (alpha - beta) = sign(alpha) / q: two independent reciprocals.
+__device__ __forceinline__ void sq_reflector(double alpha, double sig, double& tau, double& beta, double& scal) {
+  const double nrm = sqrt(fma(alpha, alpha, sig));
+  const double sg = (alpha >= 0.0) ? 1.0 : -1.0;
+  const double q = fabs(alpha) + nrm;
+  const bool zero = !(sig != 0.0);
+  tau = zero ? 0.0 : q * rcp_nr(nrm);
+  beta = zero ? alpha : -sg * nrm;
+  scal = zero ? 0.0 : sg * rcp_nr(q);
 }
 
 // x <- (I - tau v v^T) x; full rows, branch free (v is zero above its first row).
@@ -244,6 +327,85 @@ __device__ __forceinline__ void wave_argmax_vp(double v, int p, double& bv, int&
     best = min(best, __builtin_amdgcn_readlane(p, ln));
   }
   bp = best;
+}
+
+// Quad lanes (tid & ~3 .. tid | 3) exchange values with DPP quad permutes.
+template <int CTRL>
+__device__ __forceinline__ double qperm(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// Sum over the quad; every lane gets the same bits (the two additions are
+// the same pairs in either order).
+__device__ __forceinline__ double quad_sum(double v) {
+  v += qperm<0xB1>(v);
+  return v + qperm<0x4E>(v);
+}
+// The value of quad lane qs (uniform) in every lane of the quad.
+__device__ __forceinline__ double quad_bcast(double v, int qs) {
+  switch (qs) {
+    case 0: return qperm<0x00>(v);
+    case 1: return qperm<0x55>(v);
+    case 2: return qperm<0xAA>(v);
+    default: return qperm<0xFF>(v);
+  }
+}
+
+// Row-quad helpers: x[c][i] is row 4 i + q (q = quad lane) of column c.
+
+// e[c] = x[c][ri] for a uniform ri (binary branch tree on ri).
+template <int RQ, int LO, int HI>
+__device__ __forceinline__ void sq_pick_rows(const double (&x)[4][RQ], int ri, double (&e)[4]) {
+  if constexpr (HI - LO == 1) {
+    double e0 = x[0][LO], e1 = x[1][LO], e2 = x[2][LO], e3 = x[3][LO];
+    // the leaf's values pass through an empty asm statement, so the leaves
+    // cannot be merged into one access with a computed register index
+    asm volatile("; row pick" : "+v"(e0), "+v"(e1), "+v"(e2), "+v"(e3));
+    e[0] = e0;
+    e[1] = e1;
+    e[2] = e2;
+    e[3] = e3;
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (ri < MID) sq_pick_rows<RQ, LO, MID>(x, ri, e);
+    else sq_pick_rows<RQ, MID, HI>(x, ri, e);
+  }
+}
+
+template <int RQ>
+__device__ __forceinline__ void sq_copy_col(const double (&xc)[RQ], double (&y)[RQ]) {
+#pragma unroll
+  for (int i = 0; i < RQ; ++i) y[i] = xc[i];
+}
+
+// Sum over the quad of y[i]^2 for rows 4 i + q >= f (uniform f): every row
+// index i > f / 4 counts, i == f / 4 counts in lanes q >= f % 4.
+template <int RQ>
+__device__ __forceinline__ double sq_tail2_one(const double (&y)[RQ], int q, int f) {
+  const int fi = f >> 2, fq = f & 3;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < RQ; ++i) {
+    const double m = (i > fi) ? 1.0 : ((i == fi && q >= fq) ? 1.0 : 0.0);
+    acc[i & 1] = fma(y[i] * m, y[i], acc[i & 1]);
+  }
+  return quad_sum(acc[0] + acc[1]);
+}
+
+// The same for the four columns.
+template <int RQ>
+__device__ __forceinline__ void sq_tail2(const double (&x)[4][RQ], int q, int f, double (&out)[4]) {
+  const int fi = f >> 2, fq = f & 3;
+  double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+  for (int i = 0; i < RQ; ++i) {
+    const double m = (i > fi) ? 1.0 : ((i == fi && q >= fq) ? 1.0 : 0.0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c][i & 1] = fma(x[c][i] * m, x[c][i], acc[c][i & 1]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) out[c] = quad_sum(acc[c][0] + acc[c][1]);
 }
 
 // One pass over this workgroup's slab (one column per thread): apply the
@@ -340,10 +502,15 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
   double* cb = a.cand + (size_t)buf * SQ_LCAP * SQ_T;
   int* ib = a.cand_idx + (size_t)buf * 2 * SQ_T;
   if (mine && rank < a.K) {
+    // candidate columns are stored in quad layout (row 4 i + q at q RQ + i)
+    constexpr int RQ = LMAX / 4;
     const int slot = me * a.K + rank;
     double2* col = reinterpret_cast<double2*>(cb + (size_t)slot * LMAX);
 #pragma unroll
-    for (int i = 0; i < LMAX / 2; ++i) col[i] = make_double2(x[2 * i], x[2 * i + 1]);
+    for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+      for (int i = 0; i < RQ / 2; ++i)
+        col[qq * (RQ / 2) + i] = make_double2(x[4 * (2 * i) + qq], x[4 * (2 * i + 1) + qq]);
     ib[slot] = pos_s;
     ib[SQ_T + slot] = (int)c;
   }
@@ -417,30 +584,38 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
     if (!select) break;
     if (!sq_barrier(a, round)) return;
 
-    // gather the candidates (identical in every workgroup)
+    // gather the candidates (identical in every workgroup).  Four lanes (a
+    // quad) share four candidate columns: quad lane q holds rows 4 i + q,
+    // i < RQ, of all four, so each reflector value a lane reads from LDS
+    // serves four columns, and the quad's partial sums are combined by DPP.
+    constexpr int RQ = LMAX / 4;
     const int C = a.P * a.K;
     const double* cb = a.cand + (size_t)buf * SQ_LCAP * SQ_T;
     const int* ib = a.cand_idx + (size_t)buf * 2 * SQ_T;
-    int pos = (tid < C) ? ib[tid] : -1;
-    const int phys = (tid < C) ? ib[SQ_T + tid] : -1;
-    bool active = pos >= 0;
-    if (!active) pos = INT_MAX;
-    double x[LMAX];
-    if (active) {
-      const double2* col = reinterpret_cast<const double2*>(cb + (size_t)tid * LMAX);
+    const int q = tid & 3;
+    int pos[4], phys[4];
+    unsigned act = 0;  // bit c: column c of the quad is still a candidate
+    double x[4][RQ];
 #pragma unroll
-      for (int i = 0; i < LMAX / 2; ++i) {
-        const double2 w = col[i];
-        x[2 * i] = w.x;
-        x[2 * i + 1] = w.y;
+    for (int c = 0; c < 4; ++c) {
+      const int sl = (tid & ~3) + c;
+      pos[c] = (sl < C) ? ib[sl] : -1;
+      phys[c] = (sl < C) ? ib[SQ_T + sl] : -1;
+      if (pos[c] >= 0) act |= 1u << c;
+      else pos[c] = INT_MAX;
+      const double2* col = reinterpret_cast<const double2*>(cb + (size_t)sl * LMAX + q * RQ);
+      const bool on = pos[c] != INT_MAX;
+#pragma unroll
+      for (int i = 0; i < RQ / 2; ++i) {
+        const double2 w = on ? col[i] : make_double2(0.0, 0.0);
+        x[c][2 * i] = w.x;
+        x[c][2 * i + 1] = w.y;
       }
-    } else {
-#pragma unroll
-      for (int r = 0; r < LMAX; ++r) x[r] = 0.0;
     }
+    L.wonstep[tid] = -1;
     if (tid < WAVE) {
       double th = -INFINITY;
-      for (int q = tid; q < a.P; q += WAVE) th = fmax(th, a.theta[(size_t)buf * SQ_MAXP + q]);
+      for (int qq = tid; qq < a.P; qq += WAVE) th = fmax(th, a.theta[(size_t)buf * SQ_MAXP + qq]);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) th = fmax(th, __shfl_xor(th, off, WAVE));
       if (tid == 0) L.theta = th;
@@ -449,115 +624,201 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
     const double theta = uni(L.theta);
     const double bound = (theta > 0.0) ? theta * (1.0 + 1e-10) : theta;
 
-    int t = t0, won = -1;
-    double beta_w = 0.0;
-    // trailing squared norm (rows >= t) and the pivot-row entry x[t].  The
-    // norm is downdated after each step (the reflector leaves the norm of
-    // rows >= t unchanged, so rows > t keep it minus the new row-t entry
-    // squared) and recomputed once it has fallen below a tenth of its last
-    // exact value, which bounds its relative error by about 64 eps * 10.
-    double nu = active ? sq_norm2<LMAX>(x, t) : 0.0;
-    double nu_ref = nu;
-    double alpha = row_at<LMAX>(x, t);
+    int t = t0;
+    // Per column (the same in the quad's four lanes): alpha = x[t] and the
+    // trailing squared norm nu of rows >= t.  nu is downdated after each
+    // step (the reflector keeps the norm of rows >= t, so rows > t keep it
+    // minus the new row-t entry squared) and recomputed once it falls below
+    // a tenth of its last exact value, which bounds its relative error by
+    // about 64 eps * 10; the pivot's reflector always uses the exact norm
+    // of its column.
+    double alpha[4], nu[4], nu_ref[4];
+    {
+      double e[4];
+      sq_pick_rows<RQ, 0, RQ>(x, t >> 2, e);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) alpha[c] = quad_bcast(e[c], t & 3);
+      sq_tail2<RQ>(x, q, t, nu);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) nu_ref[c] = nu[c];
+    }
     while (t < a.bJ) {
       t = uni(t);
       const int par = t & 1;
-      double v;
-      int p;
-      wave_argmax_vp(active ? ranked(nu) : -INFINITY, active ? pos : INT_MAX, v, p);
-      if (active && pos == p) {
-        // this wave's best candidate: Householder reflector of rows t..l-1
-        // (dlarfg normalisation; an exactly zero tail gives tau = 0); the
-        // column is stored raw and normalised below once the winner is known
-        const double xn2 = sq_norm2<LMAX>(x, t + 1);  // exact tail norm
-        double tau = 0.0, beta = alpha, scal = 0.0;
-        if (xn2 != 0.0) {
-          // beta = -sign(alpha) nrm, so with q = |alpha| + nrm (no
-          // cancellation): tau = (beta - alpha) / beta = q / nrm and
-          // 1 / (alpha - beta) = sign(alpha) / q -- two independent
-          // reciprocals instead of two dependent divisions
-          const double nrm = sqrt(alpha * alpha + xn2);
-          const double sg = (alpha >= 0.0) ? 1.0 : -1.0;
-          const double q = fabs(alpha) + nrm;
-          beta = -sg * nrm;
-          tau = q * rcp_nr(nrm);
-          scal = sg * rcp_nr(q);
-        }
-        // the reflector is zero above row t: only the chunks from row t on
-        // are stored
-        double2* dst = reinterpret_cast<double2*>(L.wv[par][wv_id]);
+      // the quad's best column (the same in its four lanes)
+      double bv = -INFINITY;
+      int bp = INT_MAX, bc = 0;
 #pragma unroll
-        for (int k = 0; k < LMAX / 8; ++k)
-          if (8 * k + 8 > t) {
-#pragma unroll
-            for (int i = 4 * k; i < 4 * k + 4; ++i) dst[i] = make_double2(x[2 * i], x[2 * i + 1]);
-          }
-        L.wsc[par][wv_id][0] = tau;
-        L.wsc[par][wv_id][1] = beta;
-        L.wsc[par][wv_id][2] = scal;
+      for (int c = 0; c < 4; ++c) {
+        const bool on = (act >> c) & 1u;
+        const double val = on ? ranked(nu[c]) : -INFINITY;
+        const int pc = on ? pos[c] : INT_MAX;
+        if (beats(val, pc, bv, bp)) { bv = val; bp = pc; bc = c; }
       }
-      if ((tid & (WAVE - 1)) == 0) { L.rv[par][wv_id] = v; L.rp[par][wv_id] = p; }
+      double vwave;
+      int pwave;
+      wave_argmax_vp(bv, bp, vwave, pwave);
+      if ((tid & (WAVE - 1)) == 0) { L.rv[par][wv_id] = vwave; L.rp[par][wv_id] = pwave; }
       __syncthreads();
-      v = uni(L.rv[par][0]);
-      p = uni(L.rp[par][0]);
-      int ws = 0;
+      double v = uni(L.rv[par][0]);
+      int p = uni(L.rp[par][0]);
 #pragma unroll
       for (int w = 1; w < SQ_T / WAVE; ++w) {
         const double vw = uni(L.rv[par][w]);
         const int pw = uni(L.rp[par][w]);
-        if (better(vw, pw, v, p)) { v = vw; p = pw; ws = w; }
+        if (better(vw, pw, v, p)) { v = vw; p = pw; }
       }
       if ((t > t0 && !(v > bound)) || p == INT_MAX) break;
-      const double tau = uni(L.wsc[par][ws][0]);
-      double* vt = L.vlog + t * LMAX;
-      if (active && pos == p) {
-        active = false;
-        won = t;
-        beta_w = L.wsc[par][ws][1];
-        L.pphys[t] = phys;
-      } else if (active && pos == t) {
-        pos = p;  // sequential swap: the column at position t moves to p
-      }
-      if (tid < LMAX) {  // the winner's reflector, one row per thread
-        const double xr = L.wv[par][ws][tid];
-        vt[tid] = (tid < t) ? 0.0 : ((tid == t) ? 1.0 : xr * L.wsc[par][ws][2]);
-      }
-      if (tid == 0) {
-        L.taus[t] = tau;
-        L.plog[t] = p;
-      }
-      __syncthreads();
-      if (active) {
-        const double d = sq_dot<LMAX>(x, vt, tau);
-        sq_axpy<LMAX>(x, vt, d);
-        const double xt = alpha - d;  // new row-t entry (v[t] = 1)
-        nu -= xt * xt;
-        if (!(nu >= 0.1 * nu_ref)) {
-          nu = sq_norm2<LMAX>(x, t + 1);
-          nu_ref = nu;
+      double* vt = L.vq + t * LMAX;
+      if (pwave == p) {
+        // this wave holds the winner: column cw of one quad becomes pivot t.
+        // Its exact tail norm, its reflector (dlarfg normalisation) and the
+        // normalised reflector in quad layout (zero above row t, one at row
+        // t, the column below times 1 / (alpha - beta)) are formed by the
+        // whole wave with the winner's column index made uniform; only the
+        // winner's quad stores.
+        const bool is_w = bp == p;
+        const unsigned long long wm = __ballot(is_w);
+        const int cw = __builtin_amdgcn_readlane(bc, (int)__builtin_ctzll(wm));
+        const int ti = t >> 2, tq = t & 3;
+        auto win = [&](const double (&xc)[RQ], double al) __attribute__((always_inline)) {
+          const double sg2 = sq_tail2_one<RQ>(xc, q, t + 1);
+          double r_tau, r_beta, r_scal;
+          sq_reflector(al, sg2, r_tau, r_beta, r_scal);
+          if (is_w) {
+            double2* dst = reinterpret_cast<double2*>(vt + q * RQ);
+#pragma unroll
+            for (int i2 = 0; i2 < RQ / 2; ++i2) {
+              double e[2];
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int i = 2 * i2 + h;
+                const double sv = xc[i] * r_scal;
+                const double bnd = (q < tq) ? 0.0 : ((q == tq) ? 1.0 : sv);
+                e[h] = (i < ti) ? 0.0 : ((i > ti) ? sv : bnd);
+              }
+              dst[i2] = make_double2(e[0], e[1]);
+            }
+            if (q == 0) {
+              L.taus[t] = r_tau;
+              L.betas[t] = r_beta;
+              L.plog[t] = p;
+            }
+          }
+        };
+        // one copy of the code per column (the empty asm statements keep
+        // the compiler from merging them into an indexed access of x)
+        if (cw == 0) {
+          asm volatile("; winner column 0");
+          win(x[0], alpha[0]);
+        } else if (cw == 1) {
+          asm volatile("; winner column 1");
+          win(x[1], alpha[1]);
+        } else if (cw == 2) {
+          asm volatile("; winner column 2");
+          win(x[2], alpha[2]);
+        } else {
+          asm volatile("; winner column 3");
+          win(x[3], alpha[3]);
         }
-        alpha = row_at<LMAX>(x, t + 1);
+        if (is_w) {
+          int ph = phys[0];
+#pragma unroll
+          for (int c = 1; c < 4; ++c)
+            if (cw == c) ph = phys[c];
+          if (q == 0) {
+            L.pphys[t] = ph;
+            L.wonstep[(tid & ~3) + cw] = t;
+          }
+          act &= ~(1u << cw);
+        }
+      }
+      // sequential swap: the column at position t moves to p
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (((act >> c) & 1u) && pos[c] == t) pos[c] = p;
+      __syncthreads();
+      {
+        const double tau = uni(L.taus[t]);
+        double vr[RQ];
+        const double2* src = reinterpret_cast<const double2*>(vt + q * RQ);
+#pragma unroll
+        for (int i2 = 0; i2 < RQ / 2; ++i2) {
+          const double2 w = src[i2];
+          vr[2 * i2] = w.x;
+          vr[2 * i2 + 1] = w.y;
+        }
+        double dp[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+        for (int i = 0; i < RQ; ++i)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) dp[c][i & 1] = fma(vr[i], x[c][i], dp[c][i & 1]);
+        double d[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double s4 = quad_sum(dp[c][0] + dp[c][1]);
+          d[c] = ((act >> c) & 1u) ? tau * s4 : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < RQ; ++i)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) x[c][i] = fma(-d[c], vr[i], x[c][i]);
+        // downdate with the new row-t entries alpha - d (v[t] = 1)
+        bool redo = false;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double xt = alpha[c] - d[c];
+          nu[c] -= xt * xt;
+          redo = redo || (((act >> c) & 1u) && !(nu[c] >= 0.1 * nu_ref[c]));
+        }
+        if (__ballot(redo)) {
+          double ex[4];
+          sq_tail2<RQ>(x, q, t + 1, ex);
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (!(nu[c] >= 0.1 * nu_ref[c])) { nu[c] = ex[c]; nu_ref[c] = ex[c]; }
+        }
+        double e[4];
+        sq_pick_rows<RQ, 0, RQ>(x, (t + 1) >> 2, e);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) alpha[c] = quad_bcast(e[c], (t + 1) & 3);
       }
       ++t;
     }
     const int tn = t;
-    if (won >= 0) {
-      // S column of this round's pivot: rows above the pivot row as they
-      // were when it was chosen, beta on it, zeros below
-      const double* __restrict__ ml = mask_ge(L, won);
-      const double* __restrict__ mq = mask_eq(L, won);
-      double2* st = reinterpret_cast<double2*>(L.slog + won * LMAX);
-#pragma unroll
-      for (int i = 0; i < LMAX / 2; ++i)
-        st[i] = make_double2(fma(x[2 * i], 1.0 - ml[2 * i], beta_w * mq[2 * i]),
-                             fma(x[2 * i + 1], 1.0 - ml[2 * i + 1], beta_w * mq[2 * i + 1]));
-    }
     __syncthreads();
     for (int s = t0; s < tn; ++s) {
       if (c_s == L.pphys[s]) sel_s = true;
       else if (pos_s == s) pos_s = L.plog[s];
     }
     if (me == 0 && tid >= t0 && tid < tn) a.piv[tid] = L.plog[tid];
+    // the round's reflectors in row order, for the later scans
+    for (int e = tid; e < (tn - t0) * LMAX; e += SQ_T) {
+      const int st = t0 + e / LMAX, r = e % LMAX;
+      L.vlog[st * LMAX + r] = L.vq[st * LMAX + (r & 3) * (LMAX / 4) + (r >> 2)];
+    }
+    __syncthreads();
+    // S columns of this round's pivots (quad layout): rows above the pivot
+    // row as they were when it was chosen, beta on it, zeros below
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int wt = L.wonstep[(tid & ~3) + c];
+      if (wt >= 0) {
+        const double bw = L.betas[wt];
+        double2* st = reinterpret_cast<double2*>(L.vq + wt * LMAX + q * RQ);
+#pragma unroll
+        for (int i2 = 0; i2 < RQ / 2; ++i2) {
+          double e[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int r = 4 * (2 * i2 + h) + q;
+            e[h] = (r < wt) ? x[c][2 * i2 + h] : ((r == wt) ? bw : 0.0);
+          }
+          st[i2] = make_double2(e[0], e[1]);
+        }
+      }
+    }
+
     if (tn == t0) {  // no candidate left although steps remain: cannot happen for bJ <= nJ
       if (tid == 0) atomicExch(a.err, 1);
       return;
@@ -569,7 +830,10 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
   // owns those physical columns, and its own reads of them are done)
   if (me == 0) {
     __syncthreads();
-    for (int e = tid; e < a.bJ * LMAX; e += SQ_T) a.S[e] = L.slog[e];
+    for (int e = tid; e < a.bJ * LMAX; e += SQ_T) {
+      const int j = e / LMAX, r = e % LMAX;
+      a.S[e] = L.vq[j * LMAX + (r & 3) * (LMAX / 4) + (r >> 2)];
+    }
   }
 }
 
