@@ -8,6 +8,7 @@
 // LMAX contiguous doubles at S + c * LMAX, so a thread that owns a column
 // reads and writes it with 16-byte accesses at immediate offsets.
 #include <float.h>
+#include <type_traits>
 #include "kernels.hpp"
 
 namespace rq {
@@ -307,26 +308,61 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
+// Exchanges across rows of 16 lanes and across the wave halves (gfx950
+// v_permlane16_swap / v_permlane32_swap): with both operands the same value,
+// the two results hold the value of the lane itself and of its partner
+// row (half), in some order.
+__device__ __forceinline__ double xrow16_max(double v) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return fmax(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+}
+__device__ __forceinline__ double xrow32_max(double v) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return fmax(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+}
+__device__ __forceinline__ int dpp_pull_i(int v, int ctrl_id) {
+  switch (ctrl_id) {
+    case 0: return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);
+  }
+}
+
+// Maximum over the wave: DPP within rows of 16 lanes, then row and half
+// exchanges.  Every lane gets the result.
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_pull(v, 0));
   v = fmax(v, dpp_pull(v, 1));
   v = fmax(v, dpp_pull(v, 2));
   v = fmax(v, dpp_pull(v, 3));
-  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+  v = xrow16_max(v);
+  return xrow32_max(v);
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+  v = min(v, dpp_pull_i(v, 0));
+  v = min(v, dpp_pull_i(v, 1));
+  v = min(v, dpp_pull_i(v, 2));
+  v = min(v, dpp_pull_i(v, 3));
+  {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = min((int)r[0], (int)r[1]);
+  }
+  {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    v = min((int)r[0], (int)r[1]);
+  }
+  return v;
 }
 
 // Wave-level (value, position) argmax: the largest value, ties to the lowest
 // position.  Values must not be NaN.  Uniform result.
 __device__ __forceinline__ void wave_argmax_vp(double v, int p, double& bv, int& bp) {
-  bv = wave_max(v);
-  unsigned long long m = __ballot(v == bv && p != INT_MAX);
-  int best = INT_MAX;
-  while (m) {
-    const int ln = __builtin_ctzll(m);
-    m &= m - 1;
-    best = min(best, __builtin_amdgcn_readlane(p, ln));
-  }
-  bp = best;
+  bv = uni(wave_max(v));
+  bp = uni(wave_min_i((v == bv) ? p : INT_MAX));
 }
 
 // Quad lanes (tid & ~3 .. tid | 3) exchange values with DPP quad permutes.
@@ -350,6 +386,35 @@ __device__ __forceinline__ double quad_bcast(double v, int qs) {
     case 2: return qperm<0xAA>(v);
     default: return qperm<0xFF>(v);
   }
+}
+
+// Value of lane ^ STRIDE (STRIDE a power of two below 64) without LDS: DPP
+// within rows of 16 lanes, gfx950 permlane swaps across rows and halves
+// (with both operands equal, result 1 holds the partner row's value in the
+// even rows and result 0 in the odd rows).
+template <int STRIDE>
+__device__ __forceinline__ int xchg_i(int v, int lane) {
+  if constexpr (STRIDE == 1) {
+    return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  } else if constexpr (STRIDE == 2) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  } else if constexpr (STRIDE == 4) {
+    const int up = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xF, 0xF, false);   // row_shl:4 (lane + 4)
+    const int dn = __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false);   // row_shr:4 (lane - 4)
+    return (lane & 4) ? dn : up;
+  } else if constexpr (STRIDE == 8) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (STRIDE == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) ? (int)r[0] : (int)r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? (int)r[0] : (int)r[1];
+  }
+}
+template <int STRIDE>
+__device__ __forceinline__ double xchg_d(double v, int lane) {
+  return __hiloint2double(xchg_i<STRIDE>(__double2hiint(v), lane), xchg_i<STRIDE>(__double2loint(v), lane));
 }
 
 // Row-quad helpers: x[c][i] is row 4 i + q (q = quad lane) of column c.
@@ -445,6 +510,8 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
   const double kv = mine ? ranked(nu) : -INFINITY;
   const int kp = mine ? pos_s : INT_MAX;
   if (tid == 0) { L.bad = 0; L.nvalid = SQ_T; }
+  int rank = SQ_T;
+  {
   // rank of this column among the slab: the number of columns that beat it
   // (larger trailing norm, ties to the lower position); the K best become
   // candidates and the one of rank K gives theta.  Each wave sorts its 64
@@ -455,22 +522,35 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
     const int lane = tid & (WAVE - 1), w = tid / WAVE;
     double sv = kv;
     int sp = kp, sl = tid;
-#pragma unroll
-    for (int size = 2; size <= WAVE; size <<= 1) {
-#pragma unroll
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        const double ov = __shfl_xor(sv, stride, WAVE);
-        const int op = __shfl_xor(sp, stride, WAVE);
-        const int ol = __shfl_xor(sl, stride, WAVE);
-        // in a best-first run the lower lane of a pair keeps the better key,
-        // in a best-last run the worse one
-        const bool lower = (lane & stride) == 0;
-        const bool best_first = (lane & size) == 0;
-        const bool ob = beats(ov, op, sv, sp) != 0;
-        const bool take = (lower == best_first) ? ob : !ob && (ov != sv || op != sp);
-        if (take) { sv = ov; sp = op; sl = ol; }
-      }
-    }
+    // in a best-first run the lower lane of a pair keeps the better key, in
+    // a best-last run the worse one
+    auto stage = [&](auto size_c, auto stride_c) __attribute__((always_inline)) {
+      constexpr int SIZE = decltype(size_c)::value, STRIDE = decltype(stride_c)::value;
+      const double ov = xchg_d<STRIDE>(sv, lane);
+      const int op = xchg_i<STRIDE>(sp, lane);
+      const int ol = xchg_i<STRIDE>(sl, lane);
+      const bool lower = (lane & STRIDE) == 0;
+      const bool best_first = (lane & SIZE) == 0;
+      const bool ob = beats(ov, op, sv, sp) != 0;
+      const bool take = (lower == best_first) ? ob : (!ob && (ov != sv || op != sp));
+      sv = take ? ov : sv;
+      sp = take ? op : sp;
+      sl = take ? ol : sl;
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    using I8 = std::integral_constant<int, 8>;
+    using I16 = std::integral_constant<int, 16>;
+    using I32 = std::integral_constant<int, 32>;
+    using I64 = std::integral_constant<int, 64>;
+    stage(I2{}, I1{});
+    stage(I4{}, I2{}); stage(I4{}, I1{});
+    stage(I8{}, I4{}); stage(I8{}, I2{}); stage(I8{}, I1{});
+    stage(I16{}, I8{}); stage(I16{}, I4{}); stage(I16{}, I2{}); stage(I16{}, I1{});
+    stage(I32{}, I16{}); stage(I32{}, I8{}); stage(I32{}, I4{}); stage(I32{}, I2{}); stage(I32{}, I1{});
+    stage(I64{}, I32{}); stage(I64{}, I16{}); stage(I64{}, I8{}); stage(I64{}, I4{}); stage(I64{}, I2{});
+    stage(I64{}, I1{});
     L.kv[tid] = sv;
     L.kp[tid] = sp;
     __syncthreads();
@@ -496,7 +576,9 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
     if (sp == INT_MAX) atomicMin(&L.nvalid, rk);  // empty entries rank after all valid ones
   }
   __syncthreads();
-  const int rank = L.rk[tid];
+  rank = L.rk[tid];
+  }
+  __syncthreads();
   if (L.bad && tid == 0 && a.info) atomicCAS(a.info, 0, a.info_base + t0 + 1);
   const int nvalid = L.nvalid;  // min over empty entries of their rank, or SQ_T
   double* cb = a.cand + (size_t)buf * SQ_LCAP * SQ_T;
@@ -666,7 +748,9 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
       for (int w = 1; w < SQ_T / WAVE; ++w) {
         const double vw = uni(L.rv[par][w]);
         const int pw = uni(L.rp[par][w]);
-        if (better(vw, pw, v, p)) { v = vw; p = pw; }
+        const bool bw = beats(vw, pw, v, p);
+        v = bw ? vw : v;
+        p = bw ? pw : p;
       }
       if ((t > t0 && !(v > bound)) || p == INT_MAX) break;
       double* vt = L.vq + t * LMAX;
