@@ -110,6 +110,24 @@ __device__ __forceinline__ void sm_mm(const double* A, const double* B, int M, i
 // four waves.
 constexpr int SM_NB = 16;
 
+// 1 / a (a >= 1 here): hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(r, fma(-a, r, 1.0), r);
+  r = fma(r, fma(-a, r, 1.0), r);
+  return r;
+}
+
+// 1 / sqrt(a), a > 0: hardware estimate and two Newton steps
+// y <- y (3 - a y^2) / 2.
+__device__ __forceinline__ double rsqrt_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  const double h = 0.5 * a;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
 __device__ __forceinline__ double lane_val(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -135,7 +153,7 @@ __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
         const double d = lane_val(a[i], p);
         ok = ok && (d > 0.0);
         const double dd = (d > 0.0) ? d : 1.0;
-        const double sd = sqrt(dd), isd = 1.0 / sd;
+        const double isd = rsqrt_nr(dd), sd = dd * isd;
         const double r = (c > p) ? a[i] * isd : ((c == p) ? sd : 0.0);  // R(p, c)
         a[i] = r;
 #pragma unroll
@@ -189,7 +207,7 @@ __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_
           } else {
             const double sg = (c0 >= 0.0) ? -1.0 : 1.0;
             const double piv = 1.0 + fabs(c0);
-            const double f = -sg / piv;
+            const double f = -sg * rcp_nr(piv);
             const double l = (r > p) ? a[i] * f : 0.0;  // L(r, p)
             a[i] = (r > p) ? l : ((r == p) ? piv : a[i]);
 #pragma unroll
@@ -222,51 +240,50 @@ __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_
 }
 
 // Inverse of an upper-triangular matrix by recursive doubling:
-// inv([A B; 0 C]) = [inv(A), -inv(A) B inv(C); 0, inv(C)], block size 1, 2, ..., 32.
-// Blocks of 1..8 by scalar loops, 16 and 32 on the matrix cores.  R and Ri
+// inv([A B; 0 C]) = [inv(A), -inv(A) B inv(C); 0, inv(C)], block size 16, 32.
+// The four diagonal 16 x 16 blocks by back substitution (one wave each), the
+// doubling levels on the matrix cores.  R and Ri
 // must differ; W is scratch (SM_N * SM_LD).  Returns false if a diagonal
 // entry is zero.
 __device__ __forceinline__ bool sm_tri_inv(const double* R, double* Ri, double* W, int* flag) {
-  const int r = sm_r(), cg = sm_cg();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x == 0) *flag = 0;
-  __syncthreads();
-  for (int c = cg; c < SM_N; c += SM_T / SM_N) {
-    double v = 0.0;
-    if (r == c) {
-      const double d = R[r + r * SM_LD];
-      if (d == 0.0) *flag = 1;
-      v = (d != 0.0) ? 1.0 / d : 0.0;
-    }
-    Ri[r + c * SM_LD] = v;
+  // blocks below the diagonal blocks are zero
+  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+    const int i = e & (SM_N - 1), j = e >> 6;
+    if ((i >> 4) > (j >> 4)) Ri[i + j * SM_LD] = 0.0;
   }
   __syncthreads();
+  {
+    // diagonal block w, one wave: lane j < 16 holds column j of the block
+    // and forms column j of its inverse by back substitution, taking the
+    // other columns' entries with v_readlane
+    const int o = SM_NB * w, j = lane & 15;
+    double r[SM_NB], x[SM_NB];
 #pragma unroll
-  for (int ls = 0; ls < 4; ++ls) {
-    constexpr int dummy = 0;
-    (void)dummy;
-    const int sz = 1 << ls;
-    const int nel = (SM_N / 2) * sz;  // pairs * sz * sz
-    for (int e = threadIdx.x; e < nel; e += SM_T) {
-      const int i = e & (sz - 1), j = (e >> ls) & (sz - 1), q = e >> (2 * ls);
-      const int i0 = 2 * sz * q, c0 = i0 + sz;
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k <= j && k < sz) acc += R[(i0 + i) + (c0 + k) * SM_LD] * Ri[(c0 + k) + (c0 + j) * SM_LD];
-      W[(i0 + i) + (c0 + j) * SM_LD] = acc;
+    for (int i = 0; i < SM_NB; ++i) {
+      r[i] = R[(o + i) + (o + j) * SM_LD];
+      x[i] = (i == j) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nel; e += SM_T) {
-      const int i = e & (sz - 1), j = (e >> ls) & (sz - 1), q = e >> (2 * ls);
-      const int i0 = 2 * sz * q, c0 = i0 + sz;
-      double acc = 0.0;
+    double dj = 0.0;
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k >= i && k < sz) acc += Ri[(i0 + i) + (i0 + k) * SM_LD] * W[(i0 + k) + (c0 + j) * SM_LD];
-      Ri[(i0 + i) + (c0 + j) * SM_LD] = -acc;
+    for (int i = 0; i < SM_NB; ++i)
+      if (i == j) dj = r[i];
+    if (lane < SM_NB && dj == 0.0) *flag = 1;
+    const double rdj = (dj != 0.0) ? 1.0 / dj : 0.0;
+#pragma unroll
+    for (int k = SM_NB - 1; k >= 0; --k) {
+      const double xk = x[k] * lane_val(rdj, k);
+      x[k] = xk;
+#pragma unroll
+      for (int i = 0; i < k; ++i) x[i] = fma(-lane_val(r[i], k), xk, x[i]);
     }
-    __syncthreads();
+    if (lane < SM_NB) {
+#pragma unroll
+      for (int i = 0; i < SM_NB; ++i) Ri[(o + i) + (o + j) * SM_LD] = x[i];
+    }
   }
+  __syncthreads();
   for (int sz = 16; sz <= 32; sz <<= 1) {
     const int nb = SM_N / (2 * sz), boff = 2 * sz * (1 + SM_LD);
     // W = B inv(C) for each pair of diagonal blocks
@@ -339,6 +356,20 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
   __shared__ int flag;
   __shared__ int s_skip;
   __shared__ double sgn[SM_N];
+  __shared__ double wmax[SM_T / 64];
+  // All three inputs are read up front (thread (r, cg) holds entries
+  // (r, cg + 4 q)), so their latencies overlap.
+  const int r = sm_r(), cg = sm_cg();
+  double g2r[SM_N / 4], q1r[SM_N / 4], hr[SM_N / 4];
+#pragma unroll
+  for (int q = 0; q < SM_N / 4; ++q) {
+    const int c = cg + 4 * q;
+    const bool in = r < b && c < b;
+    const double id = (r == c) ? 1.0 : 0.0;
+    g2r[q] = in ? G2[r + (int64_t)c * b] : id;
+    q1r[q] = in ? Q1[r + (int64_t)c * ldq] : id;
+    hr[q] = in ? H[r + (int64_t)c * b] : 0.0;
+  }
   if (threadIdx.x == 0) s_skip = *st;
   __syncthreads();
   if (s_skip) return;
@@ -346,66 +377,63 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
   double* B = sm + SM_N * SM_LD;
   double* C = sm + 2 * SM_N * SM_LD;
   double* D = sm + 3 * SM_N * SM_LD;
-  // R2 = chol(G2); G2 must be close to the identity after the first pass
-  sm_load(A, G2, 1, b, b, false);
-  __syncthreads();
-  __shared__ unsigned long long emax_bits;
-  if (threadIdx.x == 0) {
-    flag = 0;
-    emax_bits = 0ull;
-  }
-  __syncthreads();
+  // E = G2 - I; its largest entry decides how R2 = chol(G2) is formed (G2
+  // must be close to the identity after the first pass)
   {
-    // E = G2 - I; its largest entry decides between the closed form below
-    // and a full Cholesky (bit patterns of non-negative doubles order like
-    // the values)
     double em = 0.0;
-    const int r = sm_r();
-    for (int c = sm_cg(); c < SM_N; c += SM_T / SM_N) em = fmax(em, fabs(A[r + c * SM_LD] - (r == c ? 1.0 : 0.0)));
-    if (!(em <= 0.25)) flag = 1;
-    atomicMax(&emax_bits, (unsigned long long)__double_as_longlong(em));
+#pragma unroll
+    for (int q = 0; q < SM_N / 4; ++q) em = fmax(em, fabs(g2r[q] - ((r == cg + 4 * q) ? 1.0 : 0.0)));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) em = fmax(em, __shfl_xor(em, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = em;
+    if (threadIdx.x == 0) flag = 0;
   }
   __syncthreads();
-  if (flag) {
+  const double emax = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+  if (!(emax <= 0.25)) {
     if (threadIdx.x == 0) atomicOr(st, ST_ORTH);
     return;
   }
-  const double emax = __longlong_as_double((long long)emax_bits);
-  if (emax <= 1e-6) {
-    // G2 = I + E with E tiny: R2 = I + F, F = U(E) - U(F^T F) (U: strict
-    // upper part plus half the diagonal) gives F = U0 - U(U0^T U0) with
-    // error O(|E|^3), and R2^-1 = I - F + F^2 with error O(|F|^3) -- both
-    // far below rounding at |E| <= 1e-6.  B = U0, then A = F, then B = R2^-1.
-    {
-      const int r = sm_r();
-      for (int c = sm_cg(); c < SM_N; c += SM_T / SM_N) {
-        const double e = A[r + c * SM_LD] - (r == c ? 1.0 : 0.0);
-        B[r + c * SM_LD] = (r < c) ? e : ((r == c) ? 0.5 * e : 0.0);
-      }
+  if (emax <= 1e-10) {
+    // R2 = I + F with F = U(E) - U(F^T F) (U: strict upper part plus half
+    // the diagonal) and R2^-1 = I - F + F^2 - ...; at |E| <= 1e-10 every
+    // term past U(E) is below 64 |E|^2 < 1e-18, so R2^-1 = I - U(E).
+#pragma unroll
+    for (int q = 0; q < SM_N / 4; ++q) {
+      const int c = cg + 4 * q;
+      const double e = g2r[q] - ((r == c) ? 1.0 : 0.0);
+      B[r + c * SM_LD] = (r < c) ? -e : ((r == c) ? 1.0 - 0.5 * e : 0.0);
+    }
+    __syncthreads();
+  } else if (emax <= 1e-6) {
+    // G2 = I + E with E tiny: R2 = I + F, F = U(E) - U(F^T F) gives
+    // F = U0 - U(U0^T U0) with error O(|E|^3), and R2^-1 = I - F + F^2 with
+    // error O(|F|^3) -- both far below rounding at |E| <= 1e-6.  B = U0,
+    // then A = F, then B = R2^-1.
+#pragma unroll
+    for (int q = 0; q < SM_N / 4; ++q) {
+      const int c = cg + 4 * q;
+      const double e = g2r[q] - ((r == c) ? 1.0 : 0.0);
+      B[r + c * SM_LD] = (r < c) ? e : ((r == c) ? 0.5 * e : 0.0);
     }
     __syncthreads();
     sm_mm<true>(B, B, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) { D[i + j * SM_LD] = v; });
     __syncthreads();
-    {
-      const int r = sm_r();
-      for (int c = sm_cg(); c < SM_N; c += SM_T / SM_N) {
-        const double u = (r < c) ? D[r + c * SM_LD] : ((r == c) ? 0.5 * D[r + c * SM_LD] : 0.0);
-        A[r + c * SM_LD] = B[r + c * SM_LD] - u;
-      }
+    for (int c = cg; c < SM_N; c += SM_T / SM_N) {
+      const double u = (r < c) ? D[r + c * SM_LD] : ((r == c) ? 0.5 * D[r + c * SM_LD] : 0.0);
+      A[r + c * SM_LD] = B[r + c * SM_LD] - u;
     }
     __syncthreads();
     sm_mm<false>(A, A, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) { D[i + j * SM_LD] = v; });
     __syncthreads();
-    {
-      const int r = sm_r();
-      for (int c = sm_cg(); c < SM_N; c += SM_T / SM_N)
-        B[r + c * SM_LD] = (r == c ? 1.0 : 0.0) - A[r + c * SM_LD] + D[r + c * SM_LD];
-    }
+    for (int c = cg; c < SM_N; c += SM_T / SM_N)
+      B[r + c * SM_LD] = (r == c ? 1.0 : 0.0) - A[r + c * SM_LD] + D[r + c * SM_LD];
     __syncthreads();
   } else {
-    for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {  // keep the upper triangle
-      const int i = e % SM_N, j = e / SM_N;
-      if (i > j) A[i + j * SM_LD] = 0.0;
+#pragma unroll
+    for (int q = 0; q < SM_N / 4; ++q) {  // the upper triangle
+      const int c = cg + 4 * q;
+      A[r + c * SM_LD] = (r <= c) ? g2r[q] : 0.0;
     }
     __syncthreads();
     if (!sm_chol(A, &flag)) {
@@ -419,16 +447,16 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
     }
   }
   // A = Q_top = Q1(0:b, 0:b) R2^-1 (full b x b); Q1's top block is staged
-  // in C first so the products read LDS only
-  sm_load(C, Q1, 1, ldq, b, false);
+  // in C first so the products read LDS only; D = H
+#pragma unroll
+  for (int q = 0; q < SM_N / 4; ++q) {
+    const int c = cg + 4 * q;
+    C[r + c * SM_LD] = q1r[q];
+    D[r + c * SM_LD] = hr[q];
+  }
   __syncthreads();
   sm_mm<false>(C, B, SM_N, SM_N, SM_N, 1, 0,
                [&](int, int i, int j, double v) { A[i + j * SM_LD] = (i < b && j < b) ? v : 0.0; });
-  // D = H (full b x b)
-  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
-    const int i = e % SM_N, j = e / SM_N;
-    D[i + j * SM_LD] = (i < b && j < b) ? H[i + (int64_t)j * b] : 0.0;
-  }
   __syncthreads();
   // LU of E - Q S by right-looking elimination on Q alone: at step i the
   // pivot column c = Q'(i:, i); S_ii = -sign(c_0) (sign(0) = +1); pivot
@@ -461,10 +489,12 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
     }
   });
   __syncthreads();
-  // B = -R2^-1 S (columns scaled), kept in the global M3 scratch meanwhile
-  for (int e = threadIdx.x; e < b * b; e += SM_T) {
-    const int i = e % b, j = e / b;
-    M3[i + (int64_t)j * b] = (i <= j) ? -sgn[j] * B[i + j * SM_LD] : 0.0;
+  // -R2^-1 S (columns scaled), kept in registers meanwhile (padding zero)
+  double m3r[SM_N / 4];
+#pragma unroll
+  for (int q = 0; q < SM_N / 4; ++q) {
+    const int c = cg + 4 * q;
+    m3r[q] = (r <= c && r < b && c < b) ? -sgn[c] * B[r + c * SM_LD] : 0.0;
   }
   for (int i = threadIdx.x; i < b; i += SM_T) tau[i] = C[i + i * SM_LD];
   // D = Y1^T (unit upper) padded
@@ -488,7 +518,8 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
     if (threadIdx.x == 0) atomicOr(st, ST_PIVOT);
     return;
   }
-  sm_load(B, M3, 1, b, b, true);
+#pragma unroll
+  for (int q = 0; q < SM_N / 4; ++q) B[r + (cg + 4 * q) * SM_LD] = m3r[q];
   __syncthreads();
   sm_mm<false>(B, A, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
     if (i < b && j < b) M3[i + (int64_t)j * b] = v;
