@@ -80,6 +80,39 @@ template <bool TA, class Epi>
 __device__ __forceinline__ void sm_mm(const double* A, const double* B, int M, int N, int K, int nb, int boff,
                                       Epi epi) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (M == SM_N && N == SM_N && nb == 1) {
+    // full 64 x 64: wave w takes the 32 x 32 quadrant (w & 1, w >> 1) as
+    // 2 x 2 tiles, so each operand fragment read from LDS feeds two MFMAs
+    const int i0 = 32 * (w & 1), j0 = 32 * (w >> 1);
+    double4_t acc[2][2];
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int b2 = 0; b2 < 2; ++b2) acc[a2][b2] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    const int ia = i0 + (lane & 15), jb = j0 + (lane & 15);
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int ka = k0 + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int a2 = 0; a2 < 2; ++a2) af[a2] = TA ? A[ka + (ia + 16 * a2) * SM_LD] : A[(ia + 16 * a2) + ka * SM_LD];
+#pragma unroll
+      for (int b2 = 0; b2 < 2; ++b2) bf[b2] = B[ka + (jb + 16 * b2) * SM_LD];
+#pragma unroll
+      for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2)
+          acc[a2][b2] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b2], af[a2], acc[a2][b2], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          epi(0, ia + 16 * a2, j0 + 16 * b2 + 4 * r + (lane >> 4), acc[a2][b2][r]);
+    return;
+  }
   const int tm = M >> 4, tn = N >> 4, per = tm * tn;
   for (int t = w; t < nb * per; t += SM_T / 64) {
     const int bi = t / per, tt = t - bi * per;
@@ -140,7 +173,8 @@ __device__ __forceinline__ double lane_val(double v, int lane) {
 __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
   if (threadIdx.x == 0) *flag = 0;
   __syncthreads();
-  for (int k0 = 0; k0 < SM_N; k0 += SM_NB) {
+#pragma unroll
+  for (int k0 = 0; k0 < SM_N; k0 += SM_NB) {  // unrolled: every lane index below is a constant
     if (threadIdx.x < SM_N) {
       const int c = threadIdx.x;
       double a[SM_NB];
@@ -158,6 +192,7 @@ __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
         a[i] = r;
 #pragma unroll
         for (int q = i + 1; q < SM_NB; ++q) a[q] = fma(-lane_val(r, k0 + q), r, a[q]);
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int i = 0; i < SM_NB; ++i) G[(k0 + i) + c * SM_LD] = (c >= k0 + i) ? a[i] : 0.0;
@@ -186,7 +221,9 @@ __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
 // Block k0: lane r holds A(r, k0:k0+16) (the column panel: L and the
 // diagonal block) and A(k0:k0+16, r) for r >= k0 + 16 (the row band of U).
 __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_t mJ) {
-  for (int k0 = 0; k0 < b; k0 += SM_NB) {
+#pragma unroll
+  for (int k0 = 0; k0 < SM_N; k0 += SM_NB) {  // unrolled: every lane index below is a constant
+    if (k0 >= b) break;
     if (threadIdx.x < SM_N) {
       const int r = threadIdx.x;
       const bool band = r >= k0 + SM_NB;
@@ -218,6 +255,7 @@ __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_
             if (r == 0) sgn[p] = sg;
           }
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int j = 0; j < SM_NB; ++j) {
@@ -277,6 +315,9 @@ __device__ __forceinline__ bool sm_tri_inv(const double* R, double* Ri, double* 
       x[k] = xk;
 #pragma unroll
       for (int i = 0; i < k; ++i) x[i] = fma(-lane_val(r[i], k), xk, x[i]);
+      // keep the scheduler from hoisting later steps' v_readlane results
+      // (scalar registers would spill)
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (lane < SM_NB) {
 #pragma unroll
