@@ -110,12 +110,89 @@ def copy_calibration(mib):
                       "launches": 3}), flush=True)
 
 
+def run_c3(args):
+    """TRQRCP and TUXV (fp64) at rank k = 256 on the 20000 x 10000 matrix with
+    sigma_i = 0.9^(i/10): solves/s and p99 latency of TUXV over the timed
+    solves, TRQRCP time, and the truncation error against the Eckart-Young
+    optimum (evaluated after the timed region)."""
+    import torch
+    from paper_1509_06820_amd import binding, inputs
+    A_host, prm = inputs.config_matrix("c3")
+    k, b, p, seed = prm["k"], prm["b"], prm["p"], prm["seed"]
+    m, n = A_host.shape
+    A = torch.from_numpy(A_host).cuda()
+    W, K = args.warmup, args.steps
+    print(f"[bench] workload c3 {m}x{n} k={k} b={b} p={p}: {W} warmup + {K} timed solves", file=sys.stderr,
+          flush=True)
+    stream = torch.cuda.current_stream()
+    w_trq = binding.workspace(binding.RQ_OP_TRQRCP, m, n, k, b, p, A.device)
+    w_tux = binding.workspace(binding.RQ_OP_TUXV, m, n, k, b, p, A.device)
+    for _ in range(W):
+        binding.rq_trqrcp(A, k, b, p, seed, work=w_trq)
+        binding.rq_tuxv(A, k, b, p, seed, work=w_tux)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    trq = []
+    for i in range(K):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        binding.rq_trqrcp(A, k, b, p, seed, work=w_trq)
+        e1.record(stream)
+        trq.append((e0, e1))
+    torch.cuda.synchronize()
+    res = None
+    for i in range(K):
+        ev[i][0].record(stream)
+        res = binding.rq_tuxv(A, k, b, p, seed, work=w_tux)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    lat = np.array([a.elapsed_time(z) for a, z in ev])
+    trq_ms = float(np.mean([a.elapsed_time(z) for a, z in trq]))
+    U, s, VT, info = res
+    assert int(info.item()) == 0, int(info.item())
+    err = (torch.linalg.norm(A - (U * s) @ VT) / torch.linalg.norm(A)).item()
+    opt = inputs.optimal_truncation_error(inputs.sigma_power(10000, 0.9, 10.0), k)
+    ms = float(lat.mean())
+    # TUXV flops: the TRQRCP(k) products (2kmn), Z = A V (2mnk), the sketch (2lmn)
+    flops = 2.0 * k * m * n + 2.0 * m * n * k + 2.0 * (b + p) * m * n
+    line = {
+        "metric": METRIC,
+        "value": round(1e3 / ms, 3),
+        "unit": "TUXV solves/s (fp64, 20000x10000, k=256)",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms, 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "tuxv_c3", "m": m, "n": n, "k": k, "b": b, "p": p, "seed": seed,
+                   "inputs": "U diag(0.9^(i/10)) V^T, Haar factors"},
+        "tuxv_gflops": round(flops / (ms * 1e-3) / 1e9, 2),
+        "trqrcp_ms": round(trq_ms, 3),
+        "truncation_error": err,
+        "optimal_error": opt,
+        "error_over_optimum": round(err / opt, 6),
+    }
+    gold = os.path.join(ROOT, "tests", "golden", "c3_tuxv_oracle_error.txt")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            for ln in f:
+                if ln.startswith("oracle_error:"):
+                    line["oracle_error"] = float(ln.split(":", 1)[1])
+                    line["error_over_oracle"] = round(err / line["oracle_error"], 6)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2_iid", choices=["c2_iid", "c2_lr", "c1"])
+    ap.add_argument("--workload", default="c2_iid", choices=["c2_iid", "c2_lr", "c1", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=3)
     ap.add_argument("--check", action="store_true", help="residual of the last factorization (untimed)")
@@ -136,6 +213,9 @@ def main():
     from paper_1509_06820_amd import binding, inputs
 
     torch.cuda.set_device(0)
+    if args.workload == "c3":
+        run_c3(args)
+        return
     A_host, prm = inputs.config_matrix(args.workload)
     b, p, seed = prm["b"], prm["p"], prm["seed"]
     m, n = A_host.shape

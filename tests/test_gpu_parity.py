@@ -11,6 +11,7 @@ Bars (derived in DESIGN.md):
   TRQRCP) bit-exact.
 """
 
+import os
 import sys
 
 import numpy as np
@@ -304,3 +305,48 @@ def test_rqrcp_8192_full_size_gaussian():
     say(f"8192 residual {res:.3e} orthogonality {orth:.3e}")
     assert res <= 1e-12
     assert orth <= 1e-12
+
+
+def test_trqrcp_tuxv_c3_full_size():
+    """20000 x 10000, sigma_i = 0.9^(i/10), k = 256, b = 64, p = 8, seed 3
+    (the benchmark's TRQRCP/TUXV launch): the first block's pivots against
+    the oracle's TRQRCP(64); on the GPU, the residual of the k factored
+    columns, the orthonormality of U and V, and the truncation error of TUXV
+    within 1.05x of the oracle's (stored in tests/golden, written by
+    make_c3_tuxv_error.py from the oracle) and not below the Eckart-Young
+    optimum."""
+    say("trqrcp/tuxv 20000x10000 k=256 b=64 p=8 seed=3")
+    A, prm = inputs.config_matrix("c3")
+    k, b, p, seed = prm["k"], prm["b"], prm["p"], prm["seed"]
+    At = dev(A)
+    nrm = torch.linalg.norm(At).item()
+    F, tau, jpvt, info = binding.rq_trqrcp(At, k, b, p, seed)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    ref = oracle.trqrcp(A, b, b, p, seed=seed)
+    jp = host(jpvt)
+    t = trusted_prefix(ref["gaps"], b)
+    assert np.array_equal(jp[:t], ref["jpvt"][:t])
+    assert sorted(jp.tolist()) == list(range(A.shape[1]))
+    Qk = torch.linalg.householder_product(F[:, :k], tau)
+    res = (torch.linalg.norm(At[:, jpvt[:k]] - Qk @ torch.triu(F[:k, :k])) / nrm).item()
+    say(f"c3 trqrcp residual {res:.3e}")
+    assert res <= 1e-12
+    U, s, VT, info = binding.rq_tuxv(At, k, b, p, seed)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    eye = torch.eye(k, dtype=torch.float64, device="cuda")
+    assert torch.linalg.norm(U.T @ U - eye).item() <= orth_tol(k)
+    assert torch.linalg.norm(VT @ VT.T - eye).item() <= orth_tol(k)
+    sh = host(s)
+    assert np.all(np.diff(sh) <= 0) and sh[-1] >= 0
+    e = (torch.linalg.norm(At - (U * s) @ VT) / nrm).item()
+    opt = inputs.optimal_truncation_error(inputs.sigma_power(10000, 0.9, 10.0), k)
+    gold = {}
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_tuxv_oracle_error.txt")) as f:
+        for ln in f:
+            if ":" in ln and not ln.startswith("#"):
+                key, val = ln.split(":", 1)
+                gold[key.strip()] = float(val)
+    say(f"c3 tuxv error {e:.6f} oracle {gold['oracle_error']:.6f} optimum {opt:.6f}")
+    assert opt * (1 - 1e-9) <= e <= 1.05 * gold["oracle_error"]
