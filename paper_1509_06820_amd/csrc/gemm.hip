@@ -10,8 +10,9 @@
 // composition, the sample-update product W11 R12 and the TUXV products.
 //
 // Tiling: a workgroup of 256 threads (4 waves, WM x WN) owns a BM x BN tile of
-// C; operand tiles of depth BK are staged through LDS with register
-// prefetch of the next tile.  The MFMA is issued with its operands swapped
+// C (128 x 64 for the large updates, 64 x 64 otherwise); operand tiles of
+// depth BK are staged through two LDS buffers with register prefetch of the
+// next tile, and C is loaded into the accumulators before the k loop.  The MFMA is issued with its operands swapped
 // (B-fragment first) so that lane l, register r of a 16x16 accumulator holds
 // C(i0 + l%16, j0 + 4r + l/16): sixteen consecutive rows of one column of
 // the column-major C, which makes the C loads and stores 128-byte coalesced.
@@ -256,10 +257,11 @@ constexpr int64_t GRAM_MINK = 32;
 
 bool gram_mode(int64_t M, int64_t N, int64_t K) { return M <= 64 && N <= 128 && K >= 256; }
 
-// Short-wide outputs with a long reduction (b x n products Y^T A): 64 x 128
-// tiles, up to WIDE_MAXS splits of at least WIDE_MINK rows.
+// Short-wide outputs with a long reduction (b x n products Y^T A): 64 x 64
+// tiles, up to WIDE_MAXS splits of at least WIDE_MINK rows, aiming at about
+// 2048 workgroups (eight per CU).
 constexpr int WIDE_MAXS = 16;
-constexpr int64_t WIDE_MINK = 512;
+constexpr int64_t WIDE_MINK = 256;
 
 static bool wide_mode(int64_t M, int64_t K) { return M <= 64 && K >= 1024; }
 
@@ -285,7 +287,7 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
   constexpr int BK = 16;
   int splits = 1;
   int64_t kchunk = K;
-  enum { SMALL, BIG, WIDE } shape = SMALL;
+  enum { SMALL, BIG, WIDE } shape = SMALL;  // WIDE: split-K with the SMALL tiles
   bool many = false;
   if (scratch && gram_mode(M, N, K)) {
     kchunk = std::max<int64_t>(GRAM_MINK, (K + GRAM_MAXS - 1) / GRAM_MAXS);
@@ -297,10 +299,9 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
     }
     many = true;
   } else if (scratch && wide_mode(M, K)) {
-    // aim for >= 512 workgroups (two per CU), at least WIDE_MINK rows per split
     shape = WIDE;
-    const int64_t tiles = (N + 127) / 128;
-    const int64_t want = (512 + tiles - 1) / tiles;
+    const int64_t tiles = (N + 63) / 64;
+    const int64_t want = (2048 + tiles - 1) / tiles;
     const int64_t maxs = K / WIDE_MINK;
     splits = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, (int64_t)WIDE_MAXS}));
     while (splits > 1 && (size_t)splits * (size_t)M * (size_t)N > scratch_elems) --splits;
@@ -313,10 +314,7 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
   auto tiles = [&](double al, double be, double* out, int64_t ldo, int64_t stride) {
     switch (shape) {
       case BIG:
-        return launch_tiles<128, 128, BK, 2, 2>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo, splits, kchunk,
-                                                stride);
-      case WIDE:
-        return launch_tiles<64, 128, BK, 1, 4>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo, splits, kchunk,
+        return launch_tiles<128, 64, BK, 2, 2>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo, splits, kchunk,
                                                stride);
       default:
         return launch_tiles<64, 64, BK, 2, 2>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo, splits, kchunk,
