@@ -941,16 +941,18 @@ int launch_sq(hipStream_t s, SqParams& a) {
 }
 
 // ------------------------------------------------------------------ swaps
-constexpr int SW_ROWS = 64;
+constexpr int SW_ROWS = 16;  // rows per workgroup (8192 rows: 512 workgroups)
 
 __global__ void __launch_bounds__(256) apply_swaps_kernel(const int* __restrict__ piv, int bJ, int64_t offset,
                                                           double* M, int64_t ldm, int64_t rows, int64_t* jpvt) {
   __shared__ int dst[128], src[128];
   __shared__ int npair;
+  __shared__ int pv[SQ_BMAX];
   __shared__ double tile[128 * SW_ROWS];
   __shared__ int64_t itile[128];
   const int tid = threadIdx.x;
   if (tid == 0) npair = 0;
+  if (tid < bJ) pv[tid] = piv[tid];  // the swap list is read from global memory once
   __syncthreads();
   // Destinations: positions 0..bJ-1 and every partner p_t >= bJ (first occurrence).
   if (tid < 2 * bJ) {
@@ -959,17 +961,17 @@ __global__ void __launch_bounds__(256) apply_swaps_kernel(const int* __restrict_
       q = tid;
     } else {
       const int t = tid - bJ;
-      const int pt = piv[t];
+      const int pt = pv[t];
       bool first = pt >= bJ;
       for (int s2 = 0; s2 < t && first; ++s2)
-        if (piv[s2] == pt) first = false;
+        if (pv[s2] == pt) first = false;
       if (first) q = pt;
     }
     if (q >= 0) {
       // content of position q after the swaps: undo them from the last one
       int sidx = q;
       for (int s2 = bJ - 1; s2 >= 0; --s2) {
-        const int ps = piv[s2];
+        const int ps = pv[s2];
         if (sidx == s2) sidx = ps;
         else if (sidx == ps) sidx = s2;
       }
@@ -1131,6 +1133,7 @@ int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ,
 int launch_apply_swaps(hipStream_t s, const int* piv, int bJ, int64_t offset, double* M, int64_t ldm, int64_t rows,
                        int64_t* jpvt) {
   if (bJ <= 0) return 0;
+  if (bJ > SQ_BMAX) return -5;
   const unsigned grid = std::max<unsigned>(1u, blocks_for(rows, SW_ROWS));
   hipLaunchKernelGGL(apply_swaps_kernel, dim3(grid), dim3(256), 0, s, piv, bJ, offset, M, ldm, rows, jpvt);
   RQ_HIP(hipGetLastError());
