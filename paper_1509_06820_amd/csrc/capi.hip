@@ -419,6 +419,7 @@ struct TuxvWS {
   double* ux;      // k x k
   double* vx;      // k x k
   double* svdtmp;  // k x k
+  unsigned* svdflags;  // arrival counter and per-sweep flags of the Jacobi sweeps
 };
 
 void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS& t) {
@@ -441,6 +442,7 @@ void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS
   t.ux = cv.take<double>((size_t)k * k);
   t.vx = cv.take<double>((size_t)k * k);
   t.svdtmp = cv.take<double>((size_t)k * k);
+  t.svdflags = cv.take<unsigned>(128);
 }
 
 int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int b, int p,
@@ -472,7 +474,7 @@ int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, i
   RQ_TRY(form_q(s, m, k, b, t.qu, t.u1, m));
   // X = Ux diag(sigma) Vx^T
   SvdWork sw;
-  sw.colnorm = nullptr; sw.order = nullptr; sw.flags = nullptr; sw.err = t.trq.c.err; sw.tmp = t.svdtmp;
+  sw.colnorm = nullptr; sw.order = nullptr; sw.flags = t.svdflags; sw.err = t.trq.c.err; sw.tmp = t.svdtmp;
   {
     ProfScope ps(PC_SVD, s, 8.0 * 4 * k * k, 0.0);
     RQ_TRY(launch_jacobi_svd(s, (int)k, t.x, k, t.ux, k, sigma, t.vx, k, sw));
@@ -714,9 +716,11 @@ int rq_small_svd(void* stream, int32_t k, double* X, int64_t ldx, double* U, int
   Carve cv(work, work_bytes);
   double* tmp = cv.take<double>((size_t)k * k);
   int* err = cv.take<int>(16);
+  unsigned* flags = cv.take<unsigned>(128);
   if (!cv.ok) return -100;
+  RQ_TRY(launch_fill((hipStream_t)stream, err, 16));
   SvdWork sw;
-  sw.colnorm = nullptr; sw.order = nullptr; sw.flags = nullptr; sw.err = err; sw.tmp = tmp;
+  sw.colnorm = nullptr; sw.order = nullptr; sw.flags = flags; sw.err = err; sw.tmp = tmp;
   return launch_jacobi_svd((hipStream_t)stream, k, X, ldx, U, ldu, sigma, V, ldv, sw);
 }
 

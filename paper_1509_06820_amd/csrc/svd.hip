@@ -12,7 +12,9 @@
 // s = c t with a = |x_i|^2, b = |x_j|^2, g = x_i . x_j, and is skipped when
 // |g| <= tol sqrt(a b).  Sweeps stop after one without rotations.
 // Singular values are returned in descending order with U = X V / sigma
-// (a column with sigma == 0 is left zero).
+// (a column with sigma == 0 is left zero).  The rounds of a sweep run on up
+// to 256 workgroups (one column pair each, one row per thread) that meet
+// at an arrival barrier after every round.
 #include "kernels.hpp"
 
 namespace rq {
@@ -32,89 +34,144 @@ __device__ __forceinline__ void rr_pair(int r, int idx, int kk, int& p, int& q) 
   }
 }
 
-__device__ __forceinline__ double group_sum(double v, int tpp) {
-  for (int off = tpp >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+// Rotation sweeps spread over P workgroups (cooperative launch): in each
+// round a workgroup takes pairs idx = me, me + P, ... of the round-robin
+// order, one row per thread, and the workgroups meet at an arrival barrier
+// before the next round reads the rotated columns.  A workgroup that rotates
+// marks the sweep's flag; after the sweep's last barrier every workgroup
+// reads it, so all of them stop after the same sweep.
+// flags[0]: arrival counter, flags[1 + s]: sweep s rotated (zeroed by the
+// caller).
+constexpr int JW_T = 256;     // threads of a sweep workgroup (rows)
+constexpr int JW_RPT = 4;     // rows per thread: k <= 1024
+
+__device__ bool jw_barrier(unsigned* flags, int P, unsigned round, int* err) {
+  __shared__ int s_bad;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x < WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) {
+      __hip_atomic_fetch_add(&flags[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned target = round * (unsigned)P;
+      long spins = 0;
+      int bad = 0;
+      while (__hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > SPIN_LIMIT) { bad = 1; atomicExch(err, 1); break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      s_bad = bad;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(s_bad) == 0;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
   return v;
 }
 
-__global__ void __launch_bounds__(SVD_THREADS) jacobi_kernel(int k, double* X, int64_t ldx, double* V, int64_t ldv,
-                                                             double* U, int64_t ldu, double* sigma, double* Vout,
-                                                             int64_t ldvo, double tol, int max_sweeps) {
-  __shared__ int rotated;
-  __shared__ double sn[1024];
-  const int tid = threadIdx.x;
-  const int kk = k + (k & 1);
-  const int npairs = kk / 2;
-  int tpp = SVD_THREADS / max(npairs, 1);
-  int pw = 1;
-  while (pw * 2 <= tpp && pw < 64) pw *= 2;
-  tpp = pw;
-  const int groups = SVD_THREADS / tpp;
-  const int grp = tid / tpp, sub = tid % tpp;
-
-  for (int64_t e = tid; e < (int64_t)k * k; e += SVD_THREADS) {
-    const int64_t j = e / k, i = e - j * k;
-    V[i + j * ldv] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-
+__global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, int64_t ldx, double* V, int64_t ldv,
+                                                              double tol, int max_sweeps, unsigned* flags, int* err) {
+  if (earlier_failure(err)) return;
+  __shared__ double red[2][SVD_THREADS / WAVE][3];
+  const int P = gridDim.x, me = blockIdx.x, tid = threadIdx.x, w = tid / WAVE;
+  const int kk = k + (k & 1), npairs = kk / 2;
+  unsigned round = 0;
+  int par = 0;
   for (int sweep = 0; sweep < max_sweeps && kk > 1; ++sweep) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
     for (int r = 0; r < kk - 1; ++r) {
-      for (int idx = grp; idx < npairs; idx += groups) {
+      for (int idx = me; idx < npairs; idx += P) {
         int p, q;
         rr_pair(r, idx, kk, p, q);
         if (p >= k || q >= k) continue;
         const int i = min(p, q), j = max(p, q);
         double* xi = X + (int64_t)i * ldx;
         double* xj = X + (int64_t)j * ldx;
-        double sa = 0.0, sb = 0.0, sg = 0.0;
-        for (int row = sub; row < k; row += tpp) {
-          const double u = xi[row], w = xj[row];
-          sa += u * u;
-          sb += w * w;
-          sg += u * w;
+        double u[JW_RPT], v[JW_RPT];
+#pragma unroll
+        for (int e = 0; e < JW_RPT; ++e) {
+          const int row = tid + e * JW_T;
+          u[e] = (row < k) ? xi[row] : 0.0;
+          v[e] = (row < k) ? xj[row] : 0.0;
         }
-        sa = group_sum(sa, tpp);
-        sb = group_sum(sb, tpp);
-        sg = group_sum(sg, tpp);
+        double sa = 0.0, sb = 0.0, sg = 0.0;
+#pragma unroll
+        for (int e = 0; e < JW_RPT; ++e) {
+          sa = fma(u[e], u[e], sa);
+          sb = fma(v[e], v[e], sb);
+          sg = fma(u[e], v[e], sg);
+        }
+        sa = wave_sum(sa);
+        sb = wave_sum(sb);
+        sg = wave_sum(sg);
+        if ((tid & (WAVE - 1)) == 0) {
+          red[par][w][0] = sa;
+          red[par][w][1] = sb;
+          red[par][w][2] = sg;
+        }
+        __syncthreads();
+        sa = 0.0; sb = 0.0; sg = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < JW_T / WAVE; ++ww) {
+          sa += red[par][ww][0];
+          sb += red[par][ww][1];
+          sg += red[par][ww][2];
+        }
+        par ^= 1;
         if (sg != 0.0 && fabs(sg) > tol * sqrt(sa * sb)) {
           const double z = (sb - sa) / (2.0 * sg);
           const double t = ((z >= 0.0) ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
           const double cs = 1.0 / sqrt(1.0 + t * t);
           const double sn_ = cs * t;
-          for (int row = sub; row < k; row += tpp) {
-            const double u = xi[row], w = xj[row];
-            xi[row] = cs * u - sn_ * w;
-            xj[row] = sn_ * u + cs * w;
-          }
           double* vi = V + (int64_t)i * ldv;
           double* vj = V + (int64_t)j * ldv;
-          for (int row = sub; row < k; row += tpp) {
-            const double u = vi[row], w = vj[row];
-            vi[row] = cs * u - sn_ * w;
-            vj[row] = sn_ * u + cs * w;
+          double a2[JW_RPT], b2[JW_RPT];
+#pragma unroll
+          for (int e = 0; e < JW_RPT; ++e) {
+            const int row = tid + e * JW_T;
+            a2[e] = (row < k) ? vi[row] : 0.0;
+            b2[e] = (row < k) ? vj[row] : 0.0;
           }
-          if (sub == 0) rotated = 1;
+#pragma unroll
+          for (int e = 0; e < JW_RPT; ++e) {
+            const int row = tid + e * JW_T;
+            if (row < k) {
+              xi[row] = cs * u[e] - sn_ * v[e];
+              xj[row] = sn_ * u[e] + cs * v[e];
+              vi[row] = cs * a2[e] - sn_ * b2[e];
+              vj[row] = sn_ * a2[e] + cs * b2[e];
+            }
+          }
+          if (tid == 0) atomicOr(&flags[1 + sweep], 1u);
         }
       }
-      __syncthreads();
+      if (!jw_barrier(flags, P, ++round, err)) return;
     }
-    if (!rotated) break;
-    __syncthreads();
+    const unsigned rot = __hip_atomic_load(&flags[1 + sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__builtin_amdgcn_readfirstlane(rot) == 0u) break;
   }
+}
 
-  // column norms
-  for (int j = grp; j < k; j += groups) {
+// Column norms of the rotated X, singular values in descending order (ties
+// by index), U = X V / sigma (a column with sigma == 0 is left zero).
+__global__ void __launch_bounds__(SVD_THREADS) jacobi_finish_kernel(int k, const double* X, int64_t ldx,
+                                                                     const double* V, int64_t ldv, double* U,
+                                                                     int64_t ldu, double* sigma, double* Vout,
+                                                                     int64_t ldvo, const int* err) {
+  __shared__ double sn[1024];
+  const int tid = threadIdx.x;
+  for (int j = tid / WAVE; j < k; j += SVD_THREADS / WAVE) {
     const double* xj = X + (int64_t)j * ldx;
     double s = 0.0;
-    for (int row = sub; row < k; row += tpp) s += xj[row] * xj[row];
-    s = group_sum(s, tpp);
-    if (sub == 0) sn[j] = sqrt(s);
+    for (int row = tid & (WAVE - 1); row < k; row += WAVE) s += xj[row] * xj[row];
+    s = wave_sum(s);
+    if ((tid & (WAVE - 1)) == 0) sn[j] = sqrt(s);
   }
   __syncthreads();
-  // descending order, ties by index
   for (int j = tid; j < k; j += SVD_THREADS) {
     const double v = sn[j];
     int rank = 0;
@@ -128,15 +185,39 @@ __global__ void __launch_bounds__(SVD_THREADS) jacobi_kernel(int k, double* X, i
   }
 }
 
+__global__ void identity_kernel(int k, double* V, int64_t ldv, unsigned* flags, int nflags) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (int64_t)k * k) {
+    const int64_t j = e / k, i = e - j * k;
+    V[i + j * ldv] = (i == j) ? 1.0 : 0.0;
+  }
+  if (e < nflags) flags[e] = 0u;
+}
+
 }  // namespace
 
 int launch_jacobi_svd(hipStream_t s, int k, double* X, int64_t ldx, double* U, int64_t ldu, double* sigma, double* V,
                       int64_t ldv, const SvdWork& w) {
   if (k <= 0) return 0;
-  if (k > 1024) return -3;
+  if (k > JW_T * JW_RPT) return -3;
+  if (!w.flags || !w.err) return -3;
+  constexpr int MAX_SWEEPS = 60;
   // w.tmp holds the accumulated rotations (k x k)
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(SVD_THREADS), 0, s, k, X, ldx, w.tmp, (int64_t)k, U, ldu, sigma, V,
-                     ldv, 1e-15, 60);
+  const int64_t ke = (int64_t)k * k;
+  const int nflags = 1 + MAX_SWEEPS;
+  hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((std::max<int64_t>(ke, nflags) + 255) / 256)), dim3(256), 0, s,
+                     k, w.tmp, (int64_t)k, w.flags, nflags);
+  RQ_HIP(hipGetLastError());
+  const int kk = k + (k & 1);
+  int P = std::max(1, std::min(kk / 2, 256));
+  double tol = 1e-15;
+  int ksw = k;
+  int64_t ldt = k;
+  int maxs = MAX_SWEEPS;
+  void* args[] = {&ksw, &X, &ldx, (void*)&w.tmp, &ldt, &tol, &maxs, (void*)&w.flags, (void*)&w.err};
+  RQ_HIP(hipLaunchCooperativeKernel((const void*)jacobi_sweeps_kernel, dim3(P), dim3(JW_T), args, 0, s));
+  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(SVD_THREADS), 0, s, k, (const double*)X, ldx,
+                     (const double*)w.tmp, (int64_t)k, U, ldu, sigma, V, ldv, (const int*)w.err);
   RQ_HIP(hipGetLastError());
   return 0;
 }
