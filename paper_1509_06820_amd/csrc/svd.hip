@@ -91,12 +91,19 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
         const int i = min(p, q), j = max(p, q);
         double* xi = X + (int64_t)i * ldx;
         double* xj = X + (int64_t)j * ldx;
-        double u[JW_RPT], v[JW_RPT];
+        double* vi = V + (int64_t)i * ldv;
+        double* vj = V + (int64_t)j * ldv;
+        // the pair's columns of X and V are all read up front (one memory
+        // round trip per round)
+        double u[JW_RPT], v[JW_RPT], a2[JW_RPT], b2[JW_RPT];
 #pragma unroll
         for (int e = 0; e < JW_RPT; ++e) {
           const int row = tid + e * JW_T;
-          u[e] = (row < k) ? xi[row] : 0.0;
-          v[e] = (row < k) ? xj[row] : 0.0;
+          const bool in = row < k;
+          u[e] = in ? xi[row] : 0.0;
+          v[e] = in ? xj[row] : 0.0;
+          a2[e] = in ? vi[row] : 0.0;
+          b2[e] = in ? vj[row] : 0.0;
         }
         double sa = 0.0, sb = 0.0, sg = 0.0;
 #pragma unroll
@@ -127,15 +134,6 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
           const double t = ((z >= 0.0) ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
           const double cs = 1.0 / sqrt(1.0 + t * t);
           const double sn_ = cs * t;
-          double* vi = V + (int64_t)i * ldv;
-          double* vj = V + (int64_t)j * ldv;
-          double a2[JW_RPT], b2[JW_RPT];
-#pragma unroll
-          for (int e = 0; e < JW_RPT; ++e) {
-            const int row = tid + e * JW_T;
-            a2[e] = (row < k) ? vi[row] : 0.0;
-            b2[e] = (row < k) ? vj[row] : 0.0;
-          }
 #pragma unroll
           for (int e = 0; e < JW_RPT; ++e) {
             const int row = tid + e * JW_T;
