@@ -44,10 +44,6 @@ struct SqLds {
   // reflectors of its steps; at its end they are copied to vlog and their
   // rows take the final sample columns of the round's pivots.
   double vq[SQ_BMAX * LMAX];
-  // Row masks: ge0[LMAX + d] = (d >= 0), eq0[LMAX + d] = (d == 0); ge1, eq1
-  // are the same tables shifted by one element, so that the mask of any
-  // row offset can be read with 16-byte aligned accesses.
-  double ge0[2 * LMAX], ge1[2 * LMAX], eq0[2 * LMAX], eq1[2 * LMAX];
   double taus[SQ_BMAX];
   double kv[SQ_T];                    // ranking keys sorted per wave: trailing norm, position
   int kp[SQ_T];
@@ -62,17 +58,6 @@ struct SqLds {
   int bad;
   int nvalid;
 };
-
-// m with m[r] = (r >= f) for 0 <= f <= LMAX, 16-byte aligned.
-template <int LMAX>
-__device__ __forceinline__ const double* mask_ge(const SqLds<LMAX>& L, int f) {
-  return ((LMAX - f) & 1) ? L.ge1 + (LMAX - f - 1) : L.ge0 + (LMAX - f);
-}
-// m with m[r] = (r == f).
-template <int LMAX>
-__device__ __forceinline__ const double* mask_eq(const SqLds<LMAX>& L, int f) {
-  return ((LMAX - f) & 1) ? L.eq1 + (LMAX - f - 1) : L.eq0 + (LMAX - f);
-}
 
 __device__ __forceinline__ double ranked(double nu) { return (nu != nu) ? -1.0 : nu; }
 
@@ -105,124 +90,6 @@ __device__ __forceinline__ double uni(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// LDS rows are read 8 at a time (four 16-byte reads) into a register chunk,
-// two chunks ahead of their use.  The address of each read is made to depend
-// on the result of an earlier chunk (an empty asm statement with that value
-// as input), so the compiler cannot hoist all reads to the top of the pass
-// and hold the whole reflector in registers next to the column.
-__device__ __forceinline__ void lds_chunk(double (&buf)[8], const double* __restrict__ p) {
-  const double2* q = reinterpret_cast<const double2*>(p);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const double2 w = q[i];
-    buf[2 * i] = w.x;
-    buf[2 * i + 1] = w.y;
-  }
-}
-
-__device__ __forceinline__ const double* after(const double* p, double dep) {
-  int z = 0;
-  asm volatile("" : "+v"(z) : "v"(dep));
-  return p + z;
-}
-
-// d = tau v^T x
-template <int LMAX>
-__device__ __forceinline__ double sq_dot(const double (&x)[LMAX], const double* v, double tau) {
-  constexpr int NC = LMAX / 8;
-  double vb[3][8];
-  double d[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  lds_chunk(vb[0], v);
-  lds_chunk(vb[1], v + 8);
-#pragma unroll
-  for (int k = 0; k < NC; ++k) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) d[i] = fma(vb[k % 3][i], x[8 * k + i], d[i]);
-    if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v, d[0]) + 8 * (k + 2));
-  }
-  return tau * (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])));
-}
-
-// x <- x - d v
-template <int LMAX>
-__device__ __forceinline__ void sq_axpy(double (&x)[LMAX], const double* v, double d) {
-  constexpr int NC = LMAX / 8;
-  const double* v2 = after(v, d);
-  double vb[3][8];
-  lds_chunk(vb[0], v2);
-  lds_chunk(vb[1], v2 + 8);
-#pragma unroll
-  for (int k = 0; k < NC; ++k) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) x[8 * k + i] = fma(-d, vb[k % 3][i], x[8 * k + i]);
-    if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v2, x[8 * k]) + 8 * (k + 2));
-  }
-}
-
-// The reflector of step t is zero above row t, so the step's products only
-// need the 8-row chunks from t / 8 on.  The suffix length is a template
-// parameter (every register index stays a constant and the chunk reads keep
-// their prefetch ring); *_from dispatch on the uniform first chunk.
-
-// sum over chunks K0.. of v[r] x[r]
-template <int LMAX, int K0>
-__device__ __forceinline__ double sq_dot_k(const double (&x)[LMAX], const double* v) {
-  constexpr int NC = LMAX / 8;
-  double vb[3][8];
-  double d[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  lds_chunk(vb[K0 % 3], v + 8 * K0);
-  if (K0 + 1 < NC) lds_chunk(vb[(K0 + 1) % 3], v + 8 * (K0 + 1));
-#pragma unroll
-  for (int k = K0; k < NC; ++k) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) d[i] = fma(vb[k % 3][i], x[8 * k + i], d[i]);
-    if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v, d[0]) + 8 * (k + 2));
-  }
-  return ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]));
-}
-
-// x <- x - d v over chunks K0.., returning the squared norm of rows >= from
-// (uniform, from >= 8 K0) of the result
-template <int LMAX, int K0>
-__device__ __forceinline__ double sq_axpy_norm_k(double (&x)[LMAX], const double* v, double d, int from) {
-  constexpr int NC = LMAX / 8;
-  const double* v2 = after(v, d);
-  double vb[3][8];
-  double n[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  lds_chunk(vb[K0 % 3], v2 + 8 * K0);
-  if (K0 + 1 < NC) lds_chunk(vb[(K0 + 1) % 3], v2 + 8 * (K0 + 1));
-#pragma unroll
-  for (int k = K0; k < NC; ++k) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) x[8 * k + i] = fma(-d, vb[k % 3][i], x[8 * k + i]);
-    if (8 * k >= from) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) n[i] = fma(x[8 * k + i], x[8 * k + i], n[i]);
-    } else if (8 * k + 8 > from) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) n[i] += (8 * k + i >= from) ? x[8 * k + i] * x[8 * k + i] : 0.0;
-    }
-    if (k + 2 < NC) lds_chunk(vb[(k + 2) % 3], after(v2, x[8 * k]) + 8 * (k + 2));
-  }
-  return ((n[0] + n[1]) + (n[2] + n[3])) + ((n[4] + n[5]) + (n[6] + n[7]));
-}
-
-template <int LMAX, int K>
-__device__ __forceinline__ double sq_dot_from(const double (&x)[LMAX], const double* v, int k0) {
-  if constexpr (K + 1 < LMAX / 8) {
-    if (k0 > K) return sq_dot_from<LMAX, K + 1>(x, v, k0);
-  }
-  return sq_dot_k<LMAX, K>(x, v);
-}
-
-template <int LMAX, int K>
-__device__ __forceinline__ double sq_axpy_norm_from(double (&x)[LMAX], const double* v, double d, int from, int k0) {
-  if constexpr (K + 1 < LMAX / 8) {
-    if (k0 > K) return sq_axpy_norm_from<LMAX, K + 1>(x, v, d, from, k0);
-  }
-  return sq_axpy_norm_k<LMAX, K>(x, v, d, from);
-}
-
 // Householder reflector of a column whose pivot-row entry is alpha and whose
 // rows below have squared norm sig (dlarfg normalisation: beta = -sign(alpha)
 // ||x||, tau = (beta - alpha) / beta, v = x / (alpha - beta) below the pivot
@@ -237,44 +104,6 @@ __device__ __forceinline__ void sq_reflector(double alpha, double sig, double& t
   tau = zero ? 0.0 : q * rcp_nr(nrm);
   beta = zero ? alpha : -sg * nrm;
   scal = zero ? 0.0 : sg * rcp_nr(q);
-}
-
-// x <- (I - tau v v^T) x; full rows, branch free (v is zero above its first row).
-template <int LMAX>
-__device__ __forceinline__ void sq_apply(double (&x)[LMAX], const double* v, double tau) {
-  sq_axpy<LMAX>(x, v, sq_dot<LMAX>(x, v, tau));
-}
-
-// Squared norm of rows >= from (uniform): whole 8-row chunks are taken or
-// skipped by scalar branch, only the chunk holding row `from` is masked row
-// by row (no LDS traffic).
-template <int LMAX>
-__device__ __forceinline__ double sq_norm2(const double (&x)[LMAX], int from) {
-  double n[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < LMAX / 8; ++k) {
-    if (8 * k >= from) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) n[i & 3] = fma(x[8 * k + i], x[8 * k + i], n[i & 3]);
-    } else if (8 * k + 8 > from) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) n[i & 3] += (8 * k + i >= from) ? x[8 * k + i] * x[8 * k + i] : 0.0;
-    }
-  }
-  return (n[0] + n[1]) + (n[2] + n[3]);
-}
-
-// x[t] for a uniform t.
-template <int LMAX>
-__device__ __forceinline__ double row_at(const double (&x)[LMAX], int t) {
-  double a = 0.0;
-#pragma unroll
-  for (int k = 0; k < LMAX / 8; ++k)
-    if (8 * k <= t && t < 8 * k + 8) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) a += (8 * k + i == t) ? x[8 * k + i] : 0.0;
-    }
-  return a;
 }
 
 // Maximum over the wave by DPP moves within rows of 16 lanes, then the four
@@ -473,40 +302,111 @@ __device__ __forceinline__ void sq_tail2(const double (&x)[4][RQ], int q, int f,
   for (int c = 0; c < 4; ++c) out[c] = quad_sum(acc[c][0] + acc[c][1]);
 }
 
-// One pass over this workgroup's slab (one column per thread): apply the
-// reflectors of steps [a0, t0), write the column back (on the last pass, a
-// column whose position changed goes to its final position), and, if
-// `select`, publish the K best columns by trailing norm over rows >= t0 as
-// candidates together with theta = the best norm left out.  The sample has
-// LMAX rows (rows past l are zero and stay zero).
+// Integer value of quad lane qs (a constant) in every lane of the quad.
+template <int QS>
+__device__ __forceinline__ int quad_bcast_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, QS * 0x55, 0xF, 0xF, false);
+}
+
+// One pass over this workgroup's slab of SQ_T columns: apply the reflectors
+// of steps [a0, t0), write the columns back (on the last pass, a column
+// whose position changed goes to its final position), and, if `select`,
+// publish the K best columns by trailing norm over rows >= t0 as candidates
+// together with theta = the best norm left out.  The sample has LMAX rows
+// (rows past l are zero and stay zero).
+//
+// Four lanes (a quad) share four slab columns, in row pairs: quad lane q
+// holds rows 8 i + 2 q and 8 i + 2 q + 1 of all four (x[c][2 i + h]), so the
+// quad reads each column with whole 64-byte segments and each reflector
+// value a lane reads from LDS serves four columns; the partial sums are
+// combined by DPP quad permutes.  Column c of quad g is slab column 4 g + c,
+// the column whose bookkeeping (logical position, selected flag) lane
+// 4 g + c holds.
 template <int LMAX>
 __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t0, bool select, int buf,
                         int pos_s, bool sel_s) {
-  const int tid = threadIdx.x;
-  const int64_t c = (int64_t)me * SQ_T + tid;
-  const bool mine = c < a.nJ && !sel_s;
-  double x[LMAX];
-  if (mine) {
-    const double2* col = reinterpret_cast<const double2*>(a.S + c * LMAX);
+  constexpr int RQ = LMAX / 4, NI = LMAX / 8;
+  const int tid = threadIdx.x, q = tid & 3;
+  int posc[4];
+  int64_t colc[4];
+  bool minec[4];
+  {
+    const int sel = sel_s ? 1 : 0;
+    const int p4[4] = {quad_bcast_i<0>(pos_s), quad_bcast_i<1>(pos_s), quad_bcast_i<2>(pos_s),
+                       quad_bcast_i<3>(pos_s)};
+    const int s4[4] = {quad_bcast_i<0>(sel), quad_bcast_i<1>(sel), quad_bcast_i<2>(sel), quad_bcast_i<3>(sel)};
 #pragma unroll
-    for (int i = 0; i < LMAX / 2; ++i) {
-      const double2 w = col[i];
-      x[2 * i] = w.x;
-      x[2 * i + 1] = w.y;
+    for (int c = 0; c < 4; ++c) {
+      posc[c] = p4[c];
+      colc[c] = (int64_t)me * SQ_T + (tid & ~3) + c;
+      minec[c] = colc[c] < a.nJ && s4[c] == 0;
     }
-  } else {
-#pragma unroll
-    for (int r = 0; r < LMAX; ++r) x[r] = 0.0;
   }
-  for (int s = a0; s < t0; ++s) sq_apply<LMAX>(x, L.vlog + s * LMAX, uni(L.taus[s]));
-  const bool move = !select && pos_s != c;
-  if (mine && (move || t0 > a0)) {
-    double2* col = reinterpret_cast<double2*>(a.S + (move ? (int64_t)pos_s : c) * LMAX);
+  double x[4][RQ];
 #pragma unroll
-    for (int i = 0; i < LMAX / 2; ++i) col[i] = make_double2(x[2 * i], x[2 * i + 1]);
+  for (int c = 0; c < 4; ++c) {
+    const double2* col = reinterpret_cast<const double2*>(a.S + colc[c] * LMAX + 2 * q);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const double2 w = minec[c] ? col[4 * i] : make_double2(0.0, 0.0);
+      x[c][2 * i] = w.x;
+      x[c][2 * i + 1] = w.y;
+    }
+  }
+  for (int s = a0; s < t0; ++s) {
+    const double tau = uni(L.taus[s]);
+    const double2* vp = reinterpret_cast<const double2*>(L.vlog + s * LMAX + 2 * q);
+    double2 v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) v[i] = vp[4 * i];
+    double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        acc[c][0] = fma(x[c][2 * i], v[i].x, acc[c][0]);
+        acc[c][1] = fma(x[c][2 * i + 1], v[i].y, acc[c][1]);
+      }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double d = tau * quad_sum(acc[c][0] + acc[c][1]);
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        x[c][2 * i] = fma(-d, v[i].x, x[c][2 * i]);
+        x[c][2 * i + 1] = fma(-d, v[i].y, x[c][2 * i + 1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const bool move = !select && posc[c] != colc[c];
+    if (minec[c] && (move || t0 > a0)) {
+      double2* col = reinterpret_cast<double2*>(a.S + (move ? (int64_t)posc[c] : colc[c]) * LMAX + 2 * q);
+#pragma unroll
+      for (int i = 0; i < NI; ++i) col[4 * i] = make_double2(x[c][2 * i], x[c][2 * i + 1]);
+    }
   }
   if (!select) return;
-  const double nu = mine ? sq_norm2<LMAX>(x, t0) : 0.0;
+  // trailing squared norms (rows >= t0) of the quad's columns; lane q ranks column q
+  double nu = 0.0;
+  {
+    double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const double m0 = (8 * i + 2 * q >= t0) ? 1.0 : 0.0;
+      const double m1 = (8 * i + 2 * q + 1 >= t0) ? 1.0 : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        acc[c][0] = fma(x[c][2 * i] * m0, x[c][2 * i], acc[c][0]);
+        acc[c][1] = fma(x[c][2 * i + 1] * m1, x[c][2 * i + 1], acc[c][1]);
+      }
+    }
+    double n4[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) n4[c] = quad_sum(acc[c][0] + acc[c][1]);
+    nu = (q == 0) ? n4[0] : (q == 1) ? n4[1] : (q == 2) ? n4[2] : n4[3];
+  }
+  const bool mine = (q == 0) ? minec[0] : (q == 1) ? minec[1] : (q == 2) ? minec[2] : minec[3];
   const double kv = mine ? ranked(nu) : -INFINITY;
   const int kp = mine ? pos_s : INT_MAX;
   if (tid == 0) { L.bad = 0; L.nvalid = SQ_T; }
@@ -565,8 +465,8 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
       for (int it = 0; it < 7; ++it) {
         if (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          const int q = w2 * WAVE + mid;
-          if (beats(L.kv[q], L.kp[q], sv, sp)) lo = mid + 1;
+          const int qi = w2 * WAVE + mid;
+          if (beats(L.kv[qi], L.kp[qi], sv, sp)) lo = mid + 1;
           else hi = mid;
         }
       }
@@ -583,18 +483,26 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
   const int nvalid = L.nvalid;  // min over empty entries of their rank, or SQ_T
   double* cb = a.cand + (size_t)buf * SQ_LCAP * SQ_T;
   int* ib = a.cand_idx + (size_t)buf * 2 * SQ_T;
-  if (mine && rank < a.K) {
-    // candidate columns are stored in quad layout (row 4 i + q at q RQ + i)
-    constexpr int RQ = LMAX / 4;
-    const int slot = me * a.K + rank;
-    double2* col = reinterpret_cast<double2*>(cb + (size_t)slot * LMAX);
+  const int rk4[4] = {quad_bcast_i<0>(rank), quad_bcast_i<1>(rank), quad_bcast_i<2>(rank), quad_bcast_i<3>(rank)};
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq)
+  for (int c = 0; c < 4; ++c) {
+    if (minec[c] && rk4[c] < a.K) {
+      // candidate columns are stored in the steps' quad layout: row r at
+      // (r mod 4) RQ + r / 4; this lane holds rows r = 8 i + 2 q + h
+      const int slot = me * a.K + rk4[c];
+      double* col = cb + (size_t)slot * LMAX;
 #pragma unroll
-      for (int i = 0; i < RQ / 2; ++i)
-        col[qq * (RQ / 2) + i] = make_double2(x[4 * (2 * i) + qq], x[4 * (2 * i + 1) + qq]);
-    ib[slot] = pos_s;
-    ib[SQ_T + slot] = (int)c;
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = 8 * i + 2 * q + h;
+          col[(r & 3) * RQ + (r >> 2)] = x[c][2 * i + h];
+        }
+      if (q == c) {
+        ib[slot] = posc[c];
+        ib[SQ_T + slot] = (int)colc[c];
+      }
+    }
   }
   if (tid < a.K && tid >= nvalid) ib[me * a.K + tid] = -1;
   if (mine && rank == a.K) a.theta[(size_t)buf * SQ_MAXP + me] = kv;
@@ -648,12 +556,6 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
   SqLds<LMAX>& L = *reinterpret_cast<SqLds<LMAX>*>(smem);
   const int me = blockIdx.x, tid = threadIdx.x, wv_id = tid / WAVE;
   if (earlier_failure(a.err)) return;
-  for (int e = tid; e < 2 * LMAX; e += SQ_T) {
-    L.ge0[e] = (e >= LMAX) ? 1.0 : 0.0;
-    L.ge1[e] = (e + 1 >= LMAX) ? 1.0 : 0.0;
-    L.eq0[e] = (e == LMAX) ? 1.0 : 0.0;
-    L.eq1[e] = (e + 1 == LMAX) ? 1.0 : 0.0;
-  }
   const int64_t c_s = (int64_t)me * SQ_T + tid;
   int pos_s = (int)c_s;   // logical position of this thread's slab column
   bool sel_s = false;     // selected as a pivot
