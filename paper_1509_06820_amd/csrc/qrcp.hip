@@ -580,26 +580,45 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
     int pos[4], phys[4];
     unsigned act = 0;  // bit c: column c of the quad is still a candidate
     double x[4][RQ];
+    // The left-out norms, the slot indices and the slot columns are all read
+    // before any of them is used (one memory round trip): a slot's column is
+    // read whether or not the slot holds a candidate (the buffer has SQ_T
+    // slots) and zeroed afterwards when it does not.
+    double thv[SQ_MAXP / WAVE];
+    if (tid < WAVE) {
+#pragma unroll
+      for (int k = 0; k < SQ_MAXP / WAVE; ++k) {
+        const int qq = tid + k * WAVE;
+        thv[k] = (qq < a.P) ? a.theta[(size_t)buf * SQ_MAXP + qq] : -INFINITY;
+      }
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int sl = (tid & ~3) + c;
-      pos[c] = (sl < C) ? ib[sl] : -1;
-      phys[c] = (sl < C) ? ib[SQ_T + sl] : -1;
-      if (pos[c] >= 0) act |= 1u << c;
-      else pos[c] = INT_MAX;
+      const bool in = sl < C;
+      pos[c] = in ? ib[sl] : -1;
+      phys[c] = in ? ib[SQ_T + sl] : -1;
       const double2* col = reinterpret_cast<const double2*>(cb + (size_t)sl * LMAX + q * RQ);
-      const bool on = pos[c] != INT_MAX;
 #pragma unroll
       for (int i = 0; i < RQ / 2; ++i) {
-        const double2 w = on ? col[i] : make_double2(0.0, 0.0);
+        const double2 w = in ? col[i] : make_double2(0.0, 0.0);
         x[c][2 * i] = w.x;
         x[c][2 * i + 1] = w.y;
       }
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bool on = pos[c] >= 0;
+      if (on) act |= 1u << c;
+      else pos[c] = INT_MAX;
+#pragma unroll
+      for (int i = 0; i < RQ; ++i) x[c][i] = on ? x[c][i] : 0.0;
+    }
     L.wonstep[tid] = -1;
     if (tid < WAVE) {
-      double th = -INFINITY;
-      for (int qq = tid; qq < a.P; qq += WAVE) th = fmax(th, a.theta[(size_t)buf * SQ_MAXP + qq]);
+      double th = thv[0];
+#pragma unroll
+      for (int k = 1; k < SQ_MAXP / WAVE; ++k) th = fmax(th, thv[k]);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) th = fmax(th, __shfl_xor(th, off, WAVE));
       if (tid == 0) L.theta = th;
