@@ -17,11 +17,12 @@ Modules
 philox       Philox4x64-10 counter-based generator and the Box-Muller map that
              turns its words into the Gaussian compression matrix Omega.
 householder  Elementary reflectors and the compact-WY connection matrix T.
-qrcp         Sample QRCP, RQRCP (Alg. 4), TRQRCP (Alg. 6), unpivoted blocked QR.
-svd          TUXV (Alg. 7 with j_max = 1) and the one-sided Jacobi SVD of X.
+qrcp         Sample QRCP, RQRCP (Alg. 4), RSRQRCP (Alg. 5), TRQRCP (Alg. 6),
+             unpivoted blocked QR.
+svd          TUXV (Alg. 7, any j_max) and the one-sided Jacobi SVD of X.
 """
 
 from .philox import philox4x64_10, omega, uniform52, box_muller  # noqa: F401
 from .householder import reflector, apply_reflector, larft, householder_qr, form_q  # noqa: F401
-from .qrcp import sample_qrcp, rqrcp, trqrcp, unpivoted_qr, sample_update  # noqa: F401
+from .qrcp import sample_qrcp, rqrcp, rsrqrcp, trqrcp, unpivoted_qr, sample_update  # noqa: F401
 from .svd import tuxv, jacobi_svd  # noqa: F401

@@ -7,7 +7,8 @@ path, each side implementing it independently from the published
 definitions):
 
 * Raw words: Philox4x64 with 10 rounds (Salmon, Moraes, Dror, Shaw,
-  "Parallel random numbers: as easy as 1, 2, 3", SC'11).  Key = (seed, 0).
+  "Parallel random numbers: as easy as 1, 2, 3", SC'11).  Key = (seed, 0);
+  the repeated sketches of Alg. 5 use key (seed, J) for block J.
   Block q (q = 0, 1, ...) is the bijection applied to the 256-bit counter
   (q + 1, 0, 0, 0); it yields four 64-bit words.
 * Uniforms: u = ((x >> 12) + 1/2) * 2^-52, exactly representable and
@@ -73,13 +74,14 @@ def philox4x64_10(counter, key):
     return c
 
 
-def raw_words(seed, nblocks):
-    """The first nblocks Philox blocks of the stream for `seed` ((nblocks, 4))."""
+def raw_words(seed, nblocks, key1=0):
+    """The first nblocks Philox blocks of the stream with key (seed, key1)
+    ((nblocks, 4))."""
     q = np.arange(nblocks, dtype=np.uint64)
     ctr = np.zeros((nblocks, 4), dtype=np.uint64)
     ctr[:, 0] = q + np.uint64(1)
     seed = int(seed)
-    return philox4x64_10(ctr, (seed & 0xFFFFFFFFFFFFFFFF, 0))
+    return philox4x64_10(ctr, (seed & 0xFFFFFFFFFFFFFFFF, int(key1) & 0xFFFFFFFFFFFFFFFF))
 
 
 def uniform52(x):
@@ -99,9 +101,13 @@ def box_muller(words):
                      r23 * np.cos(a23), r23 * np.sin(a23)], axis=1)
 
 
-def omega(seed, l, m):
-    """The l x m compression matrix Omega (Alg. 4 / Alg. 6, first steps)."""
+def omega(seed, l, m, key1=0):
+    """The l x m compression matrix Omega (Alg. 4 / Alg. 6, first steps).
+
+    key1 selects an independent stream with the same layout: Alg. 5 draws a
+    new matrix for every block, block J (0-based) from key (seed, J), so its
+    first block uses the Omega of Alg. 4."""
     total = l * m
     nblocks = (total + 3) // 4
-    z = box_muller(raw_words(seed, nblocks)).reshape(-1)[:total]
+    z = box_muller(raw_words(seed, nblocks, key1)).reshape(-1)[:total]
     return z.reshape(l, m)

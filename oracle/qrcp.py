@@ -18,6 +18,11 @@ Conventions (readings of points the paper leaves open; all listed in the design doc):
   the last block.
 * Alg. 6 garbles: its function name (rqrcp) is read as trqrcp, "A{[0]}" as
   A^[0], and qrcp(B^[J], b) as qrcp(B^[J-1], b), as in Alg. 4.
+* Alg. 5 (RSRQRCP) sizes its new compression matrix l x (m - Jb) for block
+  J = 1, 2, ...; the matrix it multiplies, A^[J-1], has the rows i0..m-1
+  (i0 = (J-1) b) of the trailing columns, so the size is read as l x (m - i0)
+  and the sample as Omega^[J-1] A(i0:m, i0:n).  Block J (0-based) draws its
+  matrix from Philox key (seed, J).
 """
 
 import numpy as np
@@ -217,6 +222,52 @@ def trqrcp(A, k, b, p, seed=None, Omega=None):
             B, _ = sample_update(sq["S"], bJ, R11, R12)
         i0 += bJ
     return dict(F=A, tau=tau, jpvt=jpvt, gaps=np.array(gaps), info=info, Y=Y, Wt=Wt, Omega=Omega)
+
+
+def rsrqrcp(A, b, p, seed=None, omegas=None, k=None):
+    """Alg. 5 (RSRQRCP): RQRCP that draws a new compression matrix for every
+    block and samples the updated trailing matrix with it, instead of
+    updating the sample by eq. update1.  Returns dict(F, tau, jpvt, gaps, info)
+    in the layout of rqrcp.
+
+    omegas, if given, is a function (J, mJ) -> Omega^[J] (any number of rows
+    l_J, mJ columns); otherwise block J uses the l x mJ matrix of Philox key
+    (seed, J), l = b + p.
+    """
+    A = np.array(A, dtype=np.float64, copy=True, order="F")
+    m, n = A.shape
+    l = b + p
+    kk = min(m, n) if k is None else k
+    jpvt = np.arange(n, dtype=np.int64)
+    tau = np.zeros(kk)
+    gaps, info = [], 0
+    i0, J = 0, 0
+    while i0 < kk:
+        bJ = min(b, kk - i0)
+        mJ = m - i0
+        # Generate Omega^[J] and form the sample of the trailing matrix.
+        Om = omegas(J, mJ) if omegas is not None else make_omega(seed, l, mJ, key1=J)
+        B = np.asarray(Om, dtype=np.float64) @ A[i0:, i0:]
+        # Get bJ column pivots from the sample.
+        sq = sample_qrcp(B, bJ)
+        gaps += sq["gaps"]
+        if sq["info"] and not info:
+            info = i0 + sq["info"]
+        # Permute A (all rows, completed R rows included) and jpvt.
+        apply_swaps(A, sq["piv"], i0)
+        apply_swaps(jpvt, sq["piv"], i0)
+        # Construct bJ reflectors, finish bJ rows of R, update the trailing matrix.
+        Fp, tp = householder_qr(A[i0:, i0:i0 + bJ])
+        A[i0:, i0:i0 + bJ] = Fp
+        tau[i0:i0 + bJ] = tp
+        Y = unit_lower(Fp, bJ)
+        T = larft(Y, tp)
+        if i0 + bJ < n:
+            C = A[i0:, i0 + bJ:]
+            C -= Y @ (T.T @ (Y.T @ C))
+        i0 += bJ
+        J += 1
+    return dict(F=A, tau=tau, jpvt=jpvt, gaps=np.array(gaps), info=info)
 
 
 def unpivoted_qr(A, b):
