@@ -24,7 +24,7 @@
  *   choice); -1 = an internal cross-workgroup wait timed out (results are
  *   invalid).
  * - Limits of this version: 1 <= b <= 64, 0 <= p, b + p <= 128, n <= 65536,
- *   k <= 1024 for rq_tuxv.
+ *   k <= 1024 for rq_tuxv and rq_tuxv_iter.
  * - Pivot indices are 0-based int64.  jpvt[j] is the original index of column
  *   j of A P.
  */
@@ -45,8 +45,12 @@ enum {
   RQ_OP_TUXV = 2,         /* rq_tuxv / rq_tuxv_omega            */
   RQ_OP_QR = 3,           /* rq_unpivoted_qr                    */
   RQ_OP_SAMPLE_QRCP = 4,  /* rq_sample_qrcp                     */
-  RQ_OP_SVD = 5           /* rq_small_svd                       */
+  RQ_OP_SVD = 5,          /* rq_small_svd                       */
+  RQ_OP_RSRQRCP = 6       /* rq_rsrqrcp                         */
 };
+
+/* Largest j_max accepted by rq_tuxv_iter. */
+#define RQ_TUXV_MAX_ITER 64
 
 /* Library version string (static storage). */
 const char* rq_version(void);
@@ -83,6 +87,24 @@ int rq_rqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t
 int rq_rqrcp_omega(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p,
                    const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work, size_t work_bytes,
                    int32_t* info);
+
+/*
+ * RSRQRCP -- Alg. 5 (Section 5), repeated-sampling RQRCP: the factorization
+ * of rq_rqrcp, except that every block J = 0, 1, ... (starting at column
+ * i0 = J b) draws a new compression matrix Omega^[J] (l x (m - i0), Philox
+ * key (seed, J), same normal map and layout as rq_omega) and samples the
+ * updated trailing matrix, B = Omega^[J] A(i0:m, i0:n), instead of updating
+ * the previous sample by eq. (update1).  Block 0 therefore makes the pivot
+ * choices of rq_rqrcp's first block.  The paper gives it as the comparison
+ * that shows what the sample update saves.
+ *   Outputs and layout as rq_rqrcp; workspace: rq_workspace_bytes with
+ *   RQ_OP_RSRQRCP.
+ *   Arguments: 1 stream, 2 m, 3 n, 4 A (in/out, m x n, device), 5 lda,
+ *   6 b, 7 p, 8 seed, 9 jpvt (out, n int64), 10 tau (out, min(m,n)),
+ *   11 work, 12 work_bytes, 13 info (out, device).
+ */
+int rq_rsrqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+               int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info);
 
 /*
  * TRQRCP -- Alg. 6 (Section 5.1): truncated RQRCP to rank k that never
@@ -122,6 +144,22 @@ int rq_tuxv(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int6
 int rq_tuxv_omega(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
                   const double* Omega, int64_t ldo, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt,
                   void* work, size_t work_bytes, int32_t* info);
+
+/*
+ * TUXV with j_max >= 1 iterations -- Alg. 7 (Section 6): after the first LQ,
+ * steps alternate between the QR of Z = A V (new U, upper triangular X) and
+ * the LQ of Z = U^T A, computed as the QR of A^T U (new V, lower triangular
+ * X); j_max counts these steps, so j_max = 1 is rq_tuxv.  Each step can only
+ * lower the error ||A - U X V^T||_F (the best approximation with the new
+ * column or row space).  The SVD of the last X gives the outputs, as in
+ * rq_tuxv.  Workspace: RQ_OP_TUXV.
+ * Arguments: 1 stream, 2 m, 3 n, 4 k, 5 A, 6 lda, 7 b, 8 p, 9 seed,
+ * 10 jmax (1 <= jmax <= RQ_TUXV_MAX_ITER), 11 U, 12 ldu, 13 sigma, 14 VT,
+ * 15 ldvt, 16 work, 17 work_bytes, 18 info.
+ */
+int rq_tuxv_iter(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
+                 uint64_t seed, int32_t jmax, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt,
+                 void* work, size_t work_bytes, int32_t* info);
 
 /*
  * Unpivoted blocked Householder QR (the paper's "qr" comparator, Section 7:

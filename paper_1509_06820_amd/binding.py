@@ -19,7 +19,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librqrcp.so")
 
-RQ_OP_RQRCP, RQ_OP_TRQRCP, RQ_OP_TUXV, RQ_OP_QR, RQ_OP_SAMPLE_QRCP, RQ_OP_SVD = range(6)
+RQ_OP_RQRCP, RQ_OP_TRQRCP, RQ_OP_TUXV, RQ_OP_QR, RQ_OP_SAMPLE_QRCP, RQ_OP_SVD, RQ_OP_RSRQRCP = range(7)
+RQ_TUXV_MAX_ITER = 64
 
 _c_i32, _c_i64, _c_u64, _c_sz, _c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p
 
@@ -30,6 +31,10 @@ _SIGS = {
                  ctypes.c_int),
     "rq_rqrcp_omega": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_p, _c_p, _c_p, _c_sz,
                         _c_p], ctypes.c_int),
+    "rq_rsrqrcp": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz, _c_p],
+                   ctypes.c_int),
+    "rq_tuxv_iter": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_i32, _c_p, _c_i64, _c_p,
+                      _c_p, _c_i64, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_trqrcp": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz,
                    _c_p], ctypes.c_int),
     "rq_trqrcp_omega": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_p, _c_p, _c_p,
@@ -141,6 +146,24 @@ def rq_rqrcp(A, b, p, seed=0, Omega=None, work=None, stream=None):
     return F, tau, jpvt, info
 
 
+def rq_rsrqrcp(A, b, p, seed=0, work=None, stream=None):
+    """Alg. 5 (a new compression matrix and sample per block).  Returns
+    (F, tau, jpvt, info) in the layout of rq_rqrcp; A is not modified."""
+    F = fortran(A).clone()
+    m, n = F.shape
+    k = min(m, n)
+    dev = F.device
+    jpvt = torch.empty(n, dtype=torch.int64, device=dev)
+    tau = torch.empty(k, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    if work is None:
+        work = workspace(RQ_OP_RSRQRCP, m, n, k, b, p, dev)
+    rc = load().rq_rsrqrcp(_stream(stream), m, n, _ptr(F), _ld(F), b, p, seed, _ptr(jpvt), _ptr(tau), _ptr(work),
+                           work.numel(), _ptr(info))
+    _check(rc, "rq_rsrqrcp")
+    return F, tau, jpvt, info
+
+
 def rq_trqrcp(A, k, b, p, seed=0, Omega=None, work=None, stream=None):
     """Alg. 6.  Returns (F, tau, jpvt, info) (layout as in include/rqrcp.h)."""
     F = fortran(A).clone()
@@ -164,8 +187,9 @@ def rq_trqrcp(A, k, b, p, seed=0, Omega=None, work=None, stream=None):
     return F, tau, jpvt, info
 
 
-def rq_tuxv(A, k, b, p, seed=0, Omega=None, work=None, stream=None):
-    """Alg. 7 (j_max = 1) + SVD of X.  Returns (U, sigma, VT, info)."""
+def rq_tuxv(A, k, b, p, seed=0, Omega=None, work=None, stream=None, jmax=1):
+    """Alg. 7 + SVD of X.  Returns (U, sigma, VT, info).  jmax > 1 (seeded
+    Omega only) runs the further LQ/QR steps through rq_tuxv_iter."""
     Af = fortran(A)
     m, n = Af.shape
     dev = Af.device
@@ -176,7 +200,13 @@ def rq_tuxv(A, k, b, p, seed=0, Omega=None, work=None, stream=None):
     if work is None:
         work = workspace(RQ_OP_TUXV, m, n, k, b, p, dev)
     L = load()
-    if Omega is None:
+    if jmax != 1:
+        if Omega is not None:
+            raise ValueError("jmax > 1 takes the seeded compression matrix")
+        rc = L.rq_tuxv_iter(_stream(stream), m, n, k, _ptr(Af), _ld(Af), b, p, seed, jmax, _ptr(U), m, _ptr(sigma),
+                            _ptr(VT), k, _ptr(work), work.numel(), _ptr(info))
+        _check(rc, "rq_tuxv_iter")
+    elif Omega is None:
         rc = L.rq_tuxv(_stream(stream), m, n, k, _ptr(Af), _ld(Af), b, p, seed, _ptr(U), m, _ptr(sigma), _ptr(VT), k,
                        _ptr(work), work.numel(), _ptr(info))
         _check(rc, "rq_tuxv")
@@ -268,6 +298,7 @@ def rq_profile_stop():
 
 # short aliases
 rqrcp = rq_rqrcp
+rsrqrcp = rq_rsrqrcp
 trqrcp = rq_trqrcp
 tuxv = rq_tuxv
 unpivoted_qr = rq_unpivoted_qr

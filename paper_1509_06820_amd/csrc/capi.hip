@@ -218,9 +218,13 @@ void carve_factor(Carve& cv, int64_t m, int64_t n, int b, int p, bool pivoting, 
   f.ybuf = cv.take<double>((size_t)m * b);
 }
 
+// RQRCP (Alg. 4) when pivoting, the unpivoted blocked QR otherwise; with
+// resample, RSRQRCP (Alg. 5): every block draws Omega^[J] (l x mJ, Philox key
+// (seed, J)) and samples the updated trailing matrix A(i0:m, i0:n) with it,
+// and there is no sample update.
 int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int b, int p, uint64_t seed,
                 const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work, size_t wbytes,
-                int32_t* info, bool pivoting) {
+                int32_t* info, bool pivoting, bool resample = false) {
   FactorWS f;
   Carve cv(work, wbytes);
   carve_factor(cv, m, n, b, p, pivoting, f);
@@ -228,8 +232,8 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
   const int64_t k = std::min(m, n);
   const int l = b + p;
   RQ_TRY(launch_fill(s, f.c.flags, f.c.flag_words));
-  if (pivoting) {
-    RQ_TRY(launch_iota(s, n, jpvt));
+  if (pivoting) RQ_TRY(launch_iota(s, n, jpvt));
+  if (pivoting && !resample) {
     const double* Om = Omega;
     int64_t ldom = ldo;
     if (!Om) {
@@ -243,9 +247,15 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
   for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
     const int bJ = (int)std::min<int64_t>(b, k - i0);
     const int64_t mJ = m - i0, nJ = n - i0;
-    (void)mJ;
     double* s_blk = pivoting ? f.sb.smp + i0 * f.sb.ls : nullptr;
     if (pivoting) {
+      if (resample) {
+        {
+          ProfScope ps(PC_OMEGA, s, 8.0 * l * mJ, 0.0);
+          RQ_TRY(launch_omega(s, seed, l, mJ, f.sb.omega, 1, l, (uint64_t)J));
+        }
+        RQ_TRY(sketch(s, mJ, nJ, A + i0 + i0 * lda, lda, l, f.sb.omega, l, s_blk, f.sb.ls));
+      }
       {
         ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, 4.0 * l * nJ * bJ);
         RQ_TRY(launch_sample_qrcp(s, s_blk, f.sb.ls, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J)));
@@ -255,7 +265,7 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
     }
     RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J, s_blk, 1, f.sb.ls));
     RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
-    if (pivoting && i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb));
+    if (pivoting && !resample && i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb));
     i0 += bJ;
   }
   if (info) {
@@ -445,9 +455,11 @@ void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS
   t.svdflags = cv.take<unsigned>(128);
 }
 
+// Alg. 7 with jmax multiply-and-factorize steps after the first LQ, then the
+// SVD of the last connection matrix X: A ~ (U Ux) diag(sigma) (Vx^T V^T).
 int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int b, int p,
               uint64_t seed, const double* Omega, int64_t ldo, double* U, int64_t ldu, double* sigma, double* VT,
-              int64_t ldvt, void* work, size_t wbytes, int32_t* info) {
+              int64_t ldvt, void* work, size_t wbytes, int32_t* info, int jmax = 1) {
   TuxvWS t;
   Carve cv(work, wbytes);
   carve_tuxv(cv, m, n, k, b, p, t);
@@ -472,6 +484,30 @@ int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, i
   RQ_TRY(qr_explicit(s, m, k, t.z1, m, b, t.tu, t.qu));
   RQ_TRY(launch_triu_copy(s, k, t.z1, m, t.x, k));
   RQ_TRY(form_q(s, m, k, b, t.qu, t.u1, m));
+  for (int j = 1; j < jmax;) {
+    // Z = U^T A, LQ-factorized as the QR of Z^T = A^T U (n x k): V and X
+    // lower triangular, A ~ U X V^T
+    {
+      ProfScope ps(PC_TUXV_PRODUCTS, s, 8.0 * ((double)m * n + (double)m * k + (double)n * k),
+                   2.0 * m * (double)n * k);
+      RQ_TRY(launch_gemm(s, true, false, n, k, m, 1.0, A, lda, t.u1, m, 0.0, t.z0t, n, nullptr, 0));
+    }
+    RQ_TRY(qr_explicit(s, n, k, t.z0t, n, b, t.tz, t.qz));
+    RQ_TRY(launch_triu_copy(s, k, t.z0t, n, t.ux, k));
+    RQ_TRY(launch_transpose(s, k, k, t.ux, k, t.x, k));
+    RQ_TRY(form_q(s, n, k, b, t.qz, t.v, n));
+    if (++j == jmax) break;
+    // Z = A V, QR-factorized: U and X upper triangular
+    {
+      ProfScope ps(PC_TUXV_PRODUCTS, s, 8.0 * ((double)m * n + (double)n * k + (double)m * k),
+                   2.0 * m * (double)n * k);
+      RQ_TRY(launch_gemm(s, false, false, m, k, n, 1.0, A, lda, t.v, n, 0.0, t.z1, m, nullptr, 0));
+    }
+    RQ_TRY(qr_explicit(s, m, k, t.z1, m, b, t.tu, t.qu));
+    RQ_TRY(launch_triu_copy(s, k, t.z1, m, t.x, k));
+    RQ_TRY(form_q(s, m, k, b, t.qu, t.u1, m));
+    ++j;
+  }
   // X = Ux diag(sigma) Vx^T
   SvdWork sw;
   sw.colnorm = nullptr; sw.order = nullptr; sw.flags = t.svdflags; sw.err = t.trq.c.err; sw.tmp = t.svdtmp;
@@ -519,10 +555,11 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
   size_t sz = 0;
   switch (op) {
     case RQ_OP_RQRCP:
+    case RQ_OP_RSRQRCP:
     case RQ_OP_QR: {
       FactorWS f;
       Carve cv(nullptr, 0);
-      carve_factor(cv, m, n, b, p, op == RQ_OP_RQRCP, f);
+      carve_factor(cv, m, n, b, p, op != RQ_OP_QR, f);
       sz = cv.off;
       break;
     }
@@ -583,6 +620,15 @@ int rq_rqrcp_omega(void* stream, int64_t m, int64_t n, double* A, int64_t lda, i
   return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, 0, Omega, ldo, jpvt, tau, work, work_bytes, info, true);
 }
 
+int rq_rsrqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
+               int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 5, 6, 7);
+  if (rc) return rc;
+  if (m == 0 || n == 0) return 0;
+  return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes, info,
+                     true, true);
+}
+
 int rq_unpivoted_qr(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, double* tau, void* work,
                     size_t work_bytes, int32_t* info) {
   int rc = check_common(m, n, lda, b, 0, 2, 3, 5, 6, 6);
@@ -638,6 +684,19 @@ int rq_tuxv(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int6
   if (ldvt < k) return -14;
   return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, U, ldu, sigma, VT, ldvt, work,
                    work_bytes, info);
+}
+
+int rq_tuxv_iter(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
+                 uint64_t seed, int32_t jmax, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt,
+                 void* work, size_t work_bytes, int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
+  if (rc) return rc;
+  if (k < 1 || k > std::min(m, n) || k > 1024) return -4;
+  if (jmax < 1 || jmax > RQ_TUXV_MAX_ITER) return -10;
+  if (ldu < m) return -12;
+  if (ldvt < k) return -15;
+  return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, U, ldu, sigma, VT, ldvt, work,
+                   work_bytes, info, jmax);
 }
 
 int rq_tuxv_omega(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,

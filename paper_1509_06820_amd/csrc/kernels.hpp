@@ -7,7 +7,8 @@
 namespace rq {
 
 // Omega(r, c) -> out[r*rs + c*cs], r < l, c < m (Philox4x64-10 + Box-Muller).
-int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out, int64_t rs, int64_t cs);
+int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out, int64_t rs, int64_t cs,
+                 uint64_t key1 = 0);
 
 // C = alpha * opA * opB + beta * C  (see gemm.hip).  `scratch` (may be null)
 // enables split-K for short-wide outputs; gemm_scratch_elems gives its size.

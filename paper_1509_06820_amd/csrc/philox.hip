@@ -2,7 +2,9 @@
 // entries; Alg. 4 and Alg. 6 draw it once per factorization).
 //
 // Generator: Philox4x64 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11),
-// key (seed, 0); block q is the bijection of counter (q + 1, 0, 0, 0).
+// key (seed, key1) -- key1 = 0 for Alg. 4 and Alg. 6, key1 = J for block J of
+// Alg. 5, which draws a new matrix per block; block q is the bijection of
+// counter (q + 1, 0, 0, 0).
 // Uniforms u = ((x >> 12) + 1/2) 2^-52 lie strictly inside (0, 1).
 // Box-Muller (1958) turns words (x0, x1) into r cos(2 pi u1), r sin(2 pi u1)
 // with r = sqrt(-2 ln u0), and (x2, x3) likewise.  Normal number
@@ -18,9 +20,9 @@ constexpr uint64_t kM1 = 0xCA5A826395121157ull;
 constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
 
-__device__ __forceinline__ void philox_block(uint64_t q, uint64_t seed, uint64_t out[4]) {
+__device__ __forceinline__ void philox_block(uint64_t q, uint64_t seed, uint64_t key1, uint64_t out[4]) {
   uint64_t c0 = q + 1, c1 = 0, c2 = 0, c3 = 0;
-  uint64_t k0 = seed, k1 = 0;
+  uint64_t k0 = seed, k1 = key1;
 #pragma unroll
   for (int rnd = 0; rnd < 10; ++rnd) {
     if (rnd > 0) { k0 += kW0; k1 += kW1; }
@@ -39,13 +41,13 @@ __device__ __forceinline__ double u52(uint64_t x) {
 
 // One thread per Philox block (four consecutive stream positions).
 // Omega(r, c) is stored at out[r * rs + c * cs].
-__global__ void __launch_bounds__(256) omega_kernel(uint64_t seed, int64_t l, int64_t m, double* out,
-                                                     int64_t rs, int64_t cs) {
+__global__ void __launch_bounds__(256) omega_kernel(uint64_t seed, uint64_t key1, int64_t l, int64_t m,
+                                                     double* out, int64_t rs, int64_t cs) {
   const int64_t total = l * m;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q * 4 >= total) return;
   uint64_t w[4];
-  philox_block((uint64_t)q, seed, w);
+  philox_block((uint64_t)q, seed, key1, w);
   const double two_pi = 2.0 * M_PI;
   double z[4];
   const double r01 = sqrt(-2.0 * log(u52(w[0])));
@@ -68,11 +70,12 @@ __global__ void __launch_bounds__(256) omega_kernel(uint64_t seed, int64_t l, in
 
 }  // namespace
 
-int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out, int64_t rs, int64_t cs) {
+int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out, int64_t rs, int64_t cs,
+                 uint64_t key1) {
   const int64_t blocks = (l * m + 3) / 4;
   if (blocks == 0) return 0;
   const int64_t grid = (blocks + 255) / 256;
-  hipLaunchKernelGGL(omega_kernel, dim3((unsigned)grid), dim3(256), 0, s, seed, l, m, out, rs, cs);
+  hipLaunchKernelGGL(omega_kernel, dim3((unsigned)grid), dim3(256), 0, s, seed, key1, l, m, out, rs, cs);
   RQ_HIP(hipGetLastError());
   return 0;
 }

@@ -56,6 +56,7 @@ def test_binding_covers_every_symbol():
     (binding.RQ_OP_TUXV, 20000, 10000, 256, 64, 8),
     (binding.RQ_OP_SAMPLE_QRCP, 72, 8192, 0, 64, 0),
     (binding.RQ_OP_SVD, 256, 256, 256, 1, 0),
+    (binding.RQ_OP_RSRQRCP, 8192, 8192, 0, 64, 8),
 ])
 def test_workspace_query(lib, op, m, n, k, b, p):
     nbytes = binding.rq_workspace_bytes(op, m, n, k, b, p)
@@ -92,7 +93,27 @@ def test_entry_points_reject_bad_arguments_before_any_launch(lib):
     assert lib.rq_sample_qrcp(null, 0, 4, 1, null, 1, null, null, 0, null) == -2
     assert lib.rq_sample_qrcp(null, 8, 4, 9, null, 8, null, null, 0, null) == -4
     assert lib.rq_small_svd(null, 0, null, 1, null, 1, null, null, 1, null, 0) == -2
+    assert lib.rq_rsrqrcp(null, 4, 4, null, 3, 8, 0, 1, null, null, null, 0, null) == -5
+    assert lib.rq_rsrqrcp(null, 4, 4, null, 4, 8, -1, 1, null, null, null, 0, null) == -7
+    # j_max outside [1, RQ_TUXV_MAX_ITER], then ldu < m and ldvt < k
+    for jmax in (0, -3, binding.RQ_TUXV_MAX_ITER + 1):
+        assert lib.rq_tuxv_iter(null, 10, 10, 3, null, 10, 4, 4, 1, jmax, null, 10, null, null, 3, null, 0,
+                                null) == -10
+    assert lib.rq_tuxv_iter(null, 10, 10, 3, null, 10, 4, 4, 1, 2, null, 9, null, null, 3, null, 0, null) == -12
+    assert lib.rq_tuxv_iter(null, 10, 10, 3, null, 10, 4, 4, 1, 2, null, 10, null, null, 2, null, 0, null) == -15
+    assert lib.rq_tuxv_iter(null, 10, 10, 11, null, 10, 4, 4, 1, 2, null, 10, null, null, 11, null, 0, null) == -4
     # empty matrices are valid and enqueue nothing
+    assert lib.rq_rsrqrcp(null, 0, 4, null, 1, 8, 0, 1, null, null, null, 0, null) == 0
     assert lib.rq_rqrcp(null, 0, 4, null, 1, 8, 0, 1, null, null, null, 0, null) == 0
     # workspace too small
     assert lib.rq_rqrcp(null, 40, 40, null, 40, 8, 0, 1, null, null, null, 16, null) == -100
+    assert lib.rq_rsrqrcp(null, 40, 40, null, 40, 8, 0, 1, null, null, null, 16, null) == -100
+    assert lib.rq_tuxv_iter(null, 40, 40, 8, null, 40, 8, 0, 1, 3, null, 40, null, null, 8, null, 16, null) == -100
+
+
+def test_rsrqrcp_workspace_matches_rqrcp(lib):
+    """Alg. 5 needs the buffers of Alg. 4: one sample and one Omega of the
+    first block's size, reused by every block."""
+    for m, n, b, p in [(8192, 8192, 64, 8), (300, 200, 32, 8)]:
+        assert (binding.rq_workspace_bytes(binding.RQ_OP_RSRQRCP, m, n, 0, b, p)
+                == binding.rq_workspace_bytes(binding.RQ_OP_RQRCP, m, n, 0, b, p))
