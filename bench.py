@@ -5,11 +5,18 @@ Workload (default): 8192 x 8192 i.i.d. N(0, 1), b = 64, p = 8, seed 2.
 A step is one whole RQRCP factorization of a fresh copy of A that is already
 resident in HBM (the copies are made before the timed region).  The line
 printed reports the RQRCP rate in QR-equivalent GFLOP/s (2 m n^2 - 2 n^3 / 3),
-the time of both factorizations and their ratio, the roofline position of the
-dominant stage (measured with HIP events over the timed region) and the CPU
-oracle timed on a bounded sample of the same workload.
+the time of both factorizations and their ratio, the stage breakdown (a pass
+of K steps with HIP events around every stage), the roofline position of the
+dominant stage (its launches timed with HIP events inside the timed region,
+where only that stage records events) and the CPU oracle timed on a bounded
+sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Other workloads (one JSON line each, same keys):
+    --workload rsrqrcp_c2   RSRQRCP (Alg. 5, a new sample per block) on the same
+                            matrix, with RQRCP and QR timed beside it
+    --workload c3 [--jmax J]  TRQRCP + TUXV (Alg. 7 with j_max = J) at k = 256
 """
 
 import argparse
@@ -112,24 +119,25 @@ def copy_calibration(mib):
 
 def run_c3(args):
     """TRQRCP and TUXV (fp64) at rank k = 256 on the 20000 x 10000 matrix with
-    sigma_i = 0.9^(i/10): solves/s and p99 latency of TUXV over the timed
-    solves, TRQRCP time, and the truncation error against the Eckart-Young
-    optimum (evaluated after the timed region)."""
+    sigma_i = 0.9^(i/10): solves/s and p99 latency of TUXV (j_max = --jmax)
+    over the timed solves, TRQRCP time, and the truncation error against the
+    Eckart-Young optimum (evaluated after the timed region)."""
     import torch
     from paper_1509_06820_amd import binding, inputs
     A_host, prm = inputs.config_matrix("c3")
     k, b, p, seed = prm["k"], prm["b"], prm["p"], prm["seed"]
+    jmax = args.jmax
     m, n = A_host.shape
     A = torch.from_numpy(A_host).cuda()
     W, K = args.warmup, args.steps
-    print(f"[bench] workload c3 {m}x{n} k={k} b={b} p={p}: {W} warmup + {K} timed solves", file=sys.stderr,
-          flush=True)
+    print(f"[bench] workload c3 {m}x{n} k={k} b={b} p={p} jmax={jmax}: {W} warmup + {K} timed solves",
+          file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     w_trq = binding.workspace(binding.RQ_OP_TRQRCP, m, n, k, b, p, A.device)
     w_tux = binding.workspace(binding.RQ_OP_TUXV, m, n, k, b, p, A.device)
     for _ in range(W):
         binding.rq_trqrcp(A, k, b, p, seed, work=w_trq)
-        binding.rq_tuxv(A, k, b, p, seed, work=w_tux)
+        binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     trq = []
@@ -143,7 +151,7 @@ def run_c3(args):
     res = None
     for i in range(K):
         ev[i][0].record(stream)
-        res = binding.rq_tuxv(A, k, b, p, seed, work=w_tux)
+        res = binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax)
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     lat = np.array([a.elapsed_time(z) for a, z in ev])
@@ -153,12 +161,14 @@ def run_c3(args):
     err = (torch.linalg.norm(A - (U * s) @ VT) / torch.linalg.norm(A)).item()
     opt = inputs.optimal_truncation_error(inputs.sigma_power(10000, 0.9, 10.0), k)
     ms = float(lat.mean())
-    # TUXV flops: the TRQRCP(k) products (2kmn), Z = A V (2mnk), the sketch (2lmn)
-    flops = 2.0 * k * m * n + 2.0 * m * n * k + 2.0 * (b + p) * m * n
+    # TUXV flops: the TRQRCP(k) products (2kmn), one product with A per
+    # step (2mnk each), the sketch (2lmn)
+    flops = 2.0 * k * m * n + jmax * 2.0 * m * n * k + 2.0 * (b + p) * m * n
     line = {
         "metric": METRIC,
         "value": round(1e3 / ms, 3),
-        "unit": "TUXV solves/s (fp64, 20000x10000, k=256)",
+        "unit": "TUXV solves/s (fp64, 20000x10000, k=256)" if jmax == 1 else
+                f"TUXV solves/s (fp64, 20000x10000, k=256, j_max={jmax})",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
@@ -169,8 +179,8 @@ def run_c3(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "tuxv_c3", "m": m, "n": n, "k": k, "b": b, "p": p, "seed": seed,
-                   "inputs": "U diag(0.9^(i/10)) V^T, Haar factors"},
+        "config": {"workload": "tuxv_c3" if jmax == 1 else f"tuxv_c3_jmax{jmax}", "m": m, "n": n, "k": k, "b": b,
+                   "p": p, "seed": seed, "jmax": jmax, "inputs": "U diag(0.9^(i/10)) V^T, Haar factors"},
         "tuxv_gflops": round(flops / (ms * 1e-3) / 1e9, 2),
         "trqrcp_ms": round(trq_ms, 3),
         "truncation_error": err,
@@ -178,7 +188,7 @@ def run_c3(args):
         "error_over_optimum": round(err / opt, 6),
     }
     gold = os.path.join(ROOT, "tests", "golden", "c3_tuxv_oracle_error.txt")
-    if os.path.exists(gold):
+    if jmax == 1 and os.path.exists(gold):
         with open(gold) as f:
             for ln in f:
                 if ln.startswith("oracle_error:"):
@@ -192,7 +202,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2_iid", choices=["c2_iid", "c2_lr", "c1", "c3"])
+    ap.add_argument("--workload", default="c2_iid", choices=["c2_iid", "c2_lr", "c1", "c3", "rsrqrcp_c2"])
+    ap.add_argument("--jmax", type=int, default=1, help="TUXV steps (Alg. 7 j_max) for --workload c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=3)
     ap.add_argument("--check", action="store_true", help="residual of the last factorization (untimed)")
@@ -216,7 +227,8 @@ def main():
     if args.workload == "c3":
         run_c3(args)
         return
-    A_host, prm = inputs.config_matrix(args.workload)
+    resample = args.workload == "rsrqrcp_c2"
+    A_host, prm = inputs.config_matrix("c2_iid" if resample else args.workload)
     b, p, seed = prm["b"], prm["p"], prm["seed"]
     m, n = A_host.shape
     k = min(m, n)
@@ -235,8 +247,10 @@ def main():
     tau_qr = torch.empty(k, dtype=torch.float64, device=A.device)
     info = torch.zeros(1, dtype=torch.int32, device=A.device)
 
-    # fresh copies of A for every step, made before any timed region
-    copies = [A.clone() for _ in range(W + K)]
+    # fresh copies of A for every step, made before any timed region: W
+    # warmup, K steps with HIP events around every stage (the breakdown),
+    # then the K timed steps
+    copies = [A.clone() for _ in range(W + 2 * K)]
     copies_qr = [A.clone() for _ in range(W + K)]
     torch.cuda.synchronize()
 
@@ -245,32 +259,69 @@ def main():
                         binding._ptr(work_rq), work_rq.numel(), binding._ptr(info))
         assert rc == 0, rc
 
+    def rsrqrcp(F):
+        rc = L.rq_rsrqrcp(s_ptr, m, n, binding._ptr(F), m, b, p, seed, binding._ptr(jpvt), binding._ptr(tau),
+                          binding._ptr(work_rq), work_rq.numel(), binding._ptr(info))
+        assert rc == 0, rc
+
+    # the method the line reports (Alg. 4, or Alg. 5 for rsrqrcp_c2)
+    method, method_name = (rsrqrcp, "rsrqrcp") if resample else (rqrcp, "rqrcp")
+
     def qr(F):
         rc = L.rq_unpivoted_qr(s_ptr, m, n, binding._ptr(F), m, b, binding._ptr(tau_qr), binding._ptr(work_qr),
                                work_qr.numel(), binding._ptr(info))
         assert rc == 0, rc
 
+    copies_rq = [A.clone() for _ in range(W + K)] if resample else []
     for i in range(W):
-        rqrcp(copies[i])
+        method(copies[i])
         qr(copies_qr[i])
+        if resample:
+            rqrcp(copies_rq[i])
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # timed RQRCP (stage events recorded on the same stream)
+    # pass 1: HIP events around every stage (on the kernels' stream) give the
+    # stage breakdown and the dominant stage
     binding.rq_profile_start()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(K):
+        method(copies[W + i])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stages = binding.rq_profile_stop()
+    ms_prof = e0.elapsed_time(e1) / K
+    assert int(info.item()) == 0, f"info = {int(info.item())}"
+    dom = max(stages, key=lambda nm: stages[nm]["ms"])
+    # pass 2, the timed steps: only the dominant stage keeps its events, so
+    # its launches are timed live inside the timed region at little cost
+    binding.rq_profile_start([dom])
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     e0.record(stream)
     for i in range(K):
-        rqrcp(copies[W + i])
+        method(copies[W + K + i])
     e1.record(stream)
     torch.cuda.synchronize()
     wall_rq = time.perf_counter() - t_wall
-    stages = binding.rq_profile_stop()
+    dom_timed = binding.rq_profile_stop()[dom]
+    L.rq_profile_select(0xFFFFFFFF)
     ms_rq = e0.elapsed_time(e1) / K
     assert int(info.item()) == 0, f"info = {int(info.item())}"
-    print(f"[bench] rqrcp {ms_rq:.3f} ms/factorization", file=sys.stderr, flush=True)
+    print(f"[bench] {method_name} {ms_rq:.3f} ms/factorization", file=sys.stderr, flush=True)
+    ms_rq4 = None
+    if resample:
+        # Alg. 4 on the same matrix, for the cost of repeated sampling
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(K):
+            rqrcp(copies_rq[W + i])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_rq4 = e0.elapsed_time(e1) / K
+        print(f"[bench] rqrcp {ms_rq4:.3f} ms/factorization", file=sys.stderr, flush=True)
 
     # timed unpivoted QR
     torch.cuda.synchronize()
@@ -288,8 +339,9 @@ def main():
     # dominant stage and its roofline position
     per_step = {name: dict(ms=v["ms"] / K, launches=v["count"] / K, bytes=v["bytes"] / K, flops=v["flops"] / K)
                 for name, v in stages.items()}
-    dom = max(per_step, key=lambda nm: per_step[nm]["ms"])
-    d = per_step[dom]
+    # the dominant stage as timed in the timed region
+    d = dict(ms=dom_timed["ms"] / K, launches=dom_timed["count"] / K, bytes=dom_timed["bytes"] / K,
+             flops=dom_timed["flops"] / K)
     intensity = d["flops"] / d["bytes"] if d["bytes"] else float("inf")
     ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
     if dom in ALU_STAGES:
@@ -302,14 +354,14 @@ def main():
         achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = measured_traffic(dom, args.workload)
+    roof["traffic"] = None if resample else measured_traffic(dom, args.workload)
     roof["kernel"] = dom
     roof["avg_launch_us"] = round(d["ms"] / d["launches"] * 1e3, 2) if d["launches"] else None
 
     line = {
         "metric": METRIC,
         "value": round(value, 2),
-        "unit": "GFLOP/s (QR-equivalent, RQRCP)",
+        "unit": "GFLOP/s (QR-equivalent, RSRQRCP)" if resample else "GFLOP/s (QR-equivalent, RQRCP)",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
@@ -319,21 +371,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"rqrcp_{args.workload}", "m": m, "n": n, "b": b, "p": p, "seed": seed,
-                   "inputs": "i.i.d. N(0,1)" if args.workload == "c2_iid" else args.workload},
-        "rqrcp_ms": round(ms_rq, 3),
+        "config": {"workload": "rsrqrcp_c2_iid" if resample else f"rqrcp_{args.workload}", "m": m, "n": n, "b": b,
+                   "p": p, "seed": seed,
+                   "inputs": "i.i.d. N(0,1)" if args.workload in ("c2_iid", "rsrqrcp_c2") else args.workload},
+        f"{method_name}_ms": round(ms_rq, 3),
         "unpivoted_qr_ms": round(ms_qr, 3),
-        "rqrcp_over_qr": round(ms_rq / ms_qr, 4),
-        "rqrcp_wall_ms": round(wall_rq * 1e3 / K, 3),
+        f"{method_name}_over_qr": round(ms_rq / ms_qr, 4),
+        f"{method_name}_wall_ms": round(wall_rq * 1e3 / K, 3),
         "stages_ms_per_step": {nm: round(v["ms"], 3) for nm, v in sorted(per_step.items(), key=lambda kv: -kv[1]["ms"])},
+        "profiled_ms_per_step": round(ms_prof, 3),
         "roofline": roof,
     }
     if args.check:
-        F = copies[W + K - 1]
+        F = copies[W + 2 * K - 1]
         Q = torch.linalg.householder_product(F, tau)
         res = (torch.linalg.norm(A[:, jpvt] - Q @ torch.triu(F)) / torch.linalg.norm(A)).item()
         line["residual"] = res
-    if not args.no_cpu_baseline:
+    if resample:
+        line["rqrcp_ms"] = round(ms_rq4, 3)
+        line["rsrqrcp_over_rqrcp"] = round(ms_rq / ms_rq4, 4)
+    if not args.no_cpu_baseline and not resample:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(A_host, b, p, seed, args.cpu_blocks)
     print(json.dumps(line), flush=True)

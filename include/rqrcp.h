@@ -221,8 +221,12 @@ int rq_small_svd(void* stream, int32_t k, double* X, int64_t ldx, double* U, int
  * accumulates per class; rq_profile_get() then returns the launch count,
  * total milliseconds, algorithmic bytes and flops of a class.  Not
  * reentrant across host threads that profile concurrently.
+ * rq_profile_select(mask) limits the recording to the classes whose bit is
+ * set in mask (all classes by default), so that a timed run can carry the
+ * events of one stage only.
  */
 int rq_profile_start(void);
+int rq_profile_select(uint32_t class_mask);
 int rq_profile_stop(void);
 int rq_profile_get(int32_t cls, int64_t* count, double* total_ms, double* bytes, double* flops);
 const char* rq_profile_name(int32_t cls);

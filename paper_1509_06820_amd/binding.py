@@ -50,6 +50,7 @@ _SIGS = {
     "rq_small_svd": ([_c_p, _c_i32, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_p, _c_i64, _c_p, _c_sz], ctypes.c_int),
     "rq_profile_start": ([], ctypes.c_int),
     "rq_profile_stop": ([], ctypes.c_int),
+    "rq_profile_select": ([ctypes.c_uint32], ctypes.c_int),
     "rq_profile_get": ([_c_i32, ctypes.POINTER(_c_i64), ctypes.POINTER(ctypes.c_double),
                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "rq_profile_name": ([_c_i32], ctypes.c_char_p),
@@ -278,8 +279,17 @@ def rq_small_svd(X, work=None, stream=None):
     return U, sig, V
 
 
-def rq_profile_start():
-    _check(load().rq_profile_start(), "rq_profile_start")
+def rq_profile_start(stages=None):
+    """Start stage timing; `stages` (names) limits the events to those stages."""
+    L = load()
+    mask = 0xFFFFFFFF
+    if stages is not None:
+        names = [L.rq_profile_name(c).decode() for c in range(L.rq_profile_classes())]
+        mask = 0
+        for nm in stages:
+            mask |= 1 << names.index(nm)
+    _check(L.rq_profile_select(mask), "rq_profile_select")
+    _check(L.rq_profile_start(), "rq_profile_start")
 
 
 def rq_profile_stop():

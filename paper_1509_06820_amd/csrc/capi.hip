@@ -193,12 +193,12 @@ int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, 
 }
 
 // Sketch: S (l x n, ld ls) = Omega A with Omega l x m (ld ldo); rows l..ls-1
-// of S are zeroed.
+// of S are zeroed.  With scratch the product is split along m.
 int sketch(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, int l, const double* Omega,
-           int64_t ldo, double* S, int ls) {
+           int64_t ldo, double* S, int ls, double* scratch = nullptr, size_t scratch_elems = 0) {
   const double dm = (double)m, dn = (double)n, dl = (double)l;
   ProfScope ps(PC_SKETCH, s, 8.0 * (dm * dn + dl * dm + dl * dn), 2.0 * dl * dm * dn);
-  RQ_TRY(launch_gemm(s, false, false, l, n, m, 1.0, Omega, ldo, A, lda, 0.0, S, ls, nullptr, 0));
+  RQ_TRY(launch_gemm(s, false, false, l, n, m, 1.0, Omega, ldo, A, lda, 0.0, S, ls, scratch, scratch_elems));
   return launch_zero_rows(s, l, ls, n, S, ls);
 }
 
@@ -242,7 +242,7 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
       Om = f.sb.omega;
       ldom = l;
     }
-    RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, f.sb.smp, f.sb.ls));
+    RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, f.sb.smp, f.sb.ls, f.bb.splitk, f.bb.splitk_elems));
   }
   for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
     const int bJ = (int)std::min<int64_t>(b, k - i0);
@@ -254,7 +254,8 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
           ProfScope ps(PC_OMEGA, s, 8.0 * l * mJ, 0.0);
           RQ_TRY(launch_omega(s, seed, l, mJ, f.sb.omega, 1, l, (uint64_t)J));
         }
-        RQ_TRY(sketch(s, mJ, nJ, A + i0 + i0 * lda, lda, l, f.sb.omega, l, s_blk, f.sb.ls));
+        RQ_TRY(sketch(s, mJ, nJ, A + i0 + i0 * lda, lda, l, f.sb.omega, l, s_blk, f.sb.ls, f.bb.splitk,
+                      f.bb.splitk_elems));
       }
       {
         ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, 4.0 * l * nJ * bJ);
@@ -308,7 +309,7 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
     Om = t.sb.omega;
     ldom = l;
   }
-  RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, t.sb.smp, t.sb.ls));
+  RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, t.sb.smp, t.sb.ls, t.bb.splitk, t.bb.splitk_elems));
   for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
     const int bJ = (int)std::min<int64_t>(b, k - i0);
     const int64_t mJ = m - i0, nJ = n - i0, Nt = n - i0 - bJ;
@@ -733,10 +734,15 @@ int rq_sketch(void* stream, int64_t m, int64_t n, const double* A, int64_t lda, 
   double* om = cv.take<double>((size_t)l * m);
   double* smp = cv.take<double>((size_t)n * ls);
   if (!cv.ok) return -100;
+  // the split-K scratch of the factorizations' sketch, when the workspace has room for it
+  Carve cv2 = cv;
+  const size_t sce = gemm_scratch_elems(l, n, m);
+  double* sc = cv2.take<double>(sce);
+  if (!cv2.ok) sc = nullptr;
   if (m == 0 || n == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
   RQ_TRY(launch_omega(s, seed, l, m, om, 1, l));
-  RQ_TRY(sketch(s, m, n, A, lda, l, om, l, smp, ls));
+  RQ_TRY(sketch(s, m, n, A, lda, l, om, l, smp, ls, sc, sc ? sce : 0));
   RQ_TRY(launch_copy2d(s, l, n, smp, ls, B, ldb));
   return 0;
 }

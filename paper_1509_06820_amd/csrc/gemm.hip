@@ -257,13 +257,14 @@ constexpr int64_t GRAM_MINK = 32;
 
 bool gram_mode(int64_t M, int64_t N, int64_t K) { return M <= 64 && N <= 128 && K >= 256; }
 
-// Short-wide outputs with a long reduction (b x n products Y^T A): 64 x 64
-// tiles, up to WIDE_MAXS splits of at least WIDE_MINK rows, aiming at about
-// 2048 workgroups (eight per CU).
+// Short-wide outputs with a long reduction (b x n products Y^T A, l x n
+// sketches Omega A): one row of tiles (64 x 64 up to 64 rows, 128 x 64 up
+// to 128, so that B is read once), up to WIDE_MAXS splits of at least
+// WIDE_MINK rows, aiming at about 2048 workgroups (eight per CU).
 constexpr int WIDE_MAXS = 16;
 constexpr int64_t WIDE_MINK = 256;
 
-static bool wide_mode(int64_t M, int64_t K) { return M <= 64 && K >= 1024; }
+static bool wide_mode(int64_t M, int64_t K) { return M <= 128 && K >= 1024; }
 
 size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K) {
   size_t e = 0;
@@ -287,7 +288,7 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
   constexpr int BK = 16;
   int splits = 1;
   int64_t kchunk = K;
-  enum { SMALL, BIG, WIDE } shape = SMALL;  // WIDE: split-K with the SMALL tiles
+  enum { SMALL, BIG, WIDE } shape = SMALL;  // WIDE: split-K with the SMALL tiles (BIG ones above 64 rows)
   bool many = false;
   if (scratch && gram_mode(M, N, K)) {
     kchunk = std::max<int64_t>(GRAM_MINK, (K + GRAM_MAXS - 1) / GRAM_MAXS);
@@ -299,7 +300,7 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
     }
     many = true;
   } else if (scratch && wide_mode(M, K)) {
-    shape = WIDE;
+    shape = (M <= 64) ? WIDE : BIG;
     const int64_t tiles = (N + 63) / 64;
     const int64_t want = (2048 + tiles - 1) / tiles;
     const int64_t maxs = K / WIDE_MINK;

@@ -22,6 +22,7 @@ struct Agg {
 
 std::mutex g_mu;
 bool g_on = false;
+uint32_t g_mask = 0xFFFFFFFFu;  // classes that record events
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 std::vector<hipEvent_t> g_open;  // begin events waiting for their end, one per class
@@ -46,9 +47,15 @@ hipEvent_t get_event() {
 
 bool prof_enabled() { return g_on; }
 
+static bool selected(int cls) { return cls >= 0 && cls < 32 && ((g_mask >> cls) & 1u); }
+
 void prof_begin(int cls, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_open.size() < PC_NCLASS) g_open.resize(PC_NCLASS, nullptr);
+  if (!selected(cls)) {
+    g_open[cls] = nullptr;
+    return;
+  }
   hipEvent_t e = get_event();
   if (e) hipEventRecord(e, s);
   g_open[cls] = e;
@@ -74,6 +81,12 @@ int rq_profile_start(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& a : g_agg) a = Agg();
   g_on = true;
+  return 0;
+}
+
+int rq_profile_select(uint32_t class_mask) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_mask = class_mask;
   return 0;
 }
 
