@@ -42,8 +42,9 @@ __device__ __forceinline__ void rr_pair(int r, int idx, int kk, int& p, int& q) 
 // reads it, so all of them stop after the same sweep.
 // flags[0]: arrival counter, flags[1 + s]: sweep s rotated (zeroed by the
 // caller).
-constexpr int JW_T = 256;     // threads of a sweep workgroup (rows)
-constexpr int JW_RPT = 4;     // rows per thread: k <= 1024
+constexpr int JW_T = 256;             // threads of a sweep workgroup: four waves, one column pair each
+constexpr int JW_PAIRS = JW_T / WAVE;  // column pairs a workgroup rotates at once
+constexpr int JW_MAXK = 1024;
 
 __device__ bool jw_barrier(unsigned* flags, int P, unsigned round, int* err) {
   __shared__ int s_bad;
@@ -74,17 +75,23 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Each wave rotates one column pair of the round (RPT rows per lane, the
+// three inner products reduced within the wave, no LDS), so a workgroup
+// handles four pairs and the round's k/2 pairs need k/8 workgroups; a wave
+// that rotated anything during a sweep sets that sweep's flag once, just
+// before the sweep's last barrier.
+template <int RPT>
 __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, int64_t ldx, double* V, int64_t ldv,
                                                               double tol, int max_sweeps, unsigned* flags, int* err) {
   if (earlier_failure(err)) return;
-  __shared__ double red[2][SVD_THREADS / WAVE][3];
-  const int P = gridDim.x, me = blockIdx.x, tid = threadIdx.x, w = tid / WAVE;
+  const int P = gridDim.x, lane = threadIdx.x & (WAVE - 1);
+  const int slot = blockIdx.x * JW_PAIRS + (int)(threadIdx.x / WAVE), nslots = P * JW_PAIRS;
   const int kk = k + (k & 1), npairs = kk / 2;
   unsigned round = 0;
-  int par = 0;
   for (int sweep = 0; sweep < max_sweeps && kk > 1; ++sweep) {
+    bool rotated = false;
     for (int r = 0; r < kk - 1; ++r) {
-      for (int idx = me; idx < npairs; idx += P) {
+      for (int idx = slot; idx < npairs; idx += nslots) {
         int p, q;
         rr_pair(r, idx, kk, p, q);
         if (p >= k || q >= k) continue;
@@ -95,10 +102,10 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
         double* vj = V + (int64_t)j * ldv;
         // the pair's columns of X and V are all read up front (one memory
         // round trip per round)
-        double u[JW_RPT], v[JW_RPT], a2[JW_RPT], b2[JW_RPT];
+        double u[RPT], v[RPT], a2[RPT], b2[RPT];
 #pragma unroll
-        for (int e = 0; e < JW_RPT; ++e) {
-          const int row = tid + e * JW_T;
+        for (int e = 0; e < RPT; ++e) {
+          const int row = lane + e * WAVE;
           const bool in = row < k;
           u[e] = in ? xi[row] : 0.0;
           v[e] = in ? xj[row] : 0.0;
@@ -107,7 +114,7 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
         }
         double sa = 0.0, sb = 0.0, sg = 0.0;
 #pragma unroll
-        for (int e = 0; e < JW_RPT; ++e) {
+        for (int e = 0; e < RPT; ++e) {
           sa = fma(u[e], u[e], sa);
           sb = fma(v[e], v[e], sb);
           sg = fma(u[e], v[e], sg);
@@ -115,28 +122,14 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
         sa = wave_sum(sa);
         sb = wave_sum(sb);
         sg = wave_sum(sg);
-        if ((tid & (WAVE - 1)) == 0) {
-          red[par][w][0] = sa;
-          red[par][w][1] = sb;
-          red[par][w][2] = sg;
-        }
-        __syncthreads();
-        sa = 0.0; sb = 0.0; sg = 0.0;
-#pragma unroll
-        for (int ww = 0; ww < JW_T / WAVE; ++ww) {
-          sa += red[par][ww][0];
-          sb += red[par][ww][1];
-          sg += red[par][ww][2];
-        }
-        par ^= 1;
         if (sg != 0.0 && fabs(sg) > tol * sqrt(sa * sb)) {
           const double z = (sb - sa) / (2.0 * sg);
           const double t = ((z >= 0.0) ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
           const double cs = 1.0 / sqrt(1.0 + t * t);
           const double sn_ = cs * t;
 #pragma unroll
-          for (int e = 0; e < JW_RPT; ++e) {
-            const int row = tid + e * JW_T;
+          for (int e = 0; e < RPT; ++e) {
+            const int row = lane + e * WAVE;
             if (row < k) {
               xi[row] = cs * u[e] - sn_ * v[e];
               xj[row] = sn_ * u[e] + cs * v[e];
@@ -144,9 +137,10 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
               vj[row] = sn_ * a2[e] + cs * b2[e];
             }
           }
-          if (tid == 0) atomicOr(&flags[1 + sweep], 1u);
+          rotated = true;
         }
       }
+      if (r == kk - 2 && rotated && lane == 0) atomicOr(&flags[1 + sweep], 1u);
       if (!jw_barrier(flags, P, ++round, err)) return;
     }
     const unsigned rot = __hip_atomic_load(&flags[1 + sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -197,7 +191,7 @@ __global__ void identity_kernel(int k, double* V, int64_t ldv, unsigned* flags, 
 int launch_jacobi_svd(hipStream_t s, int k, double* X, int64_t ldx, double* U, int64_t ldu, double* sigma, double* V,
                       int64_t ldv, const SvdWork& w) {
   if (k <= 0) return 0;
-  if (k > JW_T * JW_RPT) return -3;
+  if (k > JW_MAXK) return -3;
   if (!w.flags || !w.err) return -3;
   constexpr int MAX_SWEEPS = 60;
   // w.tmp holds the accumulated rotations (k x k)
@@ -207,13 +201,18 @@ int launch_jacobi_svd(hipStream_t s, int k, double* X, int64_t ldx, double* U, i
                      k, w.tmp, (int64_t)k, w.flags, nflags);
   RQ_HIP(hipGetLastError());
   const int kk = k + (k & 1);
-  int P = std::max(1, std::min(kk / 2, 256));
+  // one wave per column pair of a round, four per workgroup
+  int P = std::max(1, (kk / 2 + JW_PAIRS - 1) / JW_PAIRS);
   double tol = 1e-15;
   int ksw = k;
   int64_t ldt = k;
   int maxs = MAX_SWEEPS;
   void* args[] = {&ksw, &X, &ldx, (void*)&w.tmp, &ldt, &tol, &maxs, (void*)&w.flags, (void*)&w.err};
-  RQ_HIP(hipLaunchCooperativeKernel((const void*)jacobi_sweeps_kernel, dim3(P), dim3(JW_T), args, 0, s));
+  const void* fn = (k <= 4 * WAVE)   ? (const void*)jacobi_sweeps_kernel<4>
+                   : (k <= 8 * WAVE) ? (const void*)jacobi_sweeps_kernel<8>
+                                     : (const void*)jacobi_sweeps_kernel<16>;
+  static_assert(16 * WAVE >= JW_MAXK, "rows per lane");
+  RQ_HIP(hipLaunchCooperativeKernel(fn, dim3(P), dim3(JW_T), args, 0, s));
   hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(SVD_THREADS), 0, s, k, (const double*)X, ldx,
                      (const double*)w.tmp, (int64_t)k, U, ldu, sigma, V, ldv, (const int*)w.err);
   RQ_HIP(hipGetLastError());
