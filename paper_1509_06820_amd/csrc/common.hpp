@@ -34,6 +34,49 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Value of lane ^ STRIDE (STRIDE a power of two below 64) without LDS: DPP
+// within rows of 16 lanes, gfx950 permlane swaps across rows and halves
+// (with both operands equal, result 1 holds the partner row's value in the
+// even rows and result 0 in the odd rows).
+template <int STRIDE>
+__device__ __forceinline__ int xchg_i(int v, int lane) {
+  if constexpr (STRIDE == 1) {
+    return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  } else if constexpr (STRIDE == 2) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  } else if constexpr (STRIDE == 4) {
+    const int up = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xF, 0xF, false);   // row_shl:4 (lane + 4)
+    const int dn = __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false);   // row_shr:4 (lane - 4)
+    return (lane & 4) ? dn : up;
+  } else if constexpr (STRIDE == 8) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (STRIDE == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) ? (int)r[0] : (int)r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? (int)r[0] : (int)r[1];
+  }
+}
+template <int STRIDE>
+__device__ __forceinline__ double xchg_d(double v, int lane) {
+  return __hiloint2double(xchg_i<STRIDE>(__double2hiint(v), lane), xchg_i<STRIDE>(__double2loint(v), lane));
+}
+
+// Sum over the wave by xor butterflies (DPP and permlane exchanges, no LDS):
+// every lane ends with the same bits, since each step adds the same pair in
+// either order.
+__device__ __forceinline__ double wave_sum_x(double v) {
+  const int lane = (int)(threadIdx.x & (WAVE - 1));
+  v += xchg_d<1>(v, lane);
+  v += xchg_d<2>(v, lane);
+  v += xchg_d<4>(v, lane);
+  v += xchg_d<8>(v, lane);
+  v += xchg_d<16>(v, lane);
+  v += xchg_d<32>(v, lane);
+  return v;
+}
+
 // (value, position) ranking used for pivot selection: larger value wins,
 // ties go to the lower position.  NaN values must be mapped to -1 before.
 __device__ __forceinline__ bool rank_better(double v1, long p1, double v2, long p2) {

@@ -217,35 +217,6 @@ __device__ __forceinline__ double quad_bcast(double v, int qs) {
   }
 }
 
-// Value of lane ^ STRIDE (STRIDE a power of two below 64) without LDS: DPP
-// within rows of 16 lanes, gfx950 permlane swaps across rows and halves
-// (with both operands equal, result 1 holds the partner row's value in the
-// even rows and result 0 in the odd rows).
-template <int STRIDE>
-__device__ __forceinline__ int xchg_i(int v, int lane) {
-  if constexpr (STRIDE == 1) {
-    return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-  } else if constexpr (STRIDE == 2) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-  } else if constexpr (STRIDE == 4) {
-    const int up = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xF, 0xF, false);   // row_shl:4 (lane + 4)
-    const int dn = __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false);   // row_shr:4 (lane - 4)
-    return (lane & 4) ? dn : up;
-  } else if constexpr (STRIDE == 8) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false);  // row_ror:8
-  } else if constexpr (STRIDE == 16) {
-    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-    return (lane & 16) ? (int)r[0] : (int)r[1];
-  } else {
-    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return (lane & 32) ? (int)r[0] : (int)r[1];
-  }
-}
-template <int STRIDE>
-__device__ __forceinline__ double xchg_d(double v, int lane) {
-  return __hiloint2double(xchg_i<STRIDE>(__double2hiint(v), lane), xchg_i<STRIDE>(__double2loint(v), lane));
-}
-
 // Row-quad helpers: x[c][i] is row 4 i + q (q = quad lane) of column c.
 
 // e[c] = x[c][ri] for a uniform ri (binary branch tree on ri).

@@ -76,7 +76,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Each wave rotates one column pair of the round (RPT rows per lane, the
-// three inner products reduced within the wave, no LDS), so a workgroup
+// three inner products reduced within the wave by xor butterflies, no LDS), so a workgroup
 // handles four pairs and the round's k/2 pairs need k/8 workgroups; a wave
 // that rotated anything during a sweep sets that sweep's flag once, just
 // before the sweep's last barrier.
@@ -119,9 +119,9 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
           sb = fma(v[e], v[e], sb);
           sg = fma(u[e], v[e], sg);
         }
-        sa = wave_sum(sa);
-        sb = wave_sum(sb);
-        sg = wave_sum(sg);
+        sa = wave_sum_x(sa);
+        sb = wave_sum_x(sb);
+        sg = wave_sum_x(sg);
         if (sg != 0.0 && fabs(sg) > tol * sqrt(sa * sb)) {
           const double z = (sb - sa) / (2.0 * sg);
           const double t = ((z >= 0.0) ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
