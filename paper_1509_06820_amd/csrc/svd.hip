@@ -12,9 +12,9 @@
 // s = c t with a = |x_i|^2, b = |x_j|^2, g = x_i . x_j, and is skipped when
 // |g| <= tol sqrt(a b).  Sweeps stop after one without rotations.
 // Singular values are returned in descending order with U = X V / sigma
-// (a column with sigma == 0 is left zero).  The rounds of a sweep run on up
-// to 256 workgroups (one column pair each, one row per thread) that meet
-// at an arrival barrier after every round.
+// (a column with sigma == 0 is left zero).  The rounds of a sweep run on
+// k/8 workgroups (one wave per column pair, four pairs each) that meet at an
+// arrival barrier after every round.
 #include "kernels.hpp"
 
 namespace rq {
@@ -35,11 +35,11 @@ __device__ __forceinline__ void rr_pair(int r, int idx, int kk, int& p, int& q) 
 }
 
 // Rotation sweeps spread over P workgroups (cooperative launch): in each
-// round a workgroup takes pairs idx = me, me + P, ... of the round-robin
-// order, one row per thread, and the workgroups meet at an arrival barrier
-// before the next round reads the rotated columns.  A workgroup that rotates
-// marks the sweep's flag; after the sweep's last barrier every workgroup
-// reads it, so all of them stop after the same sweep.
+// round wave w of workgroup me takes pairs idx = 4 me + w, 4 me + w + 4 P,
+// ... of the round-robin order, and the workgroups meet at an arrival
+// barrier before the next round reads the rotated columns.  A wave that
+// rotated during the sweep marks the sweep's flag; after the sweep's last
+// barrier every workgroup reads it, so all of them stop after the same sweep.
 // flags[0]: arrival counter, flags[1 + s]: sweep s rotated (zeroed by the
 // caller).
 constexpr int JW_T = 256;             // threads of a sweep workgroup: four waves, one column pair each
