@@ -3,7 +3,7 @@
 // diagonal, reflector tails below it, tau per column; the explicit unit-lower
 // reflector block Y is written as well for the block-reflector products.
 //
-// One cooperative launch.  Workgroup q owns rows [256 q, 256 q + 256) of the
+// One launch (see launch_panel).  Workgroup q owns rows [256 q, 256 q + 256) of the
 // panel in registers (thread = one column x 32 rows).  For column j every
 // workgroup forms its partial inner products of column j with columns j..bJ-1
 // over its rows below j, publishes them (plus row j if it owns it), and after
@@ -172,8 +172,16 @@ int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, doub
   a.flags = w.flags;
   a.err = w.err;
   a.gate = w.gate;
-  void* args[] = {&a};
-  RQ_HIP(hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(a.NP), dim3(PN_THREADS), args, 0, s));
+  // An ordinary launch, not a cooperative one: the kernel is the fallback of
+  // the CholeskyQR panel and almost always leaves at its gate, before any
+  // exchange, and a cooperative dispatch costs the queue tens of
+  // microseconds per block.  When the gate is set, the NP workgroups (one
+  // per 256 rows, 512 threads each) are resident together on an otherwise
+  // idle device; the exchange waits are bounded, so a workgroup that was not
+  // resident in time makes the call report failure (info = -1) instead of
+  // hanging.
+  hipLaunchKernelGGL(panel_kernel, dim3(a.NP), dim3(PN_THREADS), 0, s, a);
+  RQ_HIP(hipGetLastError());
   return 0;
 }
 
