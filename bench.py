@@ -17,6 +17,8 @@ Other workloads (one JSON line each, same keys):
     --workload rsrqrcp_c2   RSRQRCP (Alg. 5, a new sample per block) on the same
                             matrix, with RQRCP and QR timed beside it
     --workload c3 [--jmax J]  TRQRCP + TUXV (Alg. 7 with j_max = J) at k = 256
+    --workload c3 --mixed     the same TUXV in mixed precision (FP32 matrix cores
+                            for the products with A, FP64 otherwise)
 """
 
 import argparse
@@ -127,17 +129,20 @@ def run_c3(args):
     A_host, prm = inputs.config_matrix("c3")
     k, b, p, seed = prm["k"], prm["b"], prm["p"], prm["seed"]
     jmax = args.jmax
+    mixed = args.mixed
+    if mixed and jmax != 1:
+        raise SystemExit("--mixed takes j_max = 1")
     m, n = A_host.shape
     A = torch.from_numpy(A_host).cuda()
     W, K = args.warmup, args.steps
-    print(f"[bench] workload c3 {m}x{n} k={k} b={b} p={p} jmax={jmax}: {W} warmup + {K} timed solves",
-          file=sys.stderr, flush=True)
+    print(f"[bench] workload c3 {m}x{n} k={k} b={b} p={p} jmax={jmax} mixed={mixed}: {W} warmup + {K} timed "
+          f"solves", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     w_trq = binding.workspace(binding.RQ_OP_TRQRCP, m, n, k, b, p, A.device)
-    w_tux = binding.workspace(binding.RQ_OP_TUXV, m, n, k, b, p, A.device)
+    w_tux = binding.workspace(binding.RQ_OP_TUXV_MIXED if mixed else binding.RQ_OP_TUXV, m, n, k, b, p, A.device)
     for _ in range(W):
         binding.rq_trqrcp(A, k, b, p, seed, work=w_trq)
-        binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax)
+        binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax, mixed=mixed)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     trq = []
@@ -151,7 +156,7 @@ def run_c3(args):
     res = None
     for i in range(K):
         ev[i][0].record(stream)
-        res = binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax)
+        res = binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax, mixed=mixed)
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     lat = np.array([a.elapsed_time(z) for a, z in ev])
@@ -167,8 +172,9 @@ def run_c3(args):
     line = {
         "metric": METRIC,
         "value": round(1e3 / ms, 3),
-        "unit": "TUXV solves/s (fp64, 20000x10000, k=256)" if jmax == 1 else
-                f"TUXV solves/s (fp64, 20000x10000, k=256, j_max={jmax})",
+        "unit": ("TUXV solves/s (mixed fp32/fp64, 20000x10000, k=256)" if mixed else
+                 "TUXV solves/s (fp64, 20000x10000, k=256)" if jmax == 1 else
+                 f"TUXV solves/s (fp64, 20000x10000, k=256, j_max={jmax})"),
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
@@ -177,10 +183,11 @@ def run_c3(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32/f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "tuxv_c3" if jmax == 1 else f"tuxv_c3_jmax{jmax}", "m": m, "n": n, "k": k, "b": b,
-                   "p": p, "seed": seed, "jmax": jmax, "inputs": "U diag(0.9^(i/10)) V^T, Haar factors"},
+        "config": {"workload": "tuxv_c3_mixed" if mixed else "tuxv_c3" if jmax == 1 else f"tuxv_c3_jmax{jmax}",
+                   "m": m, "n": n, "k": k, "b": b, "p": p, "seed": seed, "jmax": jmax,
+                   "inputs": "U diag(0.9^(i/10)) V^T, Haar factors"},
         "tuxv_gflops": round(flops / (ms * 1e-3) / 1e9, 2),
         "trqrcp_ms": round(trq_ms, 3),
         "truncation_error": err,
@@ -204,6 +211,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2_iid", choices=["c2_iid", "c2_lr", "c1", "c3", "rsrqrcp_c2"])
     ap.add_argument("--jmax", type=int, default=1, help="TUXV steps (Alg. 7 j_max) for --workload c3")
+    ap.add_argument("--mixed", action="store_true", help="mixed-precision TUXV for --workload c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=3)
     ap.add_argument("--check", action="store_true", help="residual of the last factorization (untimed)")

@@ -46,7 +46,8 @@ enum {
   RQ_OP_QR = 3,           /* rq_unpivoted_qr                    */
   RQ_OP_SAMPLE_QRCP = 4,  /* rq_sample_qrcp                     */
   RQ_OP_SVD = 5,          /* rq_small_svd                       */
-  RQ_OP_RSRQRCP = 6       /* rq_rsrqrcp                         */
+  RQ_OP_RSRQRCP = 6,      /* rq_rsrqrcp                         */
+  RQ_OP_TUXV_MIXED = 7    /* rq_tuxv_mixed                      */
 };
 
 /* Largest j_max accepted by rq_tuxv_iter. */
@@ -144,6 +145,23 @@ int rq_tuxv(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int6
 int rq_tuxv_omega(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
                   const double* Omega, int64_t ldo, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt,
                   void* work, size_t work_bytes, int32_t* info);
+
+/*
+ * TUXV in mixed precision (j_max = 1): the three products that stream the
+ * whole matrix -- the sketch Omega A, the per-block Y2^T A of TRQRCP and
+ * Z = A V -- run on the FP32 matrix cores (operands rounded to FP32, FP32
+ * accumulation) from an FP32 copy of A made inside the call and permuted
+ * along with A; the panels, reflectors, T, the rows of R, the sample QRCP,
+ * the orthogonal factors and the SVD of X stay FP64.  The FP32 rounding of
+ * those products (relative ~ sqrt(n) 6e-8) is far below the truncation
+ * errors this path is meant for; an approximation whose error approaches
+ * it needs rq_tuxv.  Pivots may differ from rq_tuxv's where two sample
+ * norms lie within the FP32 rounding of each other.  Arguments as rq_tuxv;
+ * workspace: RQ_OP_TUXV_MIXED (RQ_OP_TUXV plus 4 m n + 8 n k bytes).
+ */
+int rq_tuxv_mixed(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
+                  uint64_t seed, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt, void* work,
+                  size_t work_bytes, int32_t* info);
 
 /*
  * TUXV with j_max >= 1 iterations -- Alg. 7 (Section 6): after the first LQ,

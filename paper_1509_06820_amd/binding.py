@@ -19,7 +19,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librqrcp.so")
 
-RQ_OP_RQRCP, RQ_OP_TRQRCP, RQ_OP_TUXV, RQ_OP_QR, RQ_OP_SAMPLE_QRCP, RQ_OP_SVD, RQ_OP_RSRQRCP = range(7)
+(RQ_OP_RQRCP, RQ_OP_TRQRCP, RQ_OP_TUXV, RQ_OP_QR, RQ_OP_SAMPLE_QRCP, RQ_OP_SVD, RQ_OP_RSRQRCP,
+ RQ_OP_TUXV_MIXED) = range(8)
 RQ_TUXV_MAX_ITER = 64
 
 _c_i32, _c_i64, _c_u64, _c_sz, _c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p
@@ -33,6 +34,8 @@ _SIGS = {
                         _c_p], ctypes.c_int),
     "rq_rsrqrcp": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz, _c_p],
                    ctypes.c_int),
+    "rq_tuxv_mixed": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_i64, _c_p, _c_p,
+                       _c_i64, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_tuxv_iter": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_i32, _c_p, _c_i64, _c_p,
                       _c_p, _c_i64, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_trqrcp": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz,
@@ -188,9 +191,10 @@ def rq_trqrcp(A, k, b, p, seed=0, Omega=None, work=None, stream=None):
     return F, tau, jpvt, info
 
 
-def rq_tuxv(A, k, b, p, seed=0, Omega=None, work=None, stream=None, jmax=1):
+def rq_tuxv(A, k, b, p, seed=0, Omega=None, work=None, stream=None, jmax=1, mixed=False):
     """Alg. 7 + SVD of X.  Returns (U, sigma, VT, info).  jmax > 1 (seeded
-    Omega only) runs the further LQ/QR steps through rq_tuxv_iter."""
+    Omega only) runs the further LQ/QR steps through rq_tuxv_iter; mixed=True
+    (j_max = 1, seeded Omega) the mixed-precision path rq_tuxv_mixed."""
     Af = fortran(A)
     m, n = Af.shape
     dev = Af.device
@@ -199,9 +203,15 @@ def rq_tuxv(A, k, b, p, seed=0, Omega=None, work=None, stream=None, jmax=1):
     sigma = torch.empty(k, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     if work is None:
-        work = workspace(RQ_OP_TUXV, m, n, k, b, p, dev)
+        work = workspace(RQ_OP_TUXV_MIXED if mixed else RQ_OP_TUXV, m, n, k, b, p, dev)
     L = load()
-    if jmax != 1:
+    if mixed:
+        if Omega is not None or jmax != 1:
+            raise ValueError("the mixed-precision path takes j_max = 1 and the seeded compression matrix")
+        rc = L.rq_tuxv_mixed(_stream(stream), m, n, k, _ptr(Af), _ld(Af), b, p, seed, _ptr(U), m, _ptr(sigma),
+                             _ptr(VT), k, _ptr(work), work.numel(), _ptr(info))
+        _check(rc, "rq_tuxv_mixed")
+    elif jmax != 1:
         if Omega is not None:
             raise ValueError("jmax > 1 takes the seeded compression matrix")
         rc = L.rq_tuxv_iter(_stream(stream), m, n, k, _ptr(Af), _ld(Af), b, p, seed, jmax, _ptr(U), m, _ptr(sigma),

@@ -284,6 +284,7 @@ struct TrqWS {
   double* yall;   // m x k
   double* wt;     // k x n
   double* gk;     // b x k
+  float* a32 = nullptr;  // mixed precision: FP32 copy of A (ld m), permuted with A
 };
 
 void carve_trq(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TrqWS& t) {
@@ -309,7 +310,16 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
     Om = t.sb.omega;
     ldom = l;
   }
-  RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, t.sb.smp, t.sb.ls, t.bb.splitk, t.bb.splitk_elems));
+  if (t.a32) {
+    // mixed precision: Omega A on the FP32 matrix cores from the FP32 copy
+    const double dm = (double)m, dn = (double)n, dl = (double)l;
+    ProfScope ps(PC_SKETCH, s, 4.0 * dm * dn + 8.0 * (dl * dm + dl * dn), 2.0 * dl * dm * dn);
+    RQ_TRY(launch_gemm_f32(s, false, false, l, n, m, 1.0, Om, ldom, t.a32, m, 0.0, t.sb.smp, t.sb.ls, t.bb.splitk,
+                           t.bb.splitk_elems));
+    RQ_TRY(launch_zero_rows(s, l, t.sb.ls, n, t.sb.smp, t.sb.ls));
+  } else {
+    RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, t.sb.smp, t.sb.ls, t.bb.splitk, t.bb.splitk_elems));
+  }
   for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
     const int bJ = (int)std::min<int64_t>(b, k - i0);
     const int64_t mJ = m - i0, nJ = n - i0, Nt = n - i0 - bJ;
@@ -321,6 +331,7 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
     {
       ProfScope ps(PC_SWAP, s, 32.0 * (m + i0) * bJ, 0.0);
       RQ_TRY(launch_apply_swaps(s, t.sb.piv, bJ, i0, A, lda, m, jpvt));
+      if (t.a32) RQ_TRY(launch_apply_swaps_f32(s, t.sb.piv, bJ, i0, t.a32, m, m));
       if (i0 > 0) RQ_TRY(launch_apply_swaps(s, t.sb.piv, bJ, i0, t.wt, k, i0, nullptr));
     }
     double* panel = A + i0 + i0 * lda;
@@ -339,8 +350,12 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
       {
         ProfScope ps(PC_GEMM_YTA, s, 8.0 * ((double)mJ * Nt + (double)mJ * bJ + (double)bJ * Nt),
                      2.0 * bJ * (double)Nt * mJ);
-        RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y2, m, Atr, lda, 0.0, t.bb.zbuf, bJ, t.bb.splitk,
-                           t.bb.splitk_elems));
+        if (t.a32)  // mixed precision: from the FP32 copy on the FP32 matrix cores
+          RQ_TRY(launch_gemm_f32(s, true, false, bJ, Nt, mJ, 1.0, Y2, m, t.a32 + i0 + (i0 + bJ) * m, m, 0.0,
+                                 t.bb.zbuf, bJ, t.bb.splitk, t.bb.splitk_elems));
+        else
+          RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y2, m, Atr, lda, 0.0, t.bb.zbuf, bJ, t.bb.splitk,
+                             t.bb.splitk_elems));
       }
       ProfScope ps(PC_TRQ_PRODUCTS, s, 8.0 * ((double)mJ * (bJ + i0) + 2.0 * (i0 + bJ) * Nt + 3.0 * bJ * Nt),
                    2.0 * bJ * ((double)i0 * mJ + 2.0 * i0 * Nt + (double)bJ * Nt + (double)bJ * Nt));
@@ -431,9 +446,10 @@ struct TuxvWS {
   double* vx;      // k x k
   double* svdtmp;  // k x k
   unsigned* svdflags;  // arrival counter and per-sweep flags of the Jacobi sweeps
+  double* vperm;   // mixed precision: n x k, rows of V in the column order of A P
 };
 
-void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS& t) {
+void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS& t, bool mixed = false) {
   carve_trq(cv, m, n, k, b, p, t.trq);
   carve_qr(cv, n, k, b, t.qz);
   carve_qr(cv, m, k, b, t.qu);
@@ -454,17 +470,26 @@ void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS
   t.vx = cv.take<double>((size_t)k * k);
   t.svdtmp = cv.take<double>((size_t)k * k);
   t.svdflags = cv.take<unsigned>(128);
+  t.vperm = nullptr;
+  if (mixed) {
+    t.trq.a32 = cv.take<float>((size_t)m * n);
+    t.vperm = cv.take<double>((size_t)n * k);
+  }
 }
 
 // Alg. 7 with jmax multiply-and-factorize steps after the first LQ, then the
 // SVD of the last connection matrix X: A ~ (U Ux) diag(sigma) (Vx^T V^T).
 int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int b, int p,
               uint64_t seed, const double* Omega, int64_t ldo, double* U, int64_t ldu, double* sigma, double* VT,
-              int64_t ldvt, void* work, size_t wbytes, int32_t* info, int jmax = 1) {
+              int64_t ldvt, void* work, size_t wbytes, int32_t* info, int jmax = 1, bool mixed = false) {
   TuxvWS t;
   Carve cv(work, wbytes);
-  carve_tuxv(cv, m, n, k, b, p, t);
+  carve_tuxv(cv, m, n, k, b, p, t, mixed);
   if (!cv.ok) return RQ_ERR_WORKSPACE;
+  if (mixed) {
+    ProfScope ps(PC_TUXV_PRODUCTS, s, 12.0 * m * n, 0.0);
+    RQ_TRY(launch_to_f32(s, m, n, A, lda, t.trq.a32, m));
+  }
   // TRQRCP on a copy: A itself is needed again for Z1 = A V.
   {
     ProfScope ps(PC_TUXV_PRODUCTS, s, 16.0 * m * n, 0.0);
@@ -476,8 +501,12 @@ int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, i
   // LQ of Z0 as the QR of Z0^T -> V (n x k)
   RQ_TRY(qr_explicit(s, n, k, t.z0t, n, b, t.tz, t.qz));
   RQ_TRY(form_q(s, n, k, b, t.qz, t.v, n));
-  // Z1 = A V (m x k)
-  {
+  // Z1 = A V (m x k); mixed precision: (A P) (P^T V) from the permuted FP32 copy
+  if (mixed) {
+    ProfScope ps(PC_TUXV_PRODUCTS, s, 4.0 * m * n + 8.0 * (2.0 * n * k + (double)m * k), 2.0 * m * (double)n * k);
+    RQ_TRY(launch_gather_rows(s, n, k, t.v, n, t.jp, t.vperm, n));
+    RQ_TRY(launch_gemm_f32(s, false, false, m, k, n, 1.0, t.trq.a32, m, t.vperm, n, 0.0, t.z1, m, nullptr, 0));
+  } else {
     ProfScope ps(PC_TUXV_PRODUCTS, s, 8.0 * ((double)m * n + (double)n * k + (double)m * k), 2.0 * m * (double)n * k);
     RQ_TRY(launch_gemm(s, false, false, m, k, n, 1.0, A, lda, t.v, n, 0.0, t.z1, m, nullptr, 0));
   }
@@ -572,11 +601,12 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
       sz = cv.off;
       break;
     }
-    case RQ_OP_TUXV: {
+    case RQ_OP_TUXV:
+    case RQ_OP_TUXV_MIXED: {
       if (k < 1 || k > std::min(m, n) || k > 1024) return -4;
       TuxvWS t;
       Carve cv(nullptr, 0);
-      carve_tuxv(cv, m, n, k, b, p, t);
+      carve_tuxv(cv, m, n, k, b, p, t, op == RQ_OP_TUXV_MIXED);
       sz = cv.off;
       break;
     }
@@ -698,6 +728,18 @@ int rq_tuxv_iter(void* stream, int64_t m, int64_t n, int64_t k, const double* A,
   if (ldvt < k) return -15;
   return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, U, ldu, sigma, VT, ldvt, work,
                    work_bytes, info, jmax);
+}
+
+int rq_tuxv_mixed(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
+                  uint64_t seed, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt, void* work,
+                  size_t work_bytes, int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
+  if (rc) return rc;
+  if (k < 1 || k > std::min(m, n) || k > 1024) return -4;
+  if (ldu < m) return -11;
+  if (ldvt < k) return -14;
+  return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, U, ldu, sigma, VT, ldvt, work,
+                   work_bytes, info, 1, true);
 }
 
 int rq_tuxv_omega(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,

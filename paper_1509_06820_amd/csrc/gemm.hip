@@ -19,23 +19,43 @@
 //
 // Split-K (grid.z > 1) writes partial sums to a scratch buffer; a second
 // kernel adds them in a fixed order (deterministic, no atomics).
+//
+// The same kernel, instantiated with FP32 accumulation, serves the mixed-
+// precision products: operands are read in their stored precision (one of
+// them an FP32 copy of A), rounded to FP32 into the LDS tiles and multiplied
+// on v_mfma_f32_16x16x4_f32, whose operands are laid out as those of the
+// FP64 instruction but whose accumulator registers run along the other
+// index: with the operands swapped, register r of lane l holds
+// C(i0 + l%16, j0 + 4 (l/16) + r).  C and the split-K partials stay FP64.
+#include <type_traits>
 #include "kernels.hpp"
 
 namespace rq {
 
 namespace {
 
-template <int BM, int BN, int BK>
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int BK, typename Acc>
 constexpr size_t gemm_lds_bytes() {
-  return (size_t)2 * BK * ((BM + 2) + (BN + 2)) * sizeof(double);
+  return (size_t)2 * BK * ((BM + 2) + (BN + 2)) * sizeof(Acc);
 }
 
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+template <typename Acc>
+struct Acc4;
+template <>
+struct Acc4<double> { typedef double4_t type; };
+template <>
+struct Acc4<float> { typedef float4_t type; };
+
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe = double, typename TBe = double,
+          typename Acc = double>
 __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
-                                                   const double* __restrict__ A, int64_t lda,
-                                                   const double* __restrict__ B, int64_t ldb, double beta,
+                                                   const TAe* __restrict__ A, int64_t lda,
+                                                   const TBe* __restrict__ B, int64_t ldb, double beta,
                                                    double* __restrict__ C, int64_t ldc, int64_t kchunk,
                                                    int64_t split_stride) {
+  typedef typename Acc4<Acc>::type acc4_t;
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int TM = WTM / 16, TN = WTN / 16;
   constexpr int ALD = BM + 2, BLD = BN + 2;  // padded rows: no bank conflicts between k rows
@@ -43,9 +63,10 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
   static_assert(A_PER * 256 == BM * BK && B_PER * 256 == BK * BN, "tile/threads mismatch");
   static_assert(WM * WN == 4, "four waves");
   // two LDS stages: the tiles of step k+1 are stored while step k computes
-  extern __shared__ __align__(16) double gsm[];
-  double* As = gsm;                   // [2][BK][ALD]
-  double* Bs = gsm + 2 * BK * ALD;    // [2][BK][BLD]
+  extern __shared__ __align__(16) double gsm_raw[];
+  Acc* gsm = reinterpret_cast<Acc*>(gsm_raw);
+  Acc* As = gsm;                   // [2][BK][ALD]
+  Acc* Bs = gsm + 2 * BK * ALD;    // [2][BK][BLD]
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -60,9 +81,12 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
   // i = row0 + lane%16, j = col0 + 4r + lane/16): all C loads are issued
   // together, ahead of the first operand tiles, and alpha is folded into the
   // A tile, so the epilogue is stores only.
-  double4_t acc[TM][TN];
+  acc4_t acc[TM][TN];
+  constexpr bool F64 = std::is_same<Acc, double>::value;
   const int64_t ri = i0 + wm * WTM + (lane & 15);
-  const int64_t cj = j0 + wn * WTN + (lane >> 4);
+  // column of accumulator register r: cj + 16 b + CR * r
+  const int64_t cj = j0 + wn * WTN + (F64 ? (lane >> 4) : 4 * (lane >> 4));
+  constexpr int CR = F64 ? 4 : 1;
   if (beta != 0.0) {
 #pragma unroll
     for (int a = 0; a < TM; ++a)
@@ -70,23 +94,26 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
       for (int b = 0; b < TN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t gi = ri + a * 16, gj = cj + b * 16 + 4 * r;
-          acc[a][b][r] = (gi < M && gj < N) ? Cz[gi + gj * ldc] : 0.0;
+          const int64_t gi = ri + a * 16, gj = cj + b * 16 + CR * r;
+          acc[a][b][r] = (Acc)((gi < M && gj < N) ? Cz[gi + gj * ldc] : 0.0);
         }
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
       for (int b = 0; b < TN; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[a][b][r] *= beta;
+        for (int r = 0; r < 4; ++r) acc[a][b][r] *= (Acc)beta;
   } else {
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
-      for (int b = 0; b < TN; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[a][b][r] = (Acc)0;
   }
 
-  double ra[A_PER], rb[B_PER];
+  TAe ra[A_PER];
+  TBe rb[B_PER];
 
   auto load_tiles = [&](int64_t k0) {
 #pragma unroll
@@ -95,7 +122,7 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
       int ii, kk;
       if (TA) { kk = idx % BK; ii = idx / BK; } else { ii = idx % BM; kk = idx / BM; }
       const int64_t gi = i0 + ii, gk = k0 + kk;
-      double v = 0.0;
+      TAe v = (TAe)0;
       if (gi < M && gk < kend) v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
       ra[e] = v;
     }
@@ -105,27 +132,27 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
       int jj, kk;
       if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
       const int64_t gj = j0 + jj, gk = k0 + kk;
-      double v = 0.0;
+      TBe v = (TBe)0;
       if (gj < N && gk < kend) v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
       rb[e] = v;
     }
   };
   auto store_tiles = [&](int stage) {
-    double* as = As + stage * BK * ALD;
-    double* bs = Bs + stage * BK * BLD;
+    Acc* as = As + stage * BK * ALD;
+    Acc* bs = Bs + stage * BK * BLD;
 #pragma unroll
     for (int e = 0; e < A_PER; ++e) {
       const int idx = tid + e * 256;
       int ii, kk;
       if (TA) { kk = idx % BK; ii = idx / BK; } else { ii = idx % BM; kk = idx / BM; }
-      as[kk * ALD + ii] = alpha * ra[e];
+      as[kk * ALD + ii] = (Acc)(alpha * (double)ra[e]);
     }
 #pragma unroll
     for (int e = 0; e < B_PER; ++e) {
       const int idx = tid + e * 256;
       int jj, kk;
       if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
-      bs[kk * BLD + jj] = rb[e];
+      bs[kk * BLD + jj] = (Acc)rb[e];
     }
   };
 
@@ -137,11 +164,11 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
       const bool more = k0 + BK < kend;
       if (more) load_tiles(k0 + BK);
-      const double* as = As + stage * BK * ALD;
-      const double* bs = Bs + stage * BK * BLD;
+      const Acc* as = As + stage * BK * ALD;
+      const Acc* bs = Bs + stage * BK * BLD;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        double af[TM], bf[TN];
+        Acc af[TM], bf[TN];
 #pragma unroll
         for (int a = 0; a < TM; ++a) af[a] = as[(kk + (lane >> 4)) * ALD + wm * WTM + a * 16 + (lane & 15)];
 #pragma unroll
@@ -150,7 +177,12 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
         for (int a = 0; a < TM; ++a)
 #pragma unroll
           for (int b = 0; b < TN; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+          {
+            if constexpr (std::is_same<Acc, double>::value)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+            else
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[b], af[a], acc[a][b], 0, 0, 0);
+          }
       }
       if (more) store_tiles(stage ^ 1);
       __syncthreads();
@@ -164,8 +196,8 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = ri + a * 16, gj = cj + b * 16 + 4 * r;
-        if (gi < M && gj < N) Cz[gi + gj * ldc] = acc[a][b][r];
+        const int64_t gi = ri + a * 16, gj = cj + b * 16 + CR * r;
+        if (gi < M && gj < N) Cz[gi + gj * ldc] = (double)acc[a][b][r];
       }
 }
 
@@ -212,39 +244,39 @@ __global__ void __launch_bounds__(256) splitk_reduce_many_kernel(int64_t M, int6
   }
 }
 
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
-int launch_one(hipStream_t s, dim3 grid, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
-               const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe, typename TBe, typename Acc>
+int launch_one(hipStream_t s, dim3 grid, int64_t M, int64_t N, int64_t K, double alpha, const TAe* A, int64_t lda,
+               const TBe* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
                int64_t split_stride) {
-  constexpr size_t lds = gemm_lds_bytes<BM, BN, BK>();
+  constexpr size_t lds = gemm_lds_bytes<BM, BN, BK, Acc>();
   static bool attr = false;
   if (!attr) {
-    RQ_HIP(hipFuncSetAttribute((const void*)gemm_kernel<BM, BN, BK, WM, WN, TA, TB>,
+    RQ_HIP(hipFuncSetAttribute((const void*)gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
-  hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, TA, TB>), grid, dim3(256), lds, s, M, N, K, alpha, A, lda, B,
-                     ldb, beta, C, ldc, kchunk, split_stride);
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc>), grid, dim3(256), lds, s, M, N, K,
+                     alpha, A, lda, B, ldb, beta, C, ldc, kchunk, split_stride);
   RQ_HIP(hipGetLastError());
   return 0;
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
-int launch_tiles(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-                 int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int splits,
+template <int BM, int BN, int BK, int WM, int WN, typename TAe, typename TBe, typename Acc>
+int launch_tiles(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const TAe* A,
+                 int64_t lda, const TBe* B, int64_t ldb, double beta, double* C, int64_t ldc, int splits,
                  int64_t kchunk, int64_t split_stride) {
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
   if (!ta && !tb)
-    return launch_one<BM, BN, BK, WM, WN, false, false>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
-                                                         split_stride);
+    return launch_one<BM, BN, BK, WM, WN, false, false, TAe, TBe, Acc>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta,
+                                                                       C, ldc, kchunk, split_stride);
   if (ta && !tb)
-    return launch_one<BM, BN, BK, WM, WN, true, false>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
-                                                        split_stride);
+    return launch_one<BM, BN, BK, WM, WN, true, false, TAe, TBe, Acc>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta,
+                                                                      C, ldc, kchunk, split_stride);
   if (!ta && tb)
-    return launch_one<BM, BN, BK, WM, WN, false, true>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
-                                                        split_stride);
-  return launch_one<BM, BN, BK, WM, WN, true, true>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
-                                                     split_stride);
+    return launch_one<BM, BN, BK, WM, WN, false, true, TAe, TBe, Acc>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta,
+                                                                      C, ldc, kchunk, split_stride);
+  return launch_one<BM, BN, BK, WM, WN, true, true, TAe, TBe, Acc>(s, grid, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                                   ldc, kchunk, split_stride);
 }
 
 }  // namespace
@@ -276,9 +308,10 @@ size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K) {
   return e;
 }
 
-int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
-                size_t scratch_elems) {
+template <typename TAe, typename TBe, typename Acc>
+static int gemm_dispatch(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const TAe* A,
+                         int64_t lda, const TBe* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
+                         size_t scratch_elems) {
   if (M <= 0 || N <= 0) return 0;
   if (K <= 0) {
     // C = beta * C
@@ -315,11 +348,11 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
   auto tiles = [&](double al, double be, double* out, int64_t ldo, int64_t stride) {
     switch (shape) {
       case BIG:
-        return launch_tiles<128, 64, BK, 2, 2>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo, splits, kchunk,
-                                               stride);
+        return launch_tiles<128, 64, BK, 2, 2, TAe, TBe, Acc>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo,
+                                                              splits, kchunk, stride);
       default:
-        return launch_tiles<64, 64, BK, 2, 2>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo, splits, kchunk,
-                                              stride);
+        return launch_tiles<64, 64, BK, 2, 2, TAe, TBe, Acc>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo,
+                                                             splits, kchunk, stride);
     }
   };
   if (splits == 1) return tiles(alpha, beta, C, ldc, 0);
@@ -337,6 +370,27 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
   return 0;
 }
 
+int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
+                size_t scratch_elems) {
+  return gemm_dispatch<double, double, double>(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch,
+                                               scratch_elems);
+}
+
+int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A,
+                    int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
+                    size_t scratch_elems) {
+  return gemm_dispatch<float, double, float>(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch,
+                                             scratch_elems);
+}
+
+int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                    int64_t lda, const float* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
+                    size_t scratch_elems) {
+  return gemm_dispatch<double, float, float>(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch,
+                                             scratch_elems);
+}
+
 namespace {
 __global__ void __launch_bounds__(256) scale_kernel(int64_t M, int64_t N, double beta, double* C, int64_t ldc) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -345,6 +399,25 @@ __global__ void __launch_bounds__(256) scale_kernel(int64_t M, int64_t N, double
   C[i + j * ldc] *= beta;
 }
 }  // namespace
+
+namespace {
+// dst = src rounded to FP32; one thread per element, rows contiguous.
+__global__ void __launch_bounds__(256) to_f32_kernel(int64_t rows, int64_t cols, const double* __restrict__ src,
+                                                     int64_t lds, float* __restrict__ dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = idx - j * rows;
+  dst[i + j * ldd] = (float)src[i + j * lds];
+}
+}  // namespace
+
+int launch_to_f32(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst, int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return 0;
+  hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((rows * cols + 255) / 256)), dim3(256), 0, s, rows, cols, src,
+                     lds, dst, ldd);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
 
 int launch_scale(hipStream_t s, int64_t M, int64_t N, double beta, double* C, int64_t ldc) {
   if (M <= 0 || N <= 0) return 0;

@@ -16,6 +16,16 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
                 int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
                 size_t scratch_elems);
 size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K);
+// The same products on the FP32 matrix cores (operands rounded to FP32,
+// FP32 accumulation, FP64 C), with one operand stored in FP32.
+int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A,
+                    int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
+                    size_t scratch_elems);
+int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                    int64_t lda, const float* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
+                    size_t scratch_elems);
+// dst (FP32, rows x cols, ld ldd) = src (FP64, ld lds) rounded to nearest.
+int launch_to_f32(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst, int64_t ldd);
 int launch_scale(hipStream_t s, int64_t M, int64_t N, double beta, double* C, int64_t ldc);
 
 // Sample QRCP (Alg. 1 on the sample, bJ steps) in place on the l x nJ sample.
@@ -42,6 +52,9 @@ int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ,
 // columns of an R x ncols matrix (double) and optionally to an int64 vector.
 int launch_apply_swaps(hipStream_t s, const int* piv, int bJ, int64_t offset, double* M, int64_t ldm, int64_t rows,
                        int64_t* jpvt);
+// The same composed permutation applied to an FP32 copy (no jpvt).
+int launch_apply_swaps_f32(hipStream_t s, const int* piv, int bJ, int64_t offset, float* M, int64_t ldm,
+                           int64_t rows);
 
 // Householder panel QR (in-place layout), tau, explicit unit-lower Y, one
 // column at a time.  With `gate` set, the kernel runs only if *gate != 0.
@@ -80,6 +93,9 @@ int launch_copy2d(hipStream_t s, int64_t rows, int64_t cols, const double* src, 
                   int64_t ldd);
 int launch_set_identity(hipStream_t s, int64_t rows, int64_t cols, double* M, int64_t ldm);
 // Z0T(jpvt[j], i) = R(i, j) for i <= j (upper trapezoidal R, k x n) else 0.
+// Vp(i, :) = V(jpvt[i], :) for i < n (k columns).
+int launch_gather_rows(hipStream_t s, int64_t n, int64_t k, const double* V, int64_t ldv, const int64_t* jpvt,
+                       double* Vp, int64_t ldp);
 int launch_scatter_rt(hipStream_t s, int64_t k, int64_t n, const double* R, int64_t ldr, const int64_t* jpvt,
                       double* Z0T, int64_t ldz);
 // Upper-triangular part of a k x k block (zeros below the diagonal).

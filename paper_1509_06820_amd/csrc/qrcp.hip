@@ -835,12 +835,13 @@ int launch_sq(hipStream_t s, SqParams& a) {
 // ------------------------------------------------------------------ swaps
 constexpr int SW_ROWS = 16;  // rows per workgroup (8192 rows: 512 workgroups)
 
+template <typename T>
 __global__ void __launch_bounds__(256) apply_swaps_kernel(const int* __restrict__ piv, int bJ, int64_t offset,
-                                                          double* M, int64_t ldm, int64_t rows, int64_t* jpvt) {
+                                                          T* M, int64_t ldm, int64_t rows, int64_t* jpvt) {
   __shared__ int dst[128], src[128];
   __shared__ int npair;
   __shared__ int pv[SQ_BMAX];
-  __shared__ double tile[128 * SW_ROWS];
+  __shared__ T tile[128 * SW_ROWS];
   __shared__ int64_t itile[128];
   const int tid = threadIdx.x;
   if (tid == 0) npair = 0;
@@ -978,6 +979,15 @@ __global__ void set_identity_kernel(int64_t rows, int64_t cols, double* M, int64
   M[i + j * ldm] = (i == j) ? 1.0 : 0.0;
 }
 
+// Vp(i, c) = V(jpvt[i], c): the rows of V in the column order of A P.
+__global__ void gather_rows_kernel(int64_t n, int64_t k, const double* __restrict__ V, int64_t ldv,
+                                   const int64_t* __restrict__ jpvt, double* __restrict__ Vp, int64_t ldp) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t c = idx / n, i = idx - c * n;
+  Vp[i + c * ldp] = V[jpvt[i] + c * ldv];
+}
+
 __global__ void scatter_rt_kernel(int64_t k, int64_t n, const double* __restrict__ R, int64_t ldr,
                                   const int64_t* __restrict__ jpvt, double* __restrict__ Z, int64_t ldz) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1027,7 +1037,18 @@ int launch_apply_swaps(hipStream_t s, const int* piv, int bJ, int64_t offset, do
   if (bJ <= 0) return 0;
   if (bJ > SQ_BMAX) return -5;
   const unsigned grid = std::max<unsigned>(1u, blocks_for(rows, SW_ROWS));
-  hipLaunchKernelGGL(apply_swaps_kernel, dim3(grid), dim3(256), 0, s, piv, bJ, offset, M, ldm, rows, jpvt);
+  hipLaunchKernelGGL(apply_swaps_kernel<double>, dim3(grid), dim3(256), 0, s, piv, bJ, offset, M, ldm, rows, jpvt);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_apply_swaps_f32(hipStream_t s, const int* piv, int bJ, int64_t offset, float* M, int64_t ldm,
+                           int64_t rows) {
+  if (bJ <= 0) return 0;
+  if (bJ > SQ_BMAX) return -5;
+  const unsigned grid = std::max<unsigned>(1u, blocks_for(rows, SW_ROWS));
+  hipLaunchKernelGGL(apply_swaps_kernel<float>, dim3(grid), dim3(256), 0, s, piv, bJ, offset, M, ldm, rows,
+                     (int64_t*)nullptr);
   RQ_HIP(hipGetLastError());
   return 0;
 }
@@ -1071,6 +1092,14 @@ int launch_copy2d(hipStream_t s, int64_t rows, int64_t cols, const double* src, 
 int launch_set_identity(hipStream_t s, int64_t rows, int64_t cols, double* M, int64_t ldm) {
   if (rows <= 0 || cols <= 0) return 0;
   hipLaunchKernelGGL(set_identity_kernel, dim3(blocks_for(rows * cols, 256)), dim3(256), 0, s, rows, cols, M, ldm);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_gather_rows(hipStream_t s, int64_t n, int64_t k, const double* V, int64_t ldv, const int64_t* jpvt,
+                       double* Vp, int64_t ldp) {
+  if (n <= 0 || k <= 0) return 0;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for(n * k, 256)), dim3(256), 0, s, n, k, V, ldv, jpvt, Vp, ldp);
   RQ_HIP(hipGetLastError());
   return 0;
 }

@@ -111,6 +111,20 @@ def test_entry_points_reject_bad_arguments_before_any_launch(lib):
     assert lib.rq_tuxv_iter(null, 40, 40, 8, null, 40, 8, 0, 1, 3, null, 40, null, null, 8, null, 16, null) == -100
 
 
+def test_mixed_tuxv_workspace_and_arguments(lib):
+    """The mixed path adds the FP32 copy of A (4 m n bytes) and the permuted
+    V (8 n k bytes) to the TUXV workspace."""
+    m, n, k, b, p = 20000, 10000, 256, 64, 8
+    extra = (binding.rq_workspace_bytes(binding.RQ_OP_TUXV_MIXED, m, n, k, b, p)
+             - binding.rq_workspace_bytes(binding.RQ_OP_TUXV, m, n, k, b, p))
+    assert 4 * m * n + 8 * n * k <= extra <= 4 * m * n + 8 * n * k + 1024
+    null = ctypes.c_void_p(0)
+    assert lib.rq_tuxv_mixed(null, 10, 10, 0, null, 10, 4, 4, 1, null, 10, null, null, 1, null, 0, null) == -4
+    assert lib.rq_tuxv_mixed(null, 10, 10, 3, null, 10, 4, 4, 1, null, 9, null, null, 3, null, 0, null) == -11
+    assert lib.rq_tuxv_mixed(null, 10, 10, 3, null, 10, 4, 4, 1, null, 10, null, null, 2, null, 0, null) == -14
+    assert lib.rq_tuxv_mixed(null, 40, 40, 8, null, 40, 8, 0, 1, null, 40, null, null, 8, null, 16, null) == -100
+
+
 def test_rsrqrcp_workspace_matches_rqrcp(lib):
     """Alg. 5 needs the buffers of Alg. 4: one sample and one Omega of the
     first block's size, reused by every block."""
