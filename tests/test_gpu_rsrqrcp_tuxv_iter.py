@@ -86,6 +86,44 @@ def test_rsrqrcp_8192_full_size_gaussian():
     assert orth <= 1e-12
 
 
+def test_rsrqrcp_rank_deficient_zero_and_nan():
+    """Exact rank 20: the first 20 pivots are the oracle's and the trailing
+    block of R vanishes; a zero matrix factors to zeros with the identity
+    permutation; a NaN entry is reported through info."""
+    say("rsrqrcp rank-20 120x90 / zero / nan")
+    A = inputs.rank_r(21, 120, 90, 20)
+    ref = oracle.rsrqrcp(A, 8, 6, seed=3)
+    F, tau, jpvt, info = [host(x) for x in binding.rq_rsrqrcp(dev(A), 8, 6, 3)]
+    assert info[0] == 0
+    assert list(jpvt[:20]) == list(ref["jpvt"][:20])
+    R = np.triu(F[:90])
+    assert np.linalg.norm(R[20:, 20:]) <= 1e-13 * np.linalg.norm(A)
+    res, orth = qr_checks(A, F, tau, jpvt, 90)
+    assert res <= 1e-12 and orth <= 1e-13
+    F, tau, jpvt, info = [host(x) for x in binding.rq_rsrqrcp(dev(np.zeros((50, 40))), 8, 4, 1)]
+    assert np.all(F == 0) and np.all(tau == 0) and list(jpvt) == list(range(40)) and info[0] == 0
+    A = inputs.gaussian(1, 50, 40)
+    A[3, 7] = np.nan
+    F, tau, jpvt, info = [host(x) for x in binding.rq_rsrqrcp(dev(A), 8, 4, 1)]
+    assert info[0] > 0
+
+
+def test_tuxv_iter_converges_to_optimum_with_gap():
+    """sigma_{k+1} / sigma_k = 0.1: nine LQ/QR steps are a converged subspace
+    iteration, so the GPU reaches the Eckart-Young error and the leading
+    singular values (the oracle's pin of the same property)."""
+    say("tuxv_iter gap spectrum 300x200 k=12 jmax=9")
+    m, n, k = 300, 200, 12
+    sig = np.concatenate([np.linspace(2.0, 1.0, k), 0.1 * np.linspace(1.0, 0.5, n - k)])
+    A = inputs.with_spectrum(5, m, n, sig)
+    U, s, VT, info = [host(x) for x in binding.rq_tuxv(dev(A), k, 8, 4, 5, jmax=9)]
+    assert info[0] == 0
+    e = np.linalg.norm(A - (U * s) @ VT) / np.linalg.norm(A)
+    e_opt = inputs.optimal_truncation_error(sig, k)
+    assert abs(e - e_opt) <= 1e-10 * e_opt
+    assert np.abs(s - sig[:k]).max() <= 1e-10
+
+
 @pytest.mark.parametrize("m,n,k,b,p,seed,jmax", [
     (400, 300, 40, 16, 8, 1, 2),
     (700, 500, 64, 32, 8, 2, 3),
