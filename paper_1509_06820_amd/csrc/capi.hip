@@ -486,14 +486,13 @@ int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, i
   Carve cv(work, wbytes);
   carve_tuxv(cv, m, n, k, b, p, t, mixed);
   if (!cv.ok) return RQ_ERR_WORKSPACE;
-  if (mixed) {
-    ProfScope ps(PC_TUXV_PRODUCTS, s, 12.0 * m * n, 0.0);
-    RQ_TRY(launch_to_f32(s, m, n, A, lda, t.trq.a32, m));
-  }
+
   // TRQRCP on a copy: A itself is needed again for Z1 = A V.
   {
-    ProfScope ps(PC_TUXV_PRODUCTS, s, 16.0 * m * n, 0.0);
-    RQ_TRY(launch_copy2d(s, m, n, A, lda, t.ac, m));
+    // mixed precision: the FP32 copy of A is written in the same pass
+    ProfScope ps(PC_TUXV_PRODUCTS, s, (mixed ? 20.0 : 16.0) * m * n, 0.0);
+    if (mixed) RQ_TRY(launch_to_f32(s, m, n, A, lda, t.trq.a32, m, t.ac, m));
+    else RQ_TRY(launch_copy2d(s, m, n, A, lda, t.ac, m));
   }
   RQ_TRY(trqrcp_core(s, m, n, k, t.ac, m, b, p, seed, Omega, ldo, t.jp, t.tk, t.trq));
   // Z0 = R P^T, stored transposed (n x k)

@@ -401,20 +401,25 @@ __global__ void __launch_bounds__(256) scale_kernel(int64_t M, int64_t N, double
 }  // namespace
 
 namespace {
-// dst = src rounded to FP32; one thread per element, rows contiguous.
+// dst = src rounded to FP32 (and dst64 = src when given); one thread per
+// element, rows contiguous.
 __global__ void __launch_bounds__(256) to_f32_kernel(int64_t rows, int64_t cols, const double* __restrict__ src,
-                                                     int64_t lds, float* __restrict__ dst, int64_t ldd) {
+                                                     int64_t lds, float* __restrict__ dst, int64_t ldd,
+                                                     double* __restrict__ dst64, int64_t ld64) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const int64_t j = idx / rows, i = idx - j * rows;
-  dst[i + j * ldd] = (float)src[i + j * lds];
+  const double v = src[i + j * lds];
+  dst[i + j * ldd] = (float)v;
+  if (dst64) dst64[i + j * ld64] = v;
 }
 }  // namespace
 
-int launch_to_f32(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst, int64_t ldd) {
+int launch_to_f32(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst, int64_t ldd,
+                  double* dst64, int64_t ld64) {
   if (rows <= 0 || cols <= 0) return 0;
   hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((rows * cols + 255) / 256)), dim3(256), 0, s, rows, cols, src,
-                     lds, dst, ldd);
+                     lds, dst, ldd, dst64, ld64);
   RQ_HIP(hipGetLastError());
   return 0;
 }

@@ -24,8 +24,10 @@ int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64
 int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                     int64_t lda, const float* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
                     size_t scratch_elems);
-// dst (FP32, rows x cols, ld ldd) = src (FP64, ld lds) rounded to nearest.
-int launch_to_f32(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst, int64_t ldd);
+// dst (FP32, rows x cols, ld ldd) = src (FP64, ld lds) rounded to nearest;
+// with dst64, also an FP64 copy in the same pass.
+int launch_to_f32(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst, int64_t ldd,
+                  double* dst64 = nullptr, int64_t ld64 = 0);
 int launch_scale(hipStream_t s, int64_t M, int64_t N, double beta, double* C, int64_t ldc);
 
 // Sample QRCP (Alg. 1 on the sample, bJ steps) in place on the l x nJ sample.
