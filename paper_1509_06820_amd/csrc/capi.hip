@@ -142,16 +142,18 @@ int64_t nblocks(int64_t k, int b) { return (k + b - 1) / b; }
 // Panel QR of A(i0:m, i0:i0+bJ) + connection matrix T of its reflectors:
 // CholeskyQR2 + Householder reconstruction (preconditioned by the sample's
 // S11 when given), with the column-by-column Householder panel as fallback.
+// W11 (with S11): where a successful CholeskyQR writes S11 R11^-1 for the
+// sample update.
 int panel_and_t(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t i0, int bJ, double* tau, double* Y,
                 int64_t ldy, const BlockBufs& bb, const Common& c, int64_t J, const double* S11 = nullptr,
-                int64_t srs = 0, int64_t scs = 0) {
+                int64_t srs = 0, int64_t scs = 0, double* W11 = nullptr) {
   const int64_t mJ = m - i0;
   const double dm = (double)mJ, db = (double)bJ;
   PanelWork pw = panel_work(bb, c, J);
   int* st = (int*)pw.gate;
   ProfScope ps(PC_PANEL, s, 32.0 * dm * db, 6.0 * dm * db * db);
   RQ_TRY(launch_panel_cholqr(s, A + i0 + i0 * lda, lda, mJ, bJ, S11, srs, scs, tau, Y, ldy, bb.T, bb.cq, bb.splitk,
-                             bb.splitk_elems, st));
+                             bb.splitk_elems, st, W11));
   RQ_TRY(launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, pw));
   RQ_TRY(launch_larft_gated(s, mJ, bJ, Y, ldy, tau, bb.T, st));
   return 0;
@@ -176,16 +178,18 @@ int trailing_update(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t n,
 }
 
 // Sample update, eq. (update1): B1 = S12 - (S11 R11^-1) R12, B2 = S22, on the
-// sample columns of this block (S + i0 * ls, ld ls).
+// sample columns of this block (S + i0 * ls, ld ls).  W11 = S11 R11^-1 is
+// already in sb.w11 unless the panel's status word `st` reports that
+// CholeskyQR failed; then it is formed here from R11.
 int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, int bJ, double* s_blk,
-                  const SampleBufs& sb) {
+                  const SampleBufs& sb, const int* st) {
   const int64_t Nt = n - i0 - bJ;
   if (Nt <= 0) return 0;
   const double* R11 = A + i0 + i0 * lda;
   const double* R12 = A + i0 + (i0 + bJ) * lda;
   const double dn = (double)Nt, db = (double)bJ;
   ProfScope ps(PC_SAMPLE_UPDATE, s, 8.0 * (3.0 * db * dn + 2.0 * db * db), 2.0 * db * db * dn + db * db * db / 3.0);
-  RQ_TRY(launch_w11(s, bJ, s_blk, 1, sb.ls, R11, lda, sb.w11));
+  RQ_TRY(launch_w11(s, bJ, s_blk, 1, sb.ls, R11, lda, sb.w11, st));
   // S(0:bJ, bJ:) -= W11 R12
   RQ_TRY(launch_gemm(s, false, false, bJ, Nt, bJ, -1.0, sb.w11, bJ, R12, lda, 1.0, s_blk + (int64_t)bJ * sb.ls, sb.ls,
                      nullptr, 0));
@@ -264,9 +268,11 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
       ProfScope ps(PC_SWAP, s, 32.0 * m * bJ, 0.0);
       RQ_TRY(launch_apply_swaps(s, f.sb.piv, bJ, i0, A, lda, m, jpvt));
     }
-    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J, s_blk, 1, f.sb.ls));
+    const bool upd = pivoting && !resample && i0 + bJ < k;
+    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J, s_blk, 1, f.sb.ls,
+                       upd ? f.sb.w11 : nullptr));
     RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
-    if (pivoting && !resample && i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb));
+    if (upd) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb, panel_work(f.bb, f.c, J).gate));
     i0 += bJ;
   }
   if (info) {
@@ -342,7 +348,9 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
       RQ_TRY(launch_gemm(s, false, false, mJ, bJ, i0, -1.0, t.yall + i0, m, t.wt + i0 * k, k, 1.0, panel, lda,
                          nullptr, 0));
     }
-    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, Y2, m, t.bb, t.c, J, s_blk, 1, t.sb.ls));
+    const bool upd = i0 + bJ < k;
+    RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, Y2, m, t.bb, t.c, J, s_blk, 1, t.sb.ls,
+                       upd ? t.sb.w11 : nullptr));
     if (Nt > 0) {
       double* Atr = A + i0 + (i0 + bJ) * lda;
       double* wt_tr = t.wt + (i0 + bJ) * k;
@@ -370,7 +378,7 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
       RQ_TRY(launch_gemm(s, false, false, bJ, Nt, i0 + bJ, -1.0, t.yall + i0, m, wt_tr, k, 1.0, Atr, lda, nullptr,
                          0));
     }
-    if (i0 + bJ < k) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, t.sb));
+    if (upd) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, t.sb, panel_work(t.bb, t.c, J).gate));
     i0 += bJ;
   }
   return 0;

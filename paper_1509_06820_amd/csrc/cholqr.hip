@@ -392,7 +392,8 @@ __global__ void __launch_bounds__(SM_T) chol1_kernel(int b, const double* G1, do
 // than from P keeps the preconditioner's conditioning out of both.
 __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const double* G2, const double* H,
                                                      const double* Q1, int64_t ldq, double* P, int64_t ldp, double* Y,
-                                                     int64_t ldy, double* tau, double* T, double* M3, int* st) {
+                                                     int64_t ldy, double* tau, double* T, double* M3, int* st,
+                                                     const double* M1, double* W11) {
   extern __shared__ __align__(16) double sm[];
   __shared__ int flag;
   __shared__ int s_skip;
@@ -553,28 +554,54 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
     if (i < b && j < b) T[i + (int64_t)j * b] = v;
   });
   __syncthreads();
-  if (mJ == b) return;  // no rows below the top block
-  // M3 = -R2^-1 S inv(U): A = inv(U) (D scratch), B = -R2^-1 S
-  if (!sm_tri_inv(C, A, D, &flag)) {  // pivots are >= 1 here: cannot happen
-    if (threadIdx.x == 0) atomicOr(st, ST_PIVOT);
-    return;
-  }
+  // B = -R2^-1 S, for M3 and W11
 #pragma unroll
   for (int q = 0; q < SM_N / 4; ++q) B[r + (cg + 4 * q) * SM_LD] = m3r[q];
   __syncthreads();
-  sm_mm<false>(B, A, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
-    if (i < b && j < b) M3[i + (int64_t)j * b] = v;
-  });
+  if (mJ > b) {  // rows below the top block
+    // M3 = -R2^-1 S inv(U): A = inv(U) (D scratch)
+    if (!sm_tri_inv(C, A, D, &flag)) {  // pivots are >= 1 here: cannot happen
+      if (threadIdx.x == 0) atomicOr(st, ST_PIVOT);
+      return;
+    }
+    sm_mm<false>(B, A, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
+      if (i < b && j < b) M3[i + (int64_t)j * b] = v;
+    });
+    __syncthreads();
+  }
+  if (W11) {
+    // W11 = S11 R11^-1 of the sample update (eq. update1): with the panel
+    // preconditioned by X = P S11^-1, X = Q R2 R1 (the two Cholesky factors,
+    // R1^-1 = M1) and R11 = S R2 R1 S11, so W11 = M1 R2^-1 S -- upper
+    // triangular, formed from factors at hand.
+#pragma unroll
+    for (int q = 0; q < SM_N / 4; ++q) {
+      const int c = cg + 4 * q;
+      D[r + c * SM_LD] = (r <= c && r < b && c < b) ? M1[r + (int64_t)c * b] : 0.0;
+    }
+    __syncthreads();
+    sm_mm<false>(D, B, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
+      if (i < b && j < b) W11[i + (int64_t)j * b] = (i <= j) ? -v : 0.0;
+    });
+  }
 }
 
 // W11 = S11 R11^-1 of the sample update (eq. update1), b x b upper
 // triangular.  A zero pivot R11(j, j) gives a zero column j of W11 and takes
 // row j of R11 out of the later columns; that is W11 = S~ R~^-1 with column j
 // of S~ zeroed and row and column j of R~ replaced by the unit vector.
+// With st, it runs only when the panel's CholeskyQR failed (otherwise the
+// reconstruction has written W11 from its own factors).
 __global__ void __launch_bounds__(SM_T) w11_kernel(int b, const double* S, int64_t srs, int64_t scs, const double* R,
-                                                   int64_t ldr, double* W) {
+                                                   int64_t ldr, double* W, const int* st) {
   extern __shared__ __align__(16) double sm[];
   __shared__ int flag;
+  if (st) {
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) s_ok = (*st == 0);
+    __syncthreads();
+    if (s_ok) return;
+  }
   double* Rt = sm;
   double* Ri = sm + SM_N * SM_LD;
   double* Wk = sm + 2 * SM_N * SM_LD;
@@ -621,13 +648,13 @@ int set_lds(const void* fn) {
 }  // namespace
 
 int launch_w11(hipStream_t s, int bJ, const double* S, int64_t srs, int64_t scs, const double* R, int64_t ldr,
-               double* W) {
+               double* W, const int* st) {
   static bool init = false;
   if (!init) {
     RQ_TRY_RAW(set_lds((const void*)w11_kernel));
     init = true;
   }
-  hipLaunchKernelGGL(w11_kernel, dim3(1), dim3(SM_T), SM_LDS, s, bJ, S, srs, scs, R, ldr, W);
+  hipLaunchKernelGGL(w11_kernel, dim3(1), dim3(SM_T), SM_LDS, s, bJ, S, srs, scs, R, ldr, W, st);
   RQ_HIP(hipGetLastError());
   return 0;
 }
@@ -644,7 +671,7 @@ size_t cholqr_scratch_elems(int64_t mmax, int bmax) {
 // as the first pass's X = P S11^-1.
 int launch_panel_cholqr(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, const double* S11, int64_t srs,
                         int64_t scs, double* tau, double* Y, int64_t ldy, double* T, double* scratch,
-                        double* splitk, size_t splitk_elems, int* st) {
+                        double* splitk, size_t splitk_elems, int* st, double* W11) {
   static bool init = false;
   if (!init) {
     RQ_TRY_RAW(set_lds((const void*)inv_kernel));
@@ -676,7 +703,7 @@ int launch_panel_cholqr(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int b
   RQ_TRY_RAW(launch_gemm(s, true, false, b, b, mJ, 1.0, Q1, mJ, Q1, mJ, 0.0, G2, b, splitk, splitk_elems));
   RQ_TRY_RAW(launch_gemm(s, true, false, b, b, mJ, 1.0, Q1, mJ, P, ldp, 0.0, H, b, splitk, splitk_elems));
   hipLaunchKernelGGL(recon_kernel, dim3(1), dim3(SM_T), SM_LDS, s, b, mJ, G2, H, Q1, mJ, P, ldp, Y, ldy, tau, T, M3,
-                     st);
+                     st, (const double*)M1, S11 ? W11 : nullptr);
   RQ_HIP(hipGetLastError());
   if (mJ > b) {
     RQ_TRY_RAW(launch_gemm(s, false, false, mJ - b, b, b, 1.0, Q1 + b, mJ, M3, b, 0.0, Y + b, ldy, nullptr, 0));

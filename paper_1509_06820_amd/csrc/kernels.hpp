@@ -80,12 +80,12 @@ int launch_larft_gated(hipStream_t s, int64_t mJ, int bJ, const double* Y, int64
 size_t cholqr_scratch_elems(int64_t mmax, int bmax);
 int launch_panel_cholqr(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, const double* S11, int64_t srs,
                         int64_t scs, double* tau, double* Y, int64_t ldy, double* T, double* scratch,
-                        double* splitk, size_t splitk_elems, int* st);
+                        double* splitk, size_t splitk_elems, int* st, double* W11 = nullptr);
 
 // W11 = S11 R11^{-1} (upper triangular, ld bJ); zero-diagonal columns of R11 give 0.
 // S11(i, j) = S[i*srs + j*scs].
 int launch_w11(hipStream_t s, int bJ, const double* S, int64_t srs, int64_t scs, const double* R, int64_t ldr,
-               double* W);
+               double* W, const int* st = nullptr);
 
 // Small utilities.
 int launch_fill(hipStream_t s, void* p, size_t words32);  // zero-fill 32-bit words
