@@ -16,13 +16,14 @@
  *   that share a `work` buffer must be ordered on one stream.
  * - Return value (enqueue status): 0 on success; -i when argument i (1-based)
  *   is invalid, LAPACK xerbla style; -100 when the workspace is too small;
- *   1000 + hipError_t on a HIP runtime error (including a cooperative launch
- *   that does not fit the device).
+ *   1000 + hipError_t on a HIP runtime error (including a kernel whose
+ *   workgroups must all be resident at once and do not fit the device).
  * - `info` (device int32, may be NULL) is written by the kernels: 0 = no
  *   issue; j > 0 = a non-finite sample norm was first met around pivot step j
  *   (the factorization still completes; a NaN norm never wins a pivot
  *   choice); -1 = an internal cross-workgroup wait timed out (results are
- *   invalid).
+ *   invalid; possible when other work on the device keeps a workgroup of the
+ *   sample QRCP from starting for a long time).
  * - Limits of this version: 1 <= b <= 64, 0 <= p, b + p <= 128, n <= 65536,
  *   k <= 1024 for rq_tuxv and rq_tuxv_iter.
  * - Pivot indices are 0-based int64.  jpvt[j] is the original index of column

@@ -821,14 +821,26 @@ int launch_sq(hipStream_t s, SqParams& a) {
   a.K = SQ_T / a.P;
   constexpr size_t lds = sizeof(SqLds<LMAX>);
   static_assert(lds <= 160 * 1024, "LDS budget");
-  static bool attr_set = false;
-  if (!attr_set) {
+  // The P workgroups wait on each other, so all of them must be resident
+  // at once: checked here against the occupancy of one CU times the CU
+  // count.  An ordinary launch, not a cooperative one: a cooperative
+  // dispatch leaves the queue idle for 12-15 us on each side, and on a
+  // stream that runs nothing else beside it every workgroup of a grid this
+  // size starts at once.  Should other work on the device hold a workgroup
+  // back for too long, the bounded waits end the call with info = -1.
+  static int resident = 0;
+  if (!resident) {
     RQ_HIP(hipFuncSetAttribute((const void*)sample_qrcp_kernel<LMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
-    attr_set = true;
+    int occ = 0, dev = 0, cus = 0;
+    RQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sample_qrcp_kernel<LMAX>, SQ_T, lds));
+    RQ_HIP(hipGetDevice(&dev));
+    RQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    resident = occ * cus;
   }
-  void* args[] = {&a};
-  RQ_HIP(hipLaunchCooperativeKernel((const void*)sample_qrcp_kernel<LMAX>, dim3(a.P), dim3(SQ_T), args, lds, s));
+  if (a.P > resident) return RQ_ERR_HIP_BASE + (int)hipErrorCooperativeLaunchTooLarge;
+  hipLaunchKernelGGL(sample_qrcp_kernel<LMAX>, dim3(a.P), dim3(SQ_T), lds, s, a);
+  RQ_HIP(hipGetLastError());
   return 0;
 }
 
