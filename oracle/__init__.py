@@ -9,8 +9,8 @@ kernels, helpers, constants or pre/post-processing.
 Everything is float64 numpy.  Each function follows one passage of the paper
 (section / algorithm / equation named in its docstring) step by step, using a
 library matmul or triangular solve only where the paper's own step is a matrix
-product.  Readings of passages the paper leaves open are listed in each
-docstring and collected in DESIGN.md.
+product.  Readings of passages the paper leaves open are listed in the
+docstring of the function that takes them.
 
 Modules
 -------

@@ -1,7 +1,7 @@
 """RQRCP (Alg. 4), TRQRCP (Alg. 6) and the unpivoted blocked QR the paper
 compares against (Section 7: "qr" is RQRCP with sampling and pivoting removed).
 
-Conventions (readings of points the paper leaves open; all listed in the design doc):
+Conventions (readings of points the paper leaves open):
 
 * Blocks: block J starts at column i0 and has width bJ = min(b, k - i0), so b
   need not divide k (Alg. 4 assumes it does).  Full factorization: k = min(m, n).

@@ -2,7 +2,7 @@
 tuxv) followed by the SVD of the small connection matrix X that the paper
 mentions as an optional refinement.
 
-Readings (listed in DESIGN.md):
+Readings of points the paper leaves open:
 * Alg. 7 produces U from the QR of Z^(1) = A V (its index shift between U^(j+1)
   and eq. tuxv's U^(1) is read this way); its argument tau is unused.
 * j_max counts the multiply-and-factorize steps after the first LQ: j_max = 1

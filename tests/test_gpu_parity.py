@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
 same seeded inputs.
 
-Bars (derived in the design doc):
+Bars:
 * pivots: identical to the oracle's up to the first step whose oracle gap
   between the two best sample norms is below 1e-9 (rounding order may flip
   a near tie), and identical everywhere when no such step exists;
