@@ -24,6 +24,8 @@
  *   choice); -1 = an internal cross-workgroup wait timed out (results are
  *   invalid; possible when other work on the device keeps a workgroup of the
  *   sample QRCP from starting for a long time).
+ * - Empty matrices: for m = 0 or n = 0 the factorizations write only jpvt
+ *   (the identity) and info (0); rq_sketch with m = 0 writes B = 0.
  * - Limits of this version: 1 <= b <= 64, 0 <= p, b + p <= 128, n <= 65536,
  *   k <= 1024 for rq_tuxv and rq_tuxv_iter.
  * - Pivot indices are 0-based int64.  jpvt[j] is the original index of column

@@ -563,6 +563,14 @@ int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, i
   return 0;
 }
 
+// An empty matrix (m = 0 or n = 0): the identity permutation and info = 0;
+// there is nothing else to write.
+int empty_result(hipStream_t s, int64_t n, int64_t* jpvt, int32_t* info) {
+  if (jpvt && n > 0) RQ_TRY(launch_iota(s, n, jpvt));
+  if (info) RQ_TRY(launch_fill(s, info, 1));
+  return 0;
+}
+
 // ------------------------------------------------------------------ argument checks
 int check_common(int64_t m, int64_t n, int64_t lda, int b, int p, int im, int in, int ilda, int ib, int ip) {
   if (m < 0) return -im;
@@ -642,7 +650,7 @@ int rq_rqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t
              int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
   int rc = check_common(m, n, lda, b, p, 2, 3, 5, 6, 7);
   if (rc) return rc;
-  if (m == 0 || n == 0) return 0;
+  if (m == 0 || n == 0) return empty_result((hipStream_t)stream, n, jpvt, info);
   return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes, info,
                      true);
 }
@@ -654,7 +662,7 @@ int rq_rqrcp_omega(void* stream, int64_t m, int64_t n, double* A, int64_t lda, i
   if (rc) return rc;
   if (!Omega) return -8;
   if (ldo < b + p) return -9;
-  if (m == 0 || n == 0) return 0;
+  if (m == 0 || n == 0) return empty_result((hipStream_t)stream, n, jpvt, info);
   return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, 0, Omega, ldo, jpvt, tau, work, work_bytes, info, true);
 }
 
@@ -662,7 +670,7 @@ int rq_rsrqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32
                int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
   int rc = check_common(m, n, lda, b, p, 2, 3, 5, 6, 7);
   if (rc) return rc;
-  if (m == 0 || n == 0) return 0;
+  if (m == 0 || n == 0) return empty_result((hipStream_t)stream, n, jpvt, info);
   return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes, info,
                      true, true);
 }
@@ -671,7 +679,7 @@ int rq_unpivoted_qr(void* stream, int64_t m, int64_t n, double* A, int64_t lda, 
                     size_t work_bytes, int32_t* info) {
   int rc = check_common(m, n, lda, b, 0, 2, 3, 5, 6, 6);
   if (rc) return rc;
-  if (m == 0 || n == 0) return 0;
+  if (m == 0 || n == 0) return empty_result((hipStream_t)stream, 0, nullptr, info);
   return factor_impl((hipStream_t)stream, m, n, A, lda, b, 0, 0, nullptr, 0, nullptr, tau, work, work_bytes, info,
                      false);
 }
@@ -788,8 +796,9 @@ int rq_sketch(void* stream, int64_t m, int64_t n, const double* A, int64_t lda, 
   const size_t sce = gemm_scratch_elems(l, n, m);
   double* sc = cv2.take<double>(sce);
   if (!cv2.ok) sc = nullptr;
-  if (m == 0 || n == 0) return 0;
+  if (n == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
+  if (m == 0) return launch_zero_rows(s, 0, l, n, B, ldb);  // Omega A = 0
   RQ_TRY(launch_omega(s, seed, l, m, om, 1, l));
   RQ_TRY(sketch(s, m, n, A, lda, l, om, l, smp, ls, sc, sc ? sce : 0));
   RQ_TRY(launch_copy2d(s, l, n, smp, ls, B, ldb));

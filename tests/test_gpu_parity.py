@@ -111,6 +111,9 @@ def test_sketch_matches_oracle():
     (16, 20, 16),       # bsteps = l
     (9, 9, 9),          # square, every column pivoted
     (33, 40, 1),        # one step
+    (80, 3000, 64),     # l in (72, 80]
+    (128, 700, 64),     # largest l (b + p = 128)
+    (128, 65536, 64),   # largest l and n: 256 workgroups
 ])
 def test_sample_qrcp_matches_oracle(l, n, bs):
     say(f"sample_qrcp l={l} n={n} b={bs}")
@@ -177,6 +180,7 @@ def test_rqrcp_512_more_seeds(seed):
     (64, 40, 1, 4, 7),         # b = 1
     (1000, 700, 64, 8, 8),     # two panel workgroups, three sample workgroups
     (2100, 1300, 32, 8, 9),    # five panel workgroups, six sample workgroups
+    (600, 500, 64, 64, 10),    # largest oversampling, l = b + p = 128
 ])
 def test_rqrcp_shapes(m, n, b, p, seed):
     say(f"rqrcp {m}x{n} b={b} p={p} seed={seed}")
@@ -357,3 +361,35 @@ def test_trqrcp_tuxv_c3_full_size():
                 gold[key.strip()] = float(val)
     say(f"c3 tuxv error {e:.6f} oracle {gold['oracle_error']:.6f} optimum {opt:.6f}")
     assert opt * (1 - 1e-9) <= e <= 1.05 * gold["oracle_error"]
+
+
+def test_empty_matrices():
+    """m = 0 or n = 0: the factorizations write the identity permutation and
+    info = 0 and nothing else; the sketch of an empty A is zero."""
+    say("empty matrices 0x5 / 5x0 / sketch 0x7")
+    L = binding.load()
+    for m, n in ((0, 5), (5, 0), (0, 0)):
+        A = torch.empty((m, n), dtype=torch.float64, device="cuda")
+        jpvt = torch.full((max(n, 1),), -7, dtype=torch.int64, device="cuda")
+        tau = torch.empty(1, dtype=torch.float64, device="cuda")
+        info = torch.full((1,), 77, dtype=torch.int32, device="cuda")
+        work = binding.workspace(binding.RQ_OP_RQRCP, m, n, 0, 8, 4, torch.device("cuda"))
+        for fn in (L.rq_rqrcp, L.rq_rsrqrcp):
+            jpvt.fill_(-7)
+            info.fill_(77)
+            rc = fn(None, m, n, A.data_ptr(), max(1, m), 8, 4, 1, jpvt.data_ptr(), tau.data_ptr(), work.data_ptr(),
+                    work.numel(), info.data_ptr())
+            assert rc == 0
+            torch.cuda.synchronize()
+            assert host(jpvt)[:n].tolist() == list(range(n))
+            assert int(info.item()) == 0
+        info.fill_(77)
+        rc = L.rq_unpivoted_qr(None, m, n, A.data_ptr(), max(1, m), 8, tau.data_ptr(), work.data_ptr(), work.numel(),
+                               info.data_ptr())
+        assert rc == 0 and int(info.item()) == 0
+    B = torch.full((4, 7), 3.0, dtype=torch.float64, device="cuda").t().contiguous().t()
+    work = binding.workspace(binding.RQ_OP_RQRCP, 0, 7, 0, 4, 0, torch.device("cuda"))
+    A = torch.empty((0, 7), dtype=torch.float64, device="cuda")
+    rc = L.rq_sketch(None, 0, 7, A.data_ptr(), 1, 4, 5, B.data_ptr(), 4, work.data_ptr(), work.numel())
+    assert rc == 0
+    assert np.all(host(B) == 0.0)
