@@ -60,6 +60,19 @@ enum {
 const char* rq_version(void);
 
 /*
+ * Look-ahead switch for rq_rqrcp / rq_rqrcp_omega (host-side, process-wide).
+ * With it on (the default, unless the environment sets RQRCP_LOOKAHEAD=0)
+ * each block's trailing update below the new rows of R runs on a second,
+ * library-owned stream of the current device, beside the sample update and
+ * the next block's sample QRCP (which touch other data); the caller's stream
+ * waits for it before the next block's column swaps, so the call still
+ * completes in the caller's stream order.  Off: every kernel on the caller's
+ * stream.  Results are bitwise the same either way.  Returns the previous
+ * setting (0 or 1).
+ */
+int rq_set_lookahead(int32_t on);
+
+/*
  * Workspace size in bytes for operation `op` at the given sizes (host-only
  * query, no GPU work).  k is ignored for RQ_OP_RQRCP and RQ_OP_QR.
  * Returns 0 on success or -i for an invalid argument i.

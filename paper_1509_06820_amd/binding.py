@@ -27,6 +27,7 @@ _c_i32, _c_i64, _c_u64, _c_sz, _c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_u
 
 _SIGS = {
     "rq_version": ([], ctypes.c_char_p),
+    "rq_set_lookahead": ([_c_i32], ctypes.c_int),
     "rq_workspace_bytes": ([_c_i32, _c_i64, _c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_sz)], ctypes.c_int),
     "rq_rqrcp": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz, _c_p],
                  ctypes.c_int),
@@ -287,6 +288,11 @@ def rq_small_svd(X, work=None, stream=None):
     _check(load().rq_small_svd(_stream(stream), k, _ptr(Xw), _ld(Xw), _ptr(U), k, _ptr(sig), _ptr(V), k, _ptr(work),
                                work.numel()), "rq_small_svd")
     return U, sig, V
+
+
+def rq_set_lookahead(on):
+    """Turn RQRCP's look-ahead trailing update on or off; returns the previous setting."""
+    return bool(load().rq_set_lookahead(1 if on else 0))
 
 
 def rq_profile_start(stages=None):

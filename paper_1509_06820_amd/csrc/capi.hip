@@ -2,6 +2,10 @@
 // with j_max = 1 plus the SVD of X) and the unpivoted blocked QR comparator.
 // The drivers only enqueue kernels on the caller's stream; pivot indices and
 // all intermediate state stay on the device (no host synchronisation).
+#include <atomic>
+#include <cstdlib>
+#include <mutex>
+
 #include "rqrcp.h"
 #include "kernels.hpp"
 #include "prof.hpp"
@@ -177,6 +181,88 @@ int trailing_update(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t n,
   return 0;
 }
 
+// ------------------------------------------------------------------ look-ahead
+// RQRCP's trailing update splits in two once W^T is known: the first bJ rows
+// (R12, which the sample update needs at once) and the rows below them,
+// which nothing reads until the next block's swaps.  The rows below run on a
+// second, library-owned stream per device, beside the sample update and the
+// next block's sample QRCP on the caller's stream; the caller's stream waits
+// for them right before those swaps.  rq_set_lookahead(0), or
+// RQRCP_LOOKAHEAD=0 in the environment, keeps everything on the caller's
+// stream.
+hipStream_t bulk_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+
+std::atomic<int> g_lookahead{-1};  // -1: not set through the API
+
+bool lookahead_enabled() {
+  const int v = g_lookahead.load(std::memory_order_relaxed);
+  if (v >= 0) return v != 0;
+  static const bool env_on = [] {
+    const char* e = std::getenv("RQRCP_LOOKAHEAD");
+    return !(e && e[0] == '0');
+  }();
+  return env_on;
+}
+
+struct Lookahead {
+  hipStream_t s2 = nullptr;
+  hipEvent_t ready = nullptr;  // W^T and R12 formed (recorded on the caller's stream)
+  hipEvent_t done = nullptr;   // the rows below R12 updated (recorded on s2)
+  bool ok = false;
+  explicit Lookahead(bool want) {
+    if (!want || !lookahead_enabled()) return;
+    s2 = bulk_stream();
+    if (!s2) return;
+    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) return;
+    ok = true;
+  }
+  ~Lookahead() {
+    if (ready) (void)hipEventDestroy(ready);
+    if (done) (void)hipEventDestroy(done);
+  }
+  Lookahead(const Lookahead&) = delete;
+  Lookahead& operator=(const Lookahead&) = delete;
+};
+
+// Trailing update with look-ahead: W^T = T^T (Y^T C) and R12 on s, the rows
+// below R12 on la.s2 after them (the event la.done marks their end).
+int trailing_update_split(hipStream_t s, const Lookahead& la, double* A, int64_t lda, int64_t m, int64_t n,
+                          int64_t i0, int bJ, const double* Y, int64_t ldy, const BlockBufs& bb) {
+  const int64_t mJ = m - i0, Nt = n - i0 - bJ;
+  double* C = A + i0 + (i0 + bJ) * lda;
+  const double dm = (double)mJ, dn = (double)Nt, db = (double)bJ;
+  {
+    ProfScope ps(PC_GEMM_YTA, s, 8.0 * (dm * dn + dm * db + db * dn), 2.0 * db * dn * dm + 2.0 * db * db * dn);
+    RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y, ldy, C, lda, 0.0, bb.zbuf, bJ, bb.splitk,
+                       bb.splitk_elems));
+    RQ_TRY(launch_gemm(s, true, false, bJ, Nt, bJ, 1.0, bb.T, bJ, bb.zbuf, bJ, 0.0, bb.wt, bJ, nullptr, 0));
+  }
+  {
+    ProfScope ps(PC_GEMM_UPDATE, s, 8.0 * (2.0 * db * dn + db * db + db * dn), 2.0 * db * dn * db);
+    RQ_TRY(launch_gemm(s, false, false, bJ, Nt, bJ, -1.0, Y, ldy, bb.wt, bJ, 1.0, C, lda, nullptr, 0));
+  }
+  RQ_HIP(hipEventRecord(la.ready, s));
+  RQ_HIP(hipStreamWaitEvent(la.s2, la.ready, 0));
+  if (mJ > bJ) {
+    const double dr = dm - db;
+    ProfScope ps(PC_GEMM_UPDATE, la.s2, 8.0 * (2.0 * dr * dn + dr * db + db * dn), 2.0 * dr * dn * db);
+    RQ_TRY(launch_gemm(la.s2, false, false, mJ - bJ, Nt, bJ, -1.0, Y + bJ, ldy, bb.wt, bJ, 1.0, C + bJ, lda, nullptr,
+                       0));
+  }
+  RQ_HIP(hipEventRecord(la.done, la.s2));
+  return 0;
+}
+
 // Sample update, eq. (update1): B1 = S12 - (S11 R11^-1) R12, B2 = S22, on the
 // sample columns of this block (S + i0 * ls, ld ls).  W11 = S11 R11^-1 is
 // already in sb.w11 unless the panel's status word `st` reports that
@@ -237,6 +323,8 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
   const int l = b + p;
   RQ_TRY(launch_fill(s, f.c.flags, f.c.flag_words));
   if (pivoting) RQ_TRY(launch_iota(s, n, jpvt));
+  Lookahead la(pivoting && !resample);
+  bool bulk_pending = false;  // la.done guards A's rows below the last R12
   if (pivoting && !resample) {
     const double* Om = Omega;
     int64_t ldom = ldo;
@@ -265,16 +353,26 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
         ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, 4.0 * l * nJ * bJ);
         RQ_TRY(launch_sample_qrcp(s, s_blk, f.sb.ls, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J)));
       }
+      if (bulk_pending) {
+        RQ_HIP(hipStreamWaitEvent(s, la.done, 0));
+        bulk_pending = false;
+      }
       ProfScope ps(PC_SWAP, s, 32.0 * m * bJ, 0.0);
       RQ_TRY(launch_apply_swaps(s, f.sb.piv, bJ, i0, A, lda, m, jpvt));
     }
     const bool upd = pivoting && !resample && i0 + bJ < k;
     RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J, s_blk, 1, f.sb.ls,
                        upd ? f.sb.w11 : nullptr));
-    RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
+    if (upd && la.ok) {
+      RQ_TRY(trailing_update_split(s, la, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
+      bulk_pending = true;
+    } else {
+      RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
+    }
     if (upd) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb, panel_work(f.bb, f.c, J).gate));
     i0 += bJ;
   }
+  if (bulk_pending) RQ_HIP(hipStreamWaitEvent(s, la.done, 0));
   if (info) {
     hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, f.c.err, f.c.info, info);
     RQ_HIP(hipGetLastError());
@@ -590,6 +688,12 @@ using namespace rq;
 extern "C" {
 
 const char* rq_version(void) { return "rqrcp-gfx950 0.1"; }
+
+int rq_set_lookahead(int32_t on) {
+  const int prev = lookahead_enabled() ? 1 : 0;
+  g_lookahead.store(on ? 1 : 0, std::memory_order_relaxed);
+  return prev;
+}
 
 int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, int32_t p, size_t* bytes) {
   if (!bytes) return -7;

@@ -526,6 +526,9 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
   extern __shared__ __align__(16) double smem[];
   SqLds<LMAX>& L = *reinterpret_cast<SqLds<LMAX>*>(smem);
   const int me = blockIdx.x, tid = threadIdx.x, wv_id = tid / WAVE;
+  // the sequential pivot steps are the critical path: ahead of the waves of
+  // a trailing update that may share the CU
+  __builtin_amdgcn_s_setprio(3);
   if (earlier_failure(a.err)) return;
   const int64_t c_s = (int64_t)me * SQ_T + tid;
   int pos_s = (int)c_s;   // logical position of this thread's slab column

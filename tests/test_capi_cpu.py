@@ -131,3 +131,10 @@ def test_rsrqrcp_workspace_matches_rqrcp(lib):
     for m, n, b, p in [(8192, 8192, 64, 8), (300, 200, 32, 8)]:
         assert (binding.rq_workspace_bytes(binding.RQ_OP_RSRQRCP, m, n, 0, b, p)
                 == binding.rq_workspace_bytes(binding.RQ_OP_RQRCP, m, n, 0, b, p))
+
+
+def test_lookahead_switch_is_host_only(lib):
+    prev = lib.rq_set_lookahead(0)
+    assert prev in (0, 1)
+    assert lib.rq_set_lookahead(1) == 0
+    assert lib.rq_set_lookahead(prev) == 1

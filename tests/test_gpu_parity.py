@@ -393,3 +393,19 @@ def test_empty_matrices():
     rc = L.rq_sketch(None, 0, 7, A.data_ptr(), 1, 4, 5, B.data_ptr(), 4, work.data_ptr(), work.numel())
     assert rc == 0
     assert np.all(host(B) == 0.0)
+
+
+def test_rqrcp_lookahead_is_bitwise_sequential():
+    """The look-ahead (bulk of each trailing update on a second stream) gives
+    the factorization of the all-on-one-stream order bit for bit."""
+    say("rqrcp look-ahead on/off 1500x1200 b=64")
+    A = dev(inputs.with_spectrum(17, 1500, 1200, inputs.sigma_decade(1200, 8)))
+    prev = binding.rq_set_lookahead(True)
+    try:
+        on = [host(x) for x in binding.rq_rqrcp(A, 64, 8, 17)]
+        binding.rq_set_lookahead(False)
+        off = [host(x) for x in binding.rq_rqrcp(A, 64, 8, 17)]
+    finally:
+        binding.rq_set_lookahead(prev)
+    for x, y in zip(on, off):
+        assert np.array_equal(x, y)
