@@ -116,7 +116,8 @@ void carve_block(Carve& cv, int64_t m, int64_t n, int b, BlockBufs& bb) {
   bb.T = cv.take<double>((size_t)b * b);
   bb.zbuf = cv.take<double>((size_t)b * std::max<int64_t>(n, 1));
   bb.wt = cv.take<double>((size_t)b * std::max<int64_t>(n, 1));
-  bb.splitk_elems = std::max<size_t>({gemm_scratch_elems(b, n, m), gemm_scratch_elems(b, b, m), (size_t)1});
+  bb.splitk_elems =
+      std::max<size_t>({gemm_scratch_elems(b, n, m), gemm_scratch_elems(b, 2 * b, m), (size_t)1});
   bb.splitk = cv.take<double>(bb.splitk_elems);
 }
 

@@ -700,8 +700,8 @@ int launch_panel_cholqr(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int b
   hipLaunchKernelGGL(chol1_kernel, dim3(1), dim3(SM_T), SM_LDS, s, b, G1, M1, st);
   RQ_HIP(hipGetLastError());
   RQ_TRY_RAW(launch_gemm(s, false, false, mJ, b, b, 1.0, X, ldx, M1, b, 0.0, Q1, mJ, nullptr, 0));
-  RQ_TRY_RAW(launch_gemm(s, true, false, b, b, mJ, 1.0, Q1, mJ, Q1, mJ, 0.0, G2, b, splitk, splitk_elems));
-  RQ_TRY_RAW(launch_gemm(s, true, false, b, b, mJ, 1.0, Q1, mJ, P, ldp, 0.0, H, b, splitk, splitk_elems));
+  // [G2 H] = Q1^T [Q1 P] in one launch (H follows G2 in the scratch, ld b)
+  RQ_TRY_RAW(launch_gemm_pair(s, b, b, mJ, 1.0, Q1, mJ, Q1, mJ, P, ldp, 0.0, G2, b, splitk, splitk_elems));
   hipLaunchKernelGGL(recon_kernel, dim3(1), dim3(SM_T), SM_LDS, s, b, mJ, G2, H, Q1, mJ, P, ldp, Y, ldy, tau, T, M3,
                      st, (const double*)M1, S11 ? W11 : nullptr);
   RQ_HIP(hipGetLastError());

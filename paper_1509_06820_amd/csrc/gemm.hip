@@ -48,13 +48,17 @@ struct Acc4<double> { typedef double4_t type; };
 template <>
 struct Acc4<float> { typedef float4_t type; };
 
+// PAIR: the columns j >= nsplit of op(B) come from a second matrix B2 (column
+// j - nsplit of op(B2), leading dimension ldb2), so that one launch forms
+// op(A) [B B2] from two operands that are not adjacent in memory.
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe = double, typename TBe = double,
-          typename Acc = double>
+          typename Acc = double, bool PAIR = false>
 __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                    const TAe* __restrict__ A, int64_t lda,
                                                    const TBe* __restrict__ B, int64_t ldb, double beta,
                                                    double* __restrict__ C, int64_t ldc, int64_t kchunk,
-                                                   int64_t split_stride) {
+                                                   int64_t split_stride, const TBe* __restrict__ B2, int64_t ldb2,
+                                                   int64_t nsplit) {
   typedef typename Acc4<Acc>::type acc4_t;
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int TM = WTM / 16, TN = WTN / 16;
@@ -133,7 +137,18 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
       if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
       const int64_t gj = j0 + jj, gk = k0 + kk;
       TBe v = (TBe)0;
-      if (gj < N && gk < kend) v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
+      if (gj < N && gk < kend) {
+        if constexpr (PAIR) {
+          if (gj >= nsplit) {
+            const int64_t g2 = gj - nsplit;
+            v = TB ? B2[g2 + gk * ldb2] : B2[gk + g2 * ldb2];
+          } else {
+            v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
+          }
+        } else {
+          v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
+        }
+      }
       rb[e] = v;
     }
   };
@@ -244,19 +259,27 @@ __global__ void __launch_bounds__(256) splitk_reduce_many_kernel(int64_t M, int6
   }
 }
 
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe, typename TBe, typename Acc>
+struct PairB {
+  const void* B2 = nullptr;  // null: no second operand
+  int64_t ldb2 = 0;
+  int64_t nsplit = 0;
+};
+
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe, typename TBe, typename Acc,
+          bool PAIR = false>
 int launch_one(hipStream_t s, dim3 grid, int64_t M, int64_t N, int64_t K, double alpha, const TAe* A, int64_t lda,
                const TBe* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
-               int64_t split_stride) {
+               int64_t split_stride, const PairB& pb = PairB()) {
   constexpr size_t lds = gemm_lds_bytes<BM, BN, BK, Acc>();
   static bool attr = false;
   if (!attr) {
-    RQ_HIP(hipFuncSetAttribute((const void*)gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc>,
+    RQ_HIP(hipFuncSetAttribute((const void*)gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
-  hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc>), grid, dim3(256), lds, s, M, N, K,
-                     alpha, A, lda, B, ldb, beta, C, ldc, kchunk, split_stride);
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR>), grid, dim3(256), lds, s, M, N,
+                     K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, split_stride, (const TBe*)pb.B2, pb.ldb2,
+                     pb.nsplit);
   RQ_HIP(hipGetLastError());
   return 0;
 }
@@ -311,7 +334,7 @@ size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K) {
 template <typename TAe, typename TBe, typename Acc>
 static int gemm_dispatch(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const TAe* A,
                          int64_t lda, const TBe* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
-                         size_t scratch_elems) {
+                         size_t scratch_elems, const PairB& pb = PairB()) {
   if (M <= 0 || N <= 0) return 0;
   if (K <= 0) {
     // C = beta * C
@@ -346,6 +369,14 @@ static int gemm_dispatch(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, 
     shape = BIG;
   }
   auto tiles = [&](double al, double be, double* out, int64_t ldo, int64_t stride) {
+    if constexpr (std::is_same<TAe, double>::value && std::is_same<TBe, double>::value &&
+                  std::is_same<Acc, double>::value) {
+      if (pb.B2) {  // launch_gemm_pair: A transposed, B not, 64 x 64 tiles
+        dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)splits);
+        return launch_one<64, 64, BK, 2, 2, true, false, double, double, double, true>(
+            s, grid, M, N, K, al, A, lda, B, ldb, be, out, ldo, kchunk, stride, pb);
+      }
+    }
     switch (shape) {
       case BIG:
         return launch_tiles<128, 64, BK, 2, 2, TAe, TBe, Acc>(s, ta, tb, M, N, K, al, A, lda, B, ldb, be, out, ldo,
@@ -375,6 +406,22 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
                 size_t scratch_elems) {
   return gemm_dispatch<double, double, double>(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch,
                                                scratch_elems);
+}
+
+int launch_gemm_pair(hipStream_t s, int64_t M, int64_t N1, int64_t K, double alpha, const double* A, int64_t lda,
+                     const double* B1, int64_t ldb1, const double* B2, int64_t ldb2, double beta, double* C,
+                     int64_t ldc, double* scratch, size_t scratch_elems) {
+  if (M > 64 || N1 > 64) {  // outside the one-launch shape: two products
+    RQ_TRY_RAW(launch_gemm(s, true, false, M, N1, K, alpha, A, lda, B1, ldb1, beta, C, ldc, scratch, scratch_elems));
+    return launch_gemm(s, true, false, M, N1, K, alpha, A, lda, B2, ldb2, beta, C + N1 * ldc, ldc, scratch,
+                       scratch_elems);
+  }
+  PairB pb;
+  pb.B2 = B2;
+  pb.ldb2 = ldb2;
+  pb.nsplit = N1;
+  return gemm_dispatch<double, double, double>(s, true, false, M, 2 * N1, K, alpha, A, lda, B1, ldb1, beta, C, ldc,
+                                               scratch, scratch_elems, pb);
 }
 
 int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A,

@@ -15,6 +15,11 @@ int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out
 int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                 int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
                 size_t scratch_elems);
+// C (M x 2 N1, ldc) = alpha A^T [B1 B2] + beta C, with A K x M and B1, B2 K x N1
+// (separate arrays): one launch for M, N1 <= 64.
+int launch_gemm_pair(hipStream_t s, int64_t M, int64_t N1, int64_t K, double alpha, const double* A, int64_t lda,
+                     const double* B1, int64_t ldb1, const double* B2, int64_t ldb2, double beta, double* C,
+                     int64_t ldc, double* scratch, size_t scratch_elems);
 size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K);
 // The same products on the FP32 matrix cores (operands rounded to FP32,
 // FP32 accumulation, FP64 C), with one operand stored in FP32.
