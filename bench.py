@@ -49,8 +49,10 @@ STAGE_KERNEL = {"sample_qrcp": ("sample_qrcp_kernel", "paper_1509_06820_amd/csrc
 
 def qr_flops(m, n):
     k = min(m, n)
-    # Householder QR of an m x n matrix (LAPACK count), = 4n^3/3 for m = n
-    return 2.0 * m * n * k - (m + n) * k * k + 2.0 * k ** 3 / 3.0
+    # Householder QR of an m x n matrix: 2 k^2 (max(m, n) - k / 3) flops
+    # (2 m n^2 - 2 n^3 / 3 for m >= n; 4 n^3 / 3 for m = n), the same count
+    # as flops_first_columns over all columns
+    return 2.0 * k * k * max(m, n) - 2.0 * k ** 3 / 3.0
 
 
 def flops_first_columns(m, n, k):
