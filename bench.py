@@ -147,14 +147,39 @@ def run_c3(args):
         binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax, mixed=mixed)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
-    trq = []
-    for i in range(K):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        binding.rq_trqrcp(A, k, b, p, seed, work=w_trq)
-        e1.record(stream)
-        trq.append((e0, e1))
-    torch.cuda.synchronize()
+
+    def time_trqrcp(fn, work):
+        # TRQRCP overwrites its input: each timed call gets its own copy of A,
+        # made before the timed region
+        L = binding.load()
+        assert A.stride(0) == 1 and A.stride(1) == m  # column-major, ld = m
+        jp = torch.empty(n, dtype=torch.int64, device=A.device)
+        tk = torch.empty(k, dtype=torch.float64, device=A.device)
+        inf = torch.zeros(1, dtype=torch.int32, device=A.device)
+        copies = [A.clone() for _ in range(K)]
+        torch.cuda.synchronize()
+        pairs = []
+        for i in range(K):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rc = getattr(L, fn)(stream.cuda_stream, m, n, k, copies[i].data_ptr(), m, b, p, seed, jp.data_ptr(),
+                                tk.data_ptr(), work.data_ptr(), work.numel(), inf.data_ptr())
+            e1.record(stream)
+            assert rc == 0, (fn, rc)
+            pairs.append((e0, e1))
+        torch.cuda.synchronize()
+        assert int(inf.item()) == 0
+        del copies
+        return float(np.mean([a.elapsed_time(z) for a, z in pairs]))
+
+    trq_ms = time_trqrcp("rq_trqrcp", w_trq)
+    trq_mixed_ms = None
+    if mixed:  # TRQRCP alone in mixed precision (rq_trqrcp_mixed)
+        w_trqm = binding.workspace(binding.RQ_OP_TRQRCP_MIXED, m, n, k, b, p, A.device)
+        for _ in range(W):
+            binding.rq_trqrcp(A, k, b, p, seed, work=w_trqm, mixed=True)
+        trq_mixed_ms = time_trqrcp("rq_trqrcp_mixed", w_trqm)
+        del w_trqm
     res = None
     for i in range(K):
         ev[i][0].record(stream)
@@ -162,7 +187,6 @@ def run_c3(args):
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     lat = np.array([a.elapsed_time(z) for a, z in ev])
-    trq_ms = float(np.mean([a.elapsed_time(z) for a, z in trq]))
     U, s, VT, info = res
     assert int(info.item()) == 0, int(info.item())
     err = (torch.linalg.norm(A - (U * s) @ VT) / torch.linalg.norm(A)).item()
@@ -192,6 +216,7 @@ def run_c3(args):
                    "inputs": "U diag(0.9^(i/10)) V^T, Haar factors"},
         "tuxv_gflops": round(flops / (ms * 1e-3) / 1e9, 2),
         "trqrcp_ms": round(trq_ms, 3),
+        **({"trqrcp_mixed_ms": round(trq_mixed_ms, 3)} if mixed else {}),
         "truncation_error": err,
         "optimal_error": opt,
         "error_over_optimum": round(err / opt, 6),

@@ -50,7 +50,8 @@ enum {
   RQ_OP_SAMPLE_QRCP = 4,  /* rq_sample_qrcp                     */
   RQ_OP_SVD = 5,          /* rq_small_svd                       */
   RQ_OP_RSRQRCP = 6,      /* rq_rsrqrcp                         */
-  RQ_OP_TUXV_MIXED = 7    /* rq_tuxv_mixed                      */
+  RQ_OP_TUXV_MIXED = 7,   /* rq_tuxv_mixed                      */
+  RQ_OP_TRQRCP_MIXED = 8  /* rq_trqrcp_mixed                    */
 };
 
 /* Largest j_max accepted by rq_tuxv_iter. */
@@ -137,6 +138,23 @@ int rq_rsrqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32
  */
 int rq_trqrcp(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
               uint64_t seed, int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info);
+
+/*
+ * TRQRCP in mixed precision (not in the paper): as rq_trqrcp, but the two
+ * products that stream the whole matrix -- the sketch Omega A and each
+ * block's Y2^T A -- run on the FP32 matrix cores (operands rounded to FP32,
+ * FP32 accumulation, FP64 results) from an FP32 copy of A that the call
+ * makes in its workspace and permutes along with A.  The sample QRCP, the
+ * panels, reflectors, T and the column swaps stay FP64, so Q is orthonormal
+ * to FP64 accuracy and A(k:m, k:n) still holds the permuted original
+ * entries exactly; R and the selected columns carry FP32 rounding of the
+ * products (about sqrt(m) 6e-8 relative), and pivots may differ from the
+ * FP64 path where two sample norms lie within that rounding.
+ * Arguments as rq_trqrcp; workspace: rq_workspace_bytes with
+ * RQ_OP_TRQRCP_MIXED (RQ_OP_TRQRCP plus 4 m n bytes).
+ */
+int rq_trqrcp_mixed(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
+                    uint64_t seed, int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info);
 
 int rq_trqrcp_omega(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
                     const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work, size_t work_bytes,

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librqrcp.so")
 
 (RQ_OP_RQRCP, RQ_OP_TRQRCP, RQ_OP_TUXV, RQ_OP_QR, RQ_OP_SAMPLE_QRCP, RQ_OP_SVD, RQ_OP_RSRQRCP,
- RQ_OP_TUXV_MIXED) = range(8)
+ RQ_OP_TUXV_MIXED, RQ_OP_TRQRCP_MIXED) = range(9)
 RQ_TUXV_MAX_ITER = 64
 
 _c_i32, _c_i64, _c_u64, _c_sz, _c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p
@@ -41,6 +41,8 @@ _SIGS = {
                       _c_p, _c_i64, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_trqrcp": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz,
                    _c_p], ctypes.c_int),
+    "rq_trqrcp_mixed": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p,
+                         _c_sz, _c_p], ctypes.c_int),
     "rq_trqrcp_omega": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_p, _c_p, _c_p,
                          _c_sz, _c_p], ctypes.c_int),
     "rq_tuxv": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_i64, _c_p, _c_p,
@@ -169,8 +171,9 @@ def rq_rsrqrcp(A, b, p, seed=0, work=None, stream=None):
     return F, tau, jpvt, info
 
 
-def rq_trqrcp(A, k, b, p, seed=0, Omega=None, work=None, stream=None):
-    """Alg. 6.  Returns (F, tau, jpvt, info) (layout as in include/rqrcp.h)."""
+def rq_trqrcp(A, k, b, p, seed=0, Omega=None, work=None, stream=None, mixed=False):
+    """Alg. 6.  Returns (F, tau, jpvt, info) (layout as in include/rqrcp.h).
+    mixed: rq_trqrcp_mixed (FP32 sketch and Y2^T A; no Omega argument)."""
     F = fortran(A).clone()
     m, n = F.shape
     dev = F.device
@@ -178,9 +181,15 @@ def rq_trqrcp(A, k, b, p, seed=0, Omega=None, work=None, stream=None):
     tau = torch.empty(k, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     if work is None:
-        work = workspace(RQ_OP_TRQRCP, m, n, k, b, p, dev)
+        work = workspace(RQ_OP_TRQRCP_MIXED if mixed else RQ_OP_TRQRCP, m, n, k, b, p, dev)
     L = load()
-    if Omega is None:
+    if mixed:
+        if Omega is not None:
+            raise ValueError("the mixed-precision TRQRCP draws its own Omega")
+        rc = L.rq_trqrcp_mixed(_stream(stream), m, n, k, _ptr(F), _ld(F), b, p, seed, _ptr(jpvt), _ptr(tau),
+                               _ptr(work), work.numel(), _ptr(info))
+        _check(rc, "rq_trqrcp_mixed")
+    elif Omega is None:
         rc = L.rq_trqrcp(_stream(stream), m, n, k, _ptr(F), _ld(F), b, p, seed, _ptr(jpvt), _ptr(tau), _ptr(work),
                          work.numel(), _ptr(info))
         _check(rc, "rq_trqrcp")

@@ -713,11 +713,13 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
       sz = cv.off;
       break;
     }
-    case RQ_OP_TRQRCP: {
+    case RQ_OP_TRQRCP:
+    case RQ_OP_TRQRCP_MIXED: {
       if (k < 1 || k > std::min(m, n)) return -4;
       TrqWS t;
       Carve cv(nullptr, 0);
       carve_trq(cv, m, n, k, b, p, t);
+      if (op == RQ_OP_TRQRCP_MIXED) t.a32 = cv.take<float>((size_t)m * n);
       sz = cv.off;
       break;
     }
@@ -791,11 +793,17 @@ int rq_unpivoted_qr(void* stream, int64_t m, int64_t n, double* A, int64_t lda, 
 
 static int trqrcp_entry(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int b, int p,
                         uint64_t seed, const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work,
-                        size_t wbytes, int32_t* info) {
+                        size_t wbytes, int32_t* info, bool mixed = false) {
   TrqWS t;
   Carve cv(work, wbytes);
   carve_trq(cv, m, n, k, b, p, t);
+  if (mixed) t.a32 = cv.take<float>((size_t)m * n);
   if (!cv.ok) return -100;
+  if (mixed) {
+    // the FP32 copy of A that the sketch and the per-block Y2^T A read
+    ProfScope ps(PC_SKETCH, s, 12.0 * m * n, 0.0);
+    RQ_TRY(launch_to_f32(s, m, n, A, lda, t.a32, m));
+  }
   int rc = trqrcp_core(s, m, n, k, A, lda, b, p, seed, Omega, ldo, jpvt, tau, t);
   if (rc) return rc;
   if (info) {
@@ -812,6 +820,15 @@ int rq_trqrcp(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t 
   if (k < 1 || k > std::min(m, n)) return -4;
   return trqrcp_entry((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes,
                       info);
+}
+
+int rq_trqrcp_mixed(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
+                    uint64_t seed, int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
+  if (rc) return rc;
+  if (k < 1 || k > std::min(m, n)) return -4;
+  return trqrcp_entry((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes,
+                      info, true);
 }
 
 int rq_trqrcp_omega(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,

@@ -138,3 +138,18 @@ def test_lookahead_switch_is_host_only(lib):
     assert prev in (0, 1)
     assert lib.rq_set_lookahead(1) == 0
     assert lib.rq_set_lookahead(prev) == 1
+
+
+def test_mixed_trqrcp_workspace_and_arguments(lib):
+    """The mixed TRQRCP adds the FP32 copy of A (4 m n bytes) to the TRQRCP
+    workspace; arguments are checked as for rq_trqrcp."""
+    m, n, k, b, p = 20000, 10000, 256, 64, 8
+    extra = (binding.rq_workspace_bytes(binding.RQ_OP_TRQRCP_MIXED, m, n, k, b, p)
+             - binding.rq_workspace_bytes(binding.RQ_OP_TRQRCP, m, n, k, b, p))
+    assert 4 * m * n <= extra <= 4 * m * n + 512
+    null = ctypes.c_void_p(0)
+    assert lib.rq_trqrcp_mixed(null, 10, 10, 0, null, 10, 4, 4, 1, null, null, null, 0, null) == -4
+    assert lib.rq_trqrcp_mixed(null, 10, 10, 11, null, 10, 4, 4, 1, null, null, null, 0, null) == -4
+    assert lib.rq_trqrcp_mixed(null, 10, 10, 3, null, 9, 4, 4, 1, null, null, null, 0, null) == -6
+    assert lib.rq_trqrcp_mixed(null, 10, 10, 3, null, 10, 65, 4, 1, null, null, null, 0, null) == -7
+    assert lib.rq_trqrcp_mixed(null, 40, 40, 8, null, 40, 8, 0, 1, null, null, null, 16, null) == -100

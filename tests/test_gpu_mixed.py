@@ -13,6 +13,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.linalg.lapack as lapack
 import torch
 
 import oracle
@@ -78,3 +79,34 @@ def test_tuxv_mixed_c3_full_size():
     say(f"c3 mixed error {e:.6f} fp64 {e6:.6f} oracle {gold['oracle_error']:.6f} optimum {opt:.6f}")
     assert opt * (1 - 1e-9) <= e <= 1.05 * gold["oracle_error"]
     assert abs(e - e6) <= 1e-3 * e6
+
+
+@pytest.mark.parametrize("m,n,k,b,p,seed", [
+    (600, 500, 100, 32, 8, 1),
+    (300, 400, 37, 16, 6, 2),
+    (1200, 900, 128, 64, 8, 3),
+])
+def test_trqrcp_mixed_against_fp64_oracle(m, n, k, b, p, seed):
+    """rq_trqrcp_mixed: pivots of the FP64 oracle up to its first relative
+    gap below 1e-5 (FP32 products perturb sample norms by ~1e-7 relative);
+    when all k agree, R within 1e-5 ||A|| of the oracle's; the first k
+    columns factor with residual 1e-5 and an FP64-orthonormal Q; the block
+    A(k:, k:) holds the permuted original entries bit for bit."""
+    say(f"trqrcp_mixed {m}x{n} k={k} b={b} p={p}")
+    A = inputs.with_spectrum(seed, m, n, inputs.sigma_decade(min(m, n), 8))
+    ref = oracle.trqrcp(A, k, b, p, seed=seed)
+    F, tau, jpvt, info = [host(x) for x in binding.rq_trqrcp(dev(A), k, b, p, seed, mixed=True)]
+    assert info[0] == 0
+    assert sorted(jpvt.tolist()) == list(range(n))
+    gaps = np.asarray(ref["gaps"][:k])
+    bad = np.nonzero(gaps < 1e-5)[0]
+    t = int(bad[0]) if len(bad) else k
+    assert np.array_equal(jpvt[:t], ref["jpvt"][:t])
+    nrm = np.linalg.norm(A)
+    if t == k:
+        assert np.abs(np.triu(F[:k]) - np.triu(ref["F"][:k])).max() <= 1e-5 * nrm
+    Q, _, _ = lapack.dorgqr(np.asfortranarray(F[:, :k]).copy(), tau)
+    R11 = np.triu(F[:k, :k])
+    assert np.linalg.norm(A[:, jpvt[:k]] - Q @ R11) <= 1e-5 * nrm
+    assert np.linalg.norm(Q.T @ Q - np.eye(k)) <= 1e-13
+    assert np.array_equal(F[k:, k:], A[k:, :][:, jpvt[k:]])
