@@ -257,8 +257,19 @@ int trailing_update_split(hipStream_t s, const Lookahead& la, double* A, int64_t
   if (mJ > bJ) {
     const double dr = dm - db;
     ProfScope ps(PC_GEMM_UPDATE, la.s2, 8.0 * (2.0 * dr * dn + dr * db + db * dn), 2.0 * dr * dn * db);
-    RQ_TRY(launch_gemm(la.s2, false, false, mJ - bJ, Nt, bJ, -1.0, Y + bJ, ldy, bb.wt, bJ, 1.0, C + bJ, lda, nullptr,
-                       0));
+    // a persistent grid that leaves the next sample QRCP's workgroups CUs of
+    // their own (plus a margin of 16: at 32 sample-QRCP workgroups, 208 and
+    // 224 update workgroups gave 88.5 ms per C2 factorization, 240 gave
+    // 101 ms, a full grid 90.6 ms)
+    static int cus = 0;
+    if (!cus) {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    }
+    const int64_t wgs = std::max<int64_t>(cus / 4, cus - sample_qrcp_workgroups(Nt) - 16);
+    RQ_TRY(launch_gemm_persistent(la.s2, mJ - bJ, Nt, bJ, -1.0, Y + bJ, ldy, bb.wt, bJ, 1.0, C + bJ, lda, (int)wgs));
   }
   RQ_HIP(hipEventRecord(la.done, la.s2));
   return 0;

@@ -51,14 +51,13 @@ struct Acc4<float> { typedef float4_t type; };
 // PAIR: the columns j >= nsplit of op(B) come from a second matrix B2 (column
 // j - nsplit of op(B2), leading dimension ldb2), so that one launch forms
 // op(A) [B B2] from two operands that are not adjacent in memory.
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe = double, typename TBe = double,
-          typename Acc = double, bool PAIR = false>
-__global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
-                                                   const TAe* __restrict__ A, int64_t lda,
-                                                   const TBe* __restrict__ B, int64_t ldb, double beta,
-                                                   double* __restrict__ C, int64_t ldc, int64_t kchunk,
-                                                   int64_t split_stride, const TBe* __restrict__ B2, int64_t ldb2,
-                                                   int64_t nsplit) {
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe, typename TBe, typename Acc,
+          bool PAIR>
+__device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, double alpha, const TAe* __restrict__ A,
+                                          int64_t lda, const TBe* __restrict__ B, int64_t ldb, double beta,
+                                          double* __restrict__ C, int64_t ldc, int64_t kchunk, int64_t split_stride,
+                                          const TBe* __restrict__ B2, int64_t ldb2, int64_t nsplit, int64_t bx,
+                                          int64_t by, int64_t bz) {
   typedef typename Acc4<Acc>::type acc4_t;
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int TM = WTM / 16, TN = WTN / 16;
@@ -75,11 +74,11 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
-  const int64_t i0 = (int64_t)blockIdx.y * BM;
-  const int64_t j0 = (int64_t)blockIdx.x * BN;
-  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t i0 = by * BM;
+  const int64_t j0 = bx * BN;
+  const int64_t kbeg = bz * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
-  double* Cz = C + (int64_t)blockIdx.z * split_stride;
+  double* Cz = C + bz * split_stride;
 
   // The accumulators start from beta * C (lane holds C(i, j) for
   // i = row0 + lane%16, j = col0 + 4r + lane/16): all C loads are issued
@@ -216,6 +215,32 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
       }
 }
 
+// One output tile per workgroup (grid tiles_x x tiles_y x splits), or, with
+// persist_tiles > 0, a grid of fewer workgroups that walk the tiles
+// (t = blockIdx.x, blockIdx.x + gridDim.x, ...; no split-K): a launch that
+// leaves CUs free for a kernel running beside it on another stream.
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe = double, typename TBe = double,
+          typename Acc = double, bool PAIR = false, bool PERSIST = false>
+__global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                   const TAe* __restrict__ A, int64_t lda,
+                                                   const TBe* __restrict__ B, int64_t ldb, double beta,
+                                                   double* __restrict__ C, int64_t ldc, int64_t kchunk,
+                                                   int64_t split_stride, const TBe* __restrict__ B2, int64_t ldb2,
+                                                   int64_t nsplit, int64_t persist_tiles_x, int64_t persist_tiles) {
+  if constexpr (PERSIST) {
+    for (int64_t t = blockIdx.x; t < persist_tiles; t += gridDim.x) {
+      gemm_tile<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                                                                 split_stride, B2, ldb2, nsplit,
+                                                                 t % persist_tiles_x, t / persist_tiles_x, 0);
+      __syncthreads();  // the next tile's LDS stores after every wave's last reads
+    }
+  } else {
+    gemm_tile<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                                                               split_stride, B2, ldb2, nsplit, blockIdx.x,
+                                                               blockIdx.y, blockIdx.z);
+  }
+}
+
 // C = alpha * sum_z P[z] + beta * C   (P[z] is M x N with leading dimension M)
 __global__ void __launch_bounds__(256) splitk_reduce_kernel(int64_t M, int64_t N, int splits,
                                                             const double* __restrict__ P, double alpha,
@@ -263,23 +288,26 @@ struct PairB {
   const void* B2 = nullptr;  // null: no second operand
   int64_t ldb2 = 0;
   int64_t nsplit = 0;
+  int64_t persist_tiles_x = 0;  // persistent launch: tiles per row of tiles
+  int64_t persist_tiles = 0;    // and their total (0: one tile per workgroup)
 };
 
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe, typename TBe, typename Acc,
-          bool PAIR = false>
+          bool PAIR = false, bool PERSIST = false>
 int launch_one(hipStream_t s, dim3 grid, int64_t M, int64_t N, int64_t K, double alpha, const TAe* A, int64_t lda,
                const TBe* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
                int64_t split_stride, const PairB& pb = PairB()) {
   constexpr size_t lds = gemm_lds_bytes<BM, BN, BK, Acc>();
   static bool attr = false;
   if (!attr) {
-    RQ_HIP(hipFuncSetAttribute((const void*)gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR>,
+    RQ_HIP(hipFuncSetAttribute((const void*)gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR, PERSIST>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
-  hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR>), grid, dim3(256), lds, s, M, N,
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR, PERSIST>), grid, dim3(256), lds, s,
+                     M, N,
                      K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, split_stride, (const TBe*)pb.B2, pb.ldb2,
-                     pb.nsplit);
+                     pb.nsplit, pb.persist_tiles_x, pb.persist_tiles);
   RQ_HIP(hipGetLastError());
   return 0;
 }
@@ -406,6 +434,20 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
                 size_t scratch_elems) {
   return gemm_dispatch<double, double, double>(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch,
                                                scratch_elems);
+}
+
+int launch_gemm_persistent(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int wgs) {
+  if (M <= 0 || N <= 0) return 0;
+  if (K <= 0 || wgs <= 0)
+    return launch_gemm(s, false, false, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, 0);
+  const int64_t tx = (N + 63) / 64, ty = (M + 127) / 128;
+  PairB pb;
+  pb.persist_tiles_x = tx;
+  pb.persist_tiles = tx * ty;
+  const unsigned g = (unsigned)std::min<int64_t>(tx * ty, wgs);
+  return launch_one<128, 64, 16, 2, 2, false, false, double, double, double, false, true>(
+      s, dim3(g), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, K, 0, pb);
 }
 
 int launch_gemm_pair(hipStream_t s, int64_t M, int64_t N1, int64_t K, double alpha, const double* A, int64_t lda,

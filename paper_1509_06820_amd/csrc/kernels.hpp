@@ -17,6 +17,11 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
                 size_t scratch_elems);
 // C (M x 2 N1, ldc) = alpha A^T [B1 B2] + beta C, with A K x M and B1, B2 K x N1
 // (separate arrays): one launch for M, N1 <= 64.
+// C = alpha A B + beta C (no transposes) with 128 x 64 tiles on a grid of at
+// most `wgs` workgroups that walk the tiles, so that the launch leaves CUs
+// free for a kernel beside it.
+int launch_gemm_persistent(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int wgs);
 int launch_gemm_pair(hipStream_t s, int64_t M, int64_t N1, int64_t K, double alpha, const double* A, int64_t lda,
                      const double* B1, int64_t ldb1, const double* B2, int64_t ldb2, double beta, double* C,
                      int64_t ldc, double* scratch, size_t scratch_elems);
@@ -52,6 +57,8 @@ size_t sample_qrcp_idx_elems();
 size_t sample_qrcp_theta_elems();
 // S is the sample, column-major with ld lds == sample_rows_padded(l) (rows
 // past l zero).
+// Workgroups of the sample QRCP on a sample of nJ columns (all resident at once).
+int sample_qrcp_workgroups(int64_t nJ);
 int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ, int bJ, int* piv, int* info,
                        int info_base, const SampleQrcpWork& w);
 

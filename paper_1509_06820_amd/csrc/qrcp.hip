@@ -1031,6 +1031,8 @@ size_t sample_qrcp_cand_elems() { return 2 * (size_t)SQ_LCAP * SQ_T; }
 size_t sample_qrcp_idx_elems() { return 2 * 2 * (size_t)SQ_T; }
 size_t sample_qrcp_theta_elems() { return 2 * (size_t)SQ_MAXP; }
 
+int sample_qrcp_workgroups(int64_t nJ) { return (int)((nJ + SQ_T - 1) / SQ_T); }
+
 int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ, int bJ, int* piv, int* info,
                        int info_base, const SampleQrcpWork& w) {
   if (bJ <= 0 || nJ <= 0) return 0;
