@@ -1,7 +1,9 @@
 // C ABI and host-side drivers: RQRCP (Alg. 4), TRQRCP (Alg. 6), TUXV (Alg. 7
 // with j_max = 1 plus the SVD of X) and the unpivoted blocked QR comparator.
-// The drivers only enqueue kernels on the caller's stream; pivot indices and
-// all intermediate state stay on the device (no host synchronisation).
+// The drivers only enqueue kernels (on the caller's stream, and for RQRCP's
+// look-ahead on a second library-owned stream joined back by events); pivot
+// indices and all intermediate state stay on the device (no host
+// synchronisation).
 #include <atomic>
 #include <cstdlib>
 #include <mutex>
