@@ -261,7 +261,7 @@ int trailing_update_split(hipStream_t s, const Lookahead& la, double* A, int64_t
     ProfScope ps(PC_GEMM_UPDATE, la.s2, 8.0 * (2.0 * dr * dn + dr * db + db * dn), 2.0 * dr * dn * db);
     // a persistent grid that leaves the next sample QRCP's workgroups CUs of
     // their own (plus a margin of 16: at 32 sample-QRCP workgroups, 208 and
-    // 224 update workgroups gave 88.5 ms per C2 factorization, 240 gave
+    // 224 update workgroups gave 88.5 ms per 8192 x 8192 factorization, 240 gave
     // 101 ms, a full grid 90.6 ms)
     static int cus = 0;
     if (!cus) {
