@@ -396,10 +396,12 @@ def test_empty_matrices():
 
 
 def test_rqrcp_lookahead_is_bitwise_sequential():
-    """The look-ahead (bulk of each trailing update on a second stream) gives
-    the factorization of the all-on-one-stream order bit for bit."""
-    say("rqrcp look-ahead on/off 1500x1200 b=64")
-    A = dev(inputs.with_spectrum(17, 1500, 1200, inputs.sigma_decade(1200, 8)))
+    """The look-ahead (bulk of each trailing update on a second stream, as a
+    persistent grid that here walks several tiles per workgroup: about 900
+    tiles of 128 x 64 on fewer than 240 workgroups) gives the factorization
+    of the all-on-one-stream order bit for bit."""
+    say("rqrcp look-ahead on/off 3000x2500 b=64")
+    A = dev(inputs.with_spectrum(17, 3000, 2500, inputs.sigma_decade(2500, 8)))
     prev = binding.rq_set_lookahead(True)
     try:
         on = [host(x) for x in binding.rq_rqrcp(A, 64, 8, 17)]
