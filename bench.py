@@ -121,6 +121,46 @@ def copy_calibration(mib):
                       "launches": 3}), flush=True)
 
 
+def run_select_expect(args):
+    """Replay of the selection experiment of Section 3.2 (Fig. selectExpect)
+    through the product's sketch and sample QRCP: A = Q diag(phi^j) with Haar
+    Q (512 x 512); per trial a new Philox seed, B = Omega A, the first sample
+    pivot; the mean of ||a_jmax|| per cell (the GPU test of the same replay
+    compares it with the exact expectation).  value: trials per second over
+    all cells."""
+    import torch
+    from paper_1509_06820_amd import binding, inputs
+    n, trials = 512, 1500 * max(1, args.steps // 5)
+    cells = [(0.5, 8), (0.9, 8), (0.95, 16), (0.99, 4), (0.99, 32)]
+    out, total_s = [], 0.0
+    for phi, l in cells:
+        Q = inputs.haar_columns(np.random.default_rng(int(phi * 1000) + l), n, n)
+        A = torch.from_numpy(np.asfortranarray(Q * phi ** np.arange(n))).cuda()
+        wk = binding.workspace(binding.RQ_OP_RQRCP, n, n, n, l, 0, A.device)
+        ws = binding.workspace(binding.RQ_OP_SAMPLE_QRCP, l, n, 0, 1, 0, A.device)
+        for sd in range(args.warmup):
+            binding.rq_sample_qrcp(binding.rq_sketch(A, l, 10 ** 9 + sd, work=wk), 1, work=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pivs = [binding.rq_sample_qrcp(binding.rq_sketch(A, l, 7_000_000 + 10_000 * l + t, work=wk), 1, work=ws)[1]
+                for t in range(trials)]
+        torch.cuda.synchronize()
+        total_s += time.perf_counter() - t0
+        vals = phi ** torch.stack(pivs).cpu().numpy()[:, 0].astype(np.float64)
+        out.append({"phi": phi, "l": l, "mean": round(float(vals.mean()), 5),
+                    "se": round(float(vals.std(ddof=1) / np.sqrt(trials)), 5)})
+    line = {
+        "metric": METRIC, "value": round(len(cells) * trials / total_s, 1),
+        "unit": "selection trials/s (sketch + first sample pivot, 512x512)", "n_gpus": 1, "steps": trials,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * total_s / (len(cells) * trials), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "select_expect_replay", "n": n, "trials_per_cell": trials,
+                   "inputs": "Haar Q diag(phi^j)"},
+        "cells": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_c3(args):
     """TRQRCP and TUXV (fp64) at rank k = 256 on the 20000 x 10000 matrix with
     sigma_i = 0.9^(i/10): solves/s and p99 latency of TUXV (j_max = --jmax)
@@ -236,7 +276,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2_iid", choices=["c2_iid", "c2_lr", "c1", "c3", "rsrqrcp_c2"])
+    ap.add_argument("--workload", default="c2_iid",
+                    choices=["c2_iid", "c2_lr", "c1", "c3", "rsrqrcp_c2", "select_expect"])
     ap.add_argument("--jmax", type=int, default=1, help="TUXV steps (Alg. 7 j_max) for --workload c3")
     ap.add_argument("--mixed", action="store_true", help="mixed-precision TUXV for --workload c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -261,6 +302,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c3":
         run_c3(args)
+        return
+    if args.workload == "select_expect":
+        run_select_expect(args)
         return
     resample = args.workload == "rsrqrcp_c2"
     A_host, prm = inputs.config_matrix("c2_iid" if resample else args.workload)
