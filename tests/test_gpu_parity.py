@@ -411,3 +411,25 @@ def test_rqrcp_lookahead_is_bitwise_sequential():
         binding.rq_set_lookahead(prev)
     for x, y in zip(on, off):
         assert np.array_equal(x, y)
+
+
+def test_tuxv_rank_one_and_full_rank():
+    """k = 1 against the oracle; k = min(m, n): TUXV spans all of A, so it
+    is A's SVD (singular values of LAPACK, approximation error at rounding)."""
+    say("tuxv k=1 300x200 / k=min 260x200")
+    A = inputs.with_spectrum(41, 300, 200, inputs.sigma_decade(200, 6))
+    ref = oracle.tuxv(A, 1, 8, 4, seed=41)
+    U, s, VT, info = [host(x) for x in binding.rq_tuxv(dev(A), 1, 8, 4, 41)]
+    assert info[0] == 0
+    assert abs(s[0] - ref["s"][0]) <= 1e-12 * ref["s"][0]
+    nrm = np.linalg.norm(A)
+    assert np.linalg.norm(np.outer(U[:, 0], VT[0]) * s[0] - np.outer(ref["U"][:, 0], ref["VT"][0]) * ref["s"][0]) \
+        <= 1e-12 * nrm
+    A = inputs.with_spectrum(42, 260, 200, inputs.sigma_decade(200, 6))
+    U, s, VT, info = [host(x) for x in binding.rq_tuxv(dev(A), 200, 32, 8, 42)]
+    assert info[0] == 0
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert np.abs(s - sv).max() <= 1e-12 * sv[0]
+    assert np.linalg.norm(A - (U * s) @ VT) <= 1e-12 * np.linalg.norm(A)
+    assert np.linalg.norm(U.T @ U - np.eye(200)) <= orth_tol(200)
+    assert np.linalg.norm(VT @ VT.T - np.eye(200)) <= orth_tol(200)
