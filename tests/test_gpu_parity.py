@@ -181,6 +181,8 @@ def test_rqrcp_512_more_seeds(seed):
     (1000, 700, 64, 8, 8),     # two panel workgroups, three sample workgroups
     (2100, 1300, 32, 8, 9),    # five panel workgroups, six sample workgroups
     (600, 500, 64, 64, 10),    # largest oversampling, l = b + p = 128
+    (10, 300, 64, 8, 11),      # fewer rows than b and than l: one block of 10 steps
+    (5000, 3, 64, 8, 12),      # tall and three columns
 ])
 def test_rqrcp_shapes(m, n, b, p, seed):
     say(f"rqrcp {m}x{n} b={b} p={p} seed={seed}")
