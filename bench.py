@@ -17,8 +17,10 @@ Other workloads (one JSON line each, same keys):
     --workload rsrqrcp_c2   RSRQRCP (Alg. 5, a new sample per block) on the same
                             matrix, with RQRCP and QR timed beside it
     --workload c3 [--jmax J]  TRQRCP + TUXV (Alg. 7 with j_max = J) at k = 256
-    --workload c3 --mixed     the same TUXV in mixed precision (FP32 matrix cores
-                            for the products with A, FP64 otherwise)
+    --workload c3 --precision mixed|mixed_bf16
+                            the same TUXV in mixed precision (FP32 matrix cores
+                            for the products with A, the sketch on the FP32 or
+                            BF16 ones, FP64 otherwise)
 """
 
 import argparse
@@ -62,6 +64,28 @@ def flops_first_columns(m, n, k):
     return float(np.sum(4.0 * (m - j) * (n - j - 1) + 3.0 * (m - j)))
 
 
+def host_cpu():
+    """CPU model and physical core count of this host (from /proc/cpuinfo)."""
+    model, cores = None, set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ":" not in ln:
+                    continue
+                key, val = [x.strip() for x in ln.split(":", 1)]
+                if key == "model name" and model is None:
+                    model = val
+                elif key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    core = val
+                    cores.add((phys, core))
+    except OSError:  # pragma: no cover
+        pass
+    return model, (len(cores) or os.cpu_count())
+
+
 def cpu_baseline(A, b, p, seed, nblocks):
     import oracle
     try:
@@ -69,6 +93,7 @@ def cpu_baseline(A, b, p, seed, nblocks):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count()
+    model, phys = host_cpu()
     m, n = A.shape
     k = nblocks * b
     t0 = time.perf_counter()
@@ -77,7 +102,8 @@ def cpu_baseline(A, b, p, seed, nblocks):
     gflops = flops_first_columns(m, n, k) / dt / 1e9
     return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"first {nblocks} blocks (k = {k} pivots, sketch included) of the {m}x{n} RQRCP, "
-                      f"QR-equivalent flops of those columns / wall time {dt:.2f} s"}
+                      f"QR-equivalent flops of those columns / wall time {dt:.2f} s",
+            "cpu_model": model, "physical_cores": phys, "logical_cpus": os.cpu_count()}
 
 
 def measured_traffic(stage, workload):
@@ -161,114 +187,280 @@ def run_select_expect(args):
     print(json.dumps(line), flush=True)
 
 
-def run_c3(args):
-    """TRQRCP and TUXV (fp64) at rank k = 256 on the 20000 x 10000 matrix with
-    sigma_i = 0.9^(i/10): solves/s and p99 latency of TUXV (j_max = --jmax)
-    over the timed solves, TRQRCP time, and the truncation error against the
-    Eckart-Young optimum (evaluated after the timed region)."""
+def c3_measure(A, prm, K, W, prec="fp64", jmax=1, time_trq=True):
+    """TUXV (and TRQRCP) at rank k on the resident C3 matrix A: per-solve HIP
+    event latencies over K timed solves after W warm-up solves, the
+    truncation error (evaluated after the timed region) against the
+    Eckart-Young optimum and the oracle's stored error."""
     import torch
     from paper_1509_06820_amd import binding, inputs
-    A_host, prm = inputs.config_matrix("c3")
     k, b, p, seed = prm["k"], prm["b"], prm["p"], prm["seed"]
-    jmax = args.jmax
-    mixed = args.mixed
-    if mixed and jmax != 1:
-        raise SystemExit("--mixed takes j_max = 1")
-    m, n = A_host.shape
-    A = torch.from_numpy(A_host).cuda()
-    W, K = args.warmup, args.steps
-    print(f"[bench] workload c3 {m}x{n} k={k} b={b} p={p} jmax={jmax} mixed={mixed}: {W} warmup + {K} timed "
-          f"solves", file=sys.stderr, flush=True)
+    m, n = A.shape
     stream = torch.cuda.current_stream()
-    w_trq = binding.workspace(binding.RQ_OP_TRQRCP, m, n, k, b, p, A.device)
-    w_tux = binding.workspace(binding.RQ_OP_TUXV_MIXED if mixed else binding.RQ_OP_TUXV, m, n, k, b, p, A.device)
+    mixed = prec != "fp64"
+    w_tux = binding.workspace(binding.RQ_OP_TUXV, m, n, k, b, p, A.device, prec)
     for _ in range(W):
-        binding.rq_trqrcp(A, k, b, p, seed, work=w_trq)
-        binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax, mixed=mixed)
+        binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax, precision=prec)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
 
-    def time_trqrcp(fn, work):
+    def time_trqrcp(level):
         # TRQRCP overwrites its input: each timed call gets its own copy of A,
         # made before the timed region
+        work = binding.workspace(binding.RQ_OP_TRQRCP, m, n, k, b, p, A.device, level)
+        for _ in range(W):
+            binding.rq_trqrcp(A, k, b, p, seed, work=work, precision=level)
         L = binding.load()
         assert A.stride(0) == 1 and A.stride(1) == m  # column-major, ld = m
         jp = torch.empty(n, dtype=torch.int64, device=A.device)
         tk = torch.empty(k, dtype=torch.float64, device=A.device)
         inf = torch.zeros(1, dtype=torch.int32, device=A.device)
-        copies = [A.clone() for _ in range(K)]
+        ktr = min(K, 5)
+        copies = [A.clone() for _ in range(ktr)]
         torch.cuda.synchronize()
         pairs = []
-        for i in range(K):
+        for i in range(ktr):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            rc = getattr(L, fn)(stream.cuda_stream, m, n, k, copies[i].data_ptr(), m, b, p, seed, jp.data_ptr(),
-                                tk.data_ptr(), work.data_ptr(), work.numel(), inf.data_ptr())
+            rc = L.rq_trqrcp(stream.cuda_stream, m, n, k, copies[i].data_ptr(), m, b, p, seed,
+                             binding.PRECISIONS[level], jp.data_ptr(), tk.data_ptr(), work.data_ptr(), work.numel(),
+                             inf.data_ptr())
             e1.record(stream)
-            assert rc == 0, (fn, rc)
+            assert rc == 0, (level, rc)
             pairs.append((e0, e1))
         torch.cuda.synchronize()
         assert int(inf.item()) == 0
-        del copies
+        del copies, work
         return float(np.mean([a.elapsed_time(z) for a, z in pairs]))
 
-    trq_ms = time_trqrcp("rq_trqrcp", w_trq)
-    trq_mixed_ms = None
-    if mixed:  # TRQRCP alone in mixed precision (rq_trqrcp_mixed)
-        w_trqm = binding.workspace(binding.RQ_OP_TRQRCP_MIXED, m, n, k, b, p, A.device)
-        for _ in range(W):
-            binding.rq_trqrcp(A, k, b, p, seed, work=w_trqm, mixed=True)
-        trq_mixed_ms = time_trqrcp("rq_trqrcp_mixed", w_trqm)
-        del w_trqm
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     res = None
     for i in range(K):
         ev[i][0].record(stream)
-        res = binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax, mixed=mixed)
+        res = binding.rq_tuxv(A, k, b, p, seed, work=w_tux, jmax=jmax, precision=prec)
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     lat = np.array([a.elapsed_time(z) for a, z in ev])
     U, s, VT, info = res
     assert int(info.item()) == 0, int(info.item())
     err = (torch.linalg.norm(A - (U * s) @ VT) / torch.linalg.norm(A)).item()
-    opt = inputs.optimal_truncation_error(inputs.sigma_power(10000, 0.9, 10.0), k)
+    del U, s, VT, res, w_tux
+    opt = inputs.optimal_truncation_error(inputs.sigma_power(n, 0.9, 10.0), k)
     ms = float(lat.mean())
     # TUXV flops: the TRQRCP(k) products (2kmn), one product with A per
     # step (2mnk each), the sketch (2lmn)
     flops = 2.0 * k * m * n + jmax * 2.0 * m * n * k + 2.0 * (b + p) * m * n
-    line = {
-        "metric": METRIC,
-        "value": round(1e3 / ms, 3),
-        "unit": ("TUXV solves/s (mixed fp32/fp64, 20000x10000, k=256)" if mixed else
-                 "TUXV solves/s (fp64, 20000x10000, k=256)" if jmax == 1 else
-                 f"TUXV solves/s (fp64, 20000x10000, k=256, j_max={jmax})"),
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": round(ms, 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32/f64" if mixed else "f64",
-        "data": "synthetic",
-        "config": {"workload": "tuxv_c3_mixed" if mixed else "tuxv_c3" if jmax == 1 else f"tuxv_c3_jmax{jmax}",
-                   "m": m, "n": n, "k": k, "b": b, "p": p, "seed": seed, "jmax": jmax,
-                   "inputs": "U diag(0.9^(i/10)) V^T, Haar factors"},
-        "tuxv_gflops": round(flops / (ms * 1e-3) / 1e9, 2),
-        "trqrcp_ms": round(trq_ms, 3),
-        **({"trqrcp_mixed_ms": round(trq_mixed_ms, 3)} if mixed else {}),
-        "truncation_error": err,
-        "optimal_error": opt,
-        "error_over_optimum": round(err / opt, 6),
-    }
+    out = {"solves_per_s": round(1e3 / ms, 3), "ms": round(ms, 3), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3), "gflops": round(flops / (ms * 1e-3) / 1e9, 2),
+           "precision": prec, "truncation_error": err, "optimal_error": opt, "error_over_optimum": round(err / opt, 6)}
+    if time_trq:
+        out["trqrcp_ms"] = round(time_trqrcp(prec), 3)
     gold = os.path.join(ROOT, "tests", "golden", "c3_tuxv_oracle_error.txt")
     if jmax == 1 and os.path.exists(gold):
         with open(gold) as f:
             for ln in f:
                 if ln.startswith("oracle_error:"):
-                    line["oracle_error"] = float(ln.split(":", 1)[1])
-                    line["error_over_oracle"] = round(err / line["oracle_error"], 6)
+                    out["oracle_error"] = float(ln.split(":", 1)[1])
+                    out["error_over_oracle"] = round(err / out["oracle_error"], 6)
+    return out
+
+
+def run_c3(args):
+    """TRQRCP and TUXV at rank k = 256 on the 20000 x 10000 matrix with
+    sigma_i = 0.9^(i/10): solves/s and p99 latency of TUXV (j_max = --jmax,
+    precision --precision) over the timed solves, TRQRCP time, and the
+    truncation error against the Eckart-Young optimum and the oracle's."""
+    import torch
+    from paper_1509_06820_amd import inputs
+    A_host, prm = inputs.config_matrix("c3")
+    m, n = A_host.shape
+    A = torch.from_numpy(A_host).cuda()
+    del A_host
+    prec, jmax = args.precision, args.jmax
+    if prec != "fp64" and jmax != 1:
+        raise SystemExit("--precision mixed takes j_max = 1")
+    print(f"[bench] workload c3 {m}x{n} k={prm['k']} jmax={jmax} precision={prec}: {args.warmup} warmup + "
+          f"{args.steps} timed solves", file=sys.stderr, flush=True)
+    r = c3_measure(A, prm, args.steps, args.warmup, prec, jmax)
+    line = {
+        "metric": METRIC,
+        "value": r["solves_per_s"],
+        "unit": f"TUXV solves/s ({prec}, 20000x10000, k=256" + (f", j_max={jmax})" if jmax != 1 else ")"),
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms"], "p99_ms": r["p99_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"mixed": "f32/f64", "mixed_bf16": "bf16/f32/f64"}.get(prec, "f64"), "data": "synthetic",
+        "config": {"workload": f"tuxv_c3_{prec}" if prec != "fp64" else "tuxv_c3" if jmax == 1 else
+                   f"tuxv_c3_jmax{jmax}", "m": m, "n": n, "k": prm["k"], "b": prm["b"], "p": prm["p"],
+                   "seed": prm["seed"], "jmax": jmax, "inputs": "U diag(0.9^(i/10)) V^T, Haar factors"},
+        **{kk: v for kk, v in r.items() if kk not in ("solves_per_s", "ms", "p99_ms")},
+    }
     print(json.dumps(line), flush=True)
+
+
+def run_c4(args):
+    """The batched workload: 512 matrices (m log-uniform on [64, 2048], n
+    uniform on [64, m], sigma_j = 10^(-6 j/n), k = 32, p = 8), TRQRCP + TUXV
+    for all of them as one planned batch, captured in a HIP graph and
+    replayed; b and the tile of the grouped products from the autotuner.
+    Timed: graph replays (HIP events), FP32 products ("mixed") and FP64;
+    value = mixed solves/s.  Error: the truncation error of 16 matrices
+    against the FP64 oracle (after the timed region)."""
+    import torch
+    from paper_1509_06820_amd import autotune, binding, inputs
+    t_gen = time.perf_counter()
+    batch = inputs.batch_c4(512)
+    mats = [torch.from_numpy(A).cuda() for A, _ in batch]
+    seeds = [prm["seed"] for _, prm in batch]
+    k, p = 32, 8
+    print(f"[bench] c4: 512 matrices generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    W, K = args.warmup, args.steps
+    res = {}
+    outs = {}
+    for prec in ("mixed", "fp64"):
+        choice = autotune.tune(mats, k, p, seeds, precision=prec, cache_path=args.tune_cache,
+                               log=lambda s_: print(s_, file=sys.stderr, flush=True))
+        bt = binding.BatchTUXV(mats, k, choice["b"], p, seeds, precision=prec, tile=choice["tile"])
+        bt.run()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(g, stream=st):
+                bt.run()
+        torch.cuda.synchronize()
+        for _ in range(W):
+            g.replay()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        cur = torch.cuda.current_stream()
+        for i in range(K):
+            ev[i][0].record(cur)
+            g.replay()
+            ev[i][1].record(cur)
+        torch.cuda.synchronize()
+        lat = np.array([a.elapsed_time(z) for a, z in ev])
+        info = bt.info[:512].cpu().numpy()
+        assert np.all(info == 0), np.nonzero(info)
+        res[prec] = {"ms_per_batch": round(float(lat.mean()), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                     "solves_per_s": round(512 / (lat.mean() * 1e-3), 1), "b": choice["b"], "tile": choice["tile"]}
+        outs[prec] = [(bt.U[i].cpu().numpy(), bt.sigma[i].cpu().numpy(), bt.VT[i].cpu().numpy())
+                      for i in range(0, 512, 32)]
+        del g
+        bt.close()
+        print(f"[bench] c4 {prec}: {res[prec]}", file=sys.stderr, flush=True)
+    # truncation errors of 16 matrices against the FP64 oracle (untimed)
+    import oracle
+    ratios = {"mixed": [], "fp64": []}
+    for j, i in enumerate(range(0, 512, 32)):
+        A = batch[i][0]
+        ref = oracle.tuxv(A, k, res["mixed"]["b"], p, seed=seeds[i])
+        nrm = np.linalg.norm(A)
+        e_ref = np.linalg.norm(A - (ref["U"] * ref["s"]) @ ref["VT"]) / nrm
+        for prec in ("mixed", "fp64"):
+            U, sg, VT = outs[prec][j]
+            ratios[prec].append(float(np.linalg.norm(A - (U * sg) @ VT) / nrm / e_ref))
+    sums = sum(A.shape[0] * A.shape[1] for A in mats)
+    line = {
+        "metric": METRIC, "value": res["mixed"]["solves_per_s"],
+        "unit": "batched TUXV solves/s (512 uneven matrices, k=32, FP32 products)", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": res["mixed"]["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+        "config": {"workload": "tuxv_batched_c4", "matrices": 512, "k": k, "p": p, "sum_mn": sums,
+                   "inputs": "U diag(10^(-6 j/n)) V^T, m log-uniform [64, 2048], n uniform [64, m]"},
+        "mixed": res["mixed"], "fp64": res["fp64"],
+        "mixed_over_fp64": round(res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3),
+        "error_over_oracle_max": {pr: round(max(v), 5) for pr, v in ratios.items()},
+        "hbm_gbs_a_reads": round(3 * 8 * sums / (res["mixed"]["ms_per_batch"] * 1e-3) / 1e9, 1),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_c5(args):
+    """The served request stream: requests with m, n log-uniform on
+    [256, 8192] (m >= n), k in {16, 32, 64, 128, 256}, sigma_i = 0.95^i,
+    half FP64 and half mixed precision, Poisson arrivals; the server admits
+    them by HBM footprint and runs them with continuous batching.  First a
+    saturated FP64 pass (all arrivals at 0) measures the plain throughput;
+    the timed pass offers the mixed stream at 0.7 of it.  value: solves/s of
+    the timed pass; p50/p99 latency (arrival -> completion)."""
+    import torch
+    from paper_1509_06820_amd import binding, inputs, serve
+    n_req = args.requests
+    specs = inputs.serving_c5(n_req, smax=args.serve_max)
+    t_gen = time.perf_counter()
+    mats = [serve.serving_matrix_device(r["i"], r["m"], r["n"]) for r in specs]
+    torch.cuda.synchronize()
+    print(f"[bench] c5: {n_req} request matrices made on the GPU in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+    budget = args.hbm_budget_gb * 1e9
+
+    def reqs(precisions, gaps):
+        out, t = [], 0.0
+        for r, A, prec, gap in zip(specs, mats, precisions, gaps):
+            out.append(serve.Request(r["i"], A, r["k"], prec, seed=50_000 + r["i"], arrival=t))
+            t += gap
+        return out
+
+    # warm-up: every distinct (k, precision) once
+    warm = reqs([binding.RQ_FP64] * n_req, [0.0] * n_req)[:min(n_req, 12)]
+    serve.TuxvServer(budget, streams=args.serve_streams).serve(warm)
+    sat = serve.TuxvServer(budget, streams=args.serve_streams).serve(reqs([binding.RQ_FP64] * n_req, [0.0] * n_req))
+    mu = sat["solves_per_s"]
+    lam = 0.7 * mu
+    precs = [binding.RQ_MIXED if r["mixed"] else binding.RQ_FP64 for r in specs]
+    timed_reqs = reqs(precs, [r["gap"] / lam for r in specs])
+    srv = serve.TuxvServer(budget, streams=args.serve_streams)
+    st = srv.serve(timed_reqs)
+    bad = [r.id for r in timed_reqs if int(r.info.item()) != 0]
+    assert not bad, bad
+    line = {
+        "metric": METRIC, "value": round(st["solves_per_s"], 2),
+        "unit": "served TUXV solves/s (Poisson arrivals at 0.7x saturated FP64 throughput)", "n_gpus": 1,
+        "steps": n_req, "warmup": len(warm), "ms_per_step": round(1e3 / st["solves_per_s"], 3),
+        "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 and f32/f64", "data": "synthetic",
+        "config": {"workload": "tuxv_served_c5", "requests": n_req, "size_range": [256, args.serve_max],
+                   "k_choices": [16, 32, 64, 128, 256], "hbm_budget_gb": args.hbm_budget_gb,
+                   "streams": args.serve_streams, "arrival_rate_per_s": round(lam, 2)},
+        "saturated_fp64": {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in sat.items()},
+        "served": {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in st.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def c1_latency(K, W):
+    """RQRCP of the 512 x 512 configuration (b = 32, 16 blocks): microseconds
+    per factorization and per block (HIP events, mean of K after W warm-ups;
+    each call factors its own copy made before the timed region)."""
+    import torch
+    from paper_1509_06820_amd import binding, inputs
+    A_host, prm = inputs.config_matrix("c1")
+    A = torch.from_numpy(A_host).cuda()
+    b, p, seed = prm["b"], prm["p"], prm["seed"]
+    m, n = A.shape
+    L = binding.load()
+    stream = torch.cuda.current_stream()
+    work = binding.workspace(binding.RQ_OP_RQRCP, m, n, n, b, p, A.device)
+    jp = torch.empty(n, dtype=torch.int64, device=A.device)
+    tau = torch.empty(n, dtype=torch.float64, device=A.device)
+    inf = torch.zeros(1, dtype=torch.int32, device=A.device)
+    copies = [A.clone() for _ in range(W + K)]
+    torch.cuda.synchronize()
+    pairs = []
+    for i in range(W + K):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rc = L.rq_rqrcp(stream.cuda_stream, m, n, copies[i].data_ptr(), m, b, p, seed, binding.RQ_FP64,
+                        jp.data_ptr(), tau.data_ptr(), work.data_ptr(), work.numel(), inf.data_ptr())
+        e1.record(stream)
+        assert rc == 0, rc
+        pairs.append((e0, e1))
+    torch.cuda.synchronize()
+    assert int(inf.item()) == 0
+    t = np.array([a.elapsed_time(z) for a, z in pairs[W:]]) * 1e3
+    blocks = (n + b - 1) // b
+    return {"us_per_factorization": round(float(t.mean()), 1), "us_per_block": round(float(t.mean()) / blocks, 2),
+            "p99_us": round(float(np.percentile(t, 99)), 1), "blocks": blocks, "m": m, "n": n, "b": b, "p": p}
 
 
 def main():
@@ -277,10 +469,18 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2_iid",
-                    choices=["c2_iid", "c2_lr", "c1", "c3", "rsrqrcp_c2", "select_expect"])
+                    choices=["c2_iid", "c2_lr", "c1", "c3", "c4", "c5", "rsrqrcp_c2", "select_expect"])
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (c4; default: the user cache)")
+    ap.add_argument("--requests", type=int, default=200, help="c5: number of requests")
+    ap.add_argument("--serve-max", type=int, default=8192, help="c5: largest matrix dimension")
+    ap.add_argument("--serve-streams", type=int, default=4, help="c5: streams of the server")
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="c5: HBM admission budget")
     ap.add_argument("--jmax", type=int, default=1, help="TUXV steps (Alg. 7 j_max) for --workload c3")
-    ap.add_argument("--mixed", action="store_true", help="mixed-precision TUXV for --workload c3")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_bf16"],
+                    help="arithmetic of the products with A (RQ_FP64, RQ_MIXED, RQ_MIXED_BF16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the 512 x 512 latency and the TUXV (20000 x 10000) part")
     ap.add_argument("--cpu-blocks", type=int, default=3)
     ap.add_argument("--check", action="store_true", help="residual of the last factorization (untimed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -306,6 +506,15 @@ def main():
     if args.workload == "select_expect":
         run_select_expect(args)
         return
+    if args.workload == "c4":
+        if args.tune_cache is None:
+            from paper_1509_06820_amd import autotune
+            args.tune_cache = autotune.DEFAULT_CACHE
+        run_c4(args)
+        return
+    if args.workload == "c5":
+        run_c5(args)
+        return
     resample = args.workload == "rsrqrcp_c2"
     A_host, prm = inputs.config_matrix("c2_iid" if resample else args.workload)
     b, p, seed = prm["b"], prm["p"], prm["seed"]
@@ -319,7 +528,7 @@ def main():
     L = binding.load()
     stream = torch.cuda.current_stream()
     s_ptr = binding._stream(stream)
-    work_rq = binding.workspace(binding.RQ_OP_RQRCP, m, n, k, b, p, A.device)
+    work_rq = binding.workspace(binding.RQ_OP_RQRCP, m, n, k, b, p, A.device, args.precision)
     work_qr = binding.workspace(binding.RQ_OP_QR, m, n, k, b, 0, A.device)
     jpvt = torch.empty(n, dtype=torch.int64, device=A.device)
     tau = torch.empty(k, dtype=torch.float64, device=A.device)
@@ -334,7 +543,8 @@ def main():
     torch.cuda.synchronize()
 
     def rqrcp(F):
-        rc = L.rq_rqrcp(s_ptr, m, n, binding._ptr(F), m, b, p, seed, binding._ptr(jpvt), binding._ptr(tau),
+        rc = L.rq_rqrcp(s_ptr, m, n, binding._ptr(F), m, b, p, seed, binding.PRECISIONS[args.precision],
+                        binding._ptr(jpvt), binding._ptr(tau),
                         binding._ptr(work_rq), work_rq.numel(), binding._ptr(info))
         assert rc == 0, rc
 
@@ -472,6 +682,26 @@ def main():
     if not args.no_cpu_baseline and not resample:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(A_host, b, p, seed, args.cpu_blocks)
+    if args.workload == "c2_iid" and not args.no_extras:
+        # the rest of the metric: TUXV solves/s and p99 at its error (20000 x
+        # 10000, k = 256; FP64 and both mixed levels), and the latency of the
+        # 512 x 512 configuration
+        del copies, copies_qr, copies_rq, work_rq, work_qr, A
+        torch.cuda.empty_cache()
+        print("[bench] 512x512 latency ...", file=sys.stderr, flush=True)
+        line["c1_rqrcp"] = c1_latency(max(K, 10), max(W, 3))
+        print("[bench] tuxv 20000x10000 k=256 ...", file=sys.stderr, flush=True)
+        A3_host, prm3 = inputs.config_matrix("c3")
+        A3 = torch.from_numpy(A3_host).cuda()
+        del A3_host
+        k3 = max(K // 2, 5)
+        line["tuxv_c3"] = c3_measure(A3, prm3, k3, min(W, 2), "fp64")
+        for lvl in ("mixed", "mixed_bf16"):
+            line[f"tuxv_c3_{lvl}"] = c3_measure(A3, prm3, k3, min(W, 2), lvl)
+            line[f"tuxv_c3_{lvl}"]["speedup_over_fp64"] = round(
+                line[f"tuxv_c3_{lvl}"]["solves_per_s"] / line["tuxv_c3"]["solves_per_s"], 3)
+        print(f"[bench] tuxv fp64 {line['tuxv_c3']['ms']:.3f} ms, mixed {line['tuxv_c3_mixed']['ms']:.3f} ms, "
+              f"mixed_bf16 {line['tuxv_c3_mixed_bf16']['ms']:.3f} ms", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

@@ -19,8 +19,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librqrcp.so")
 
-(RQ_OP_RQRCP, RQ_OP_TRQRCP, RQ_OP_TUXV, RQ_OP_QR, RQ_OP_SAMPLE_QRCP, RQ_OP_SVD, RQ_OP_RSRQRCP,
- RQ_OP_TUXV_MIXED, RQ_OP_TRQRCP_MIXED) = range(9)
+(RQ_OP_RQRCP, RQ_OP_TRQRCP, RQ_OP_TUXV, RQ_OP_QR, RQ_OP_SAMPLE_QRCP, RQ_OP_SVD, RQ_OP_RSRQRCP) = range(7)
+RQ_FP64, RQ_MIXED, RQ_MIXED_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": RQ_FP64, "mixed": RQ_MIXED, "mixed_bf16": RQ_MIXED_BF16}
 RQ_TUXV_MAX_ITER = 64
 
 _c_i32, _c_i64, _c_u64, _c_sz, _c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p
@@ -28,32 +29,38 @@ _c_i32, _c_i64, _c_u64, _c_sz, _c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_u
 _SIGS = {
     "rq_version": ([], ctypes.c_char_p),
     "rq_set_lookahead": ([_c_i32], ctypes.c_int),
-    "rq_workspace_bytes": ([_c_i32, _c_i64, _c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_sz)], ctypes.c_int),
-    "rq_rqrcp": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz, _c_p],
+    "rq_set_panel_path": ([_c_i32], ctypes.c_int),
+    "rq_set_block_dump": ([_c_p, _c_i64], ctypes.c_int),
+    "rq_workspace_bytes": ([_c_i32, _c_i64, _c_i64, _c_i64, _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_sz)],
+                           ctypes.c_int),
+    "rq_rqrcp": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_i32, _c_p, _c_p, _c_p, _c_sz, _c_p],
                  ctypes.c_int),
     "rq_rqrcp_omega": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_p, _c_p, _c_p, _c_sz,
                         _c_p], ctypes.c_int),
     "rq_rsrqrcp": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz, _c_p],
                    ctypes.c_int),
-    "rq_tuxv_mixed": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_i64, _c_p, _c_p,
-                       _c_i64, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_tuxv_iter": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_i32, _c_p, _c_i64, _c_p,
                       _c_p, _c_i64, _c_p, _c_sz, _c_p], ctypes.c_int),
-    "rq_trqrcp": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz,
-                   _c_p], ctypes.c_int),
-    "rq_trqrcp_mixed": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p,
-                         _c_sz, _c_p], ctypes.c_int),
+    "rq_trqrcp": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_i32, _c_p, _c_p, _c_p,
+                   _c_sz, _c_p], ctypes.c_int),
     "rq_trqrcp_omega": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_p, _c_p, _c_p,
                          _c_sz, _c_p], ctypes.c_int),
-    "rq_tuxv": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_i64, _c_p, _c_p,
-                 _c_i64, _c_p, _c_sz, _c_p], ctypes.c_int),
+    "rq_tuxv": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_i32, _c_p, _c_i64, _c_p,
+                 _c_p, _c_i64, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_tuxv_omega": ([_c_p, _c_i64, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_p, _c_i64,
                        _c_p, _c_p, _c_i64, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_unpivoted_qr": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_omega": ([_c_p, _c_u64, _c_i64, _c_i64, _c_p, _c_i64], ctypes.c_int),
-    "rq_sketch": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_u64, _c_p, _c_i64, _c_p, _c_sz], ctypes.c_int),
+    "rq_sketch": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_u64, _c_i32, _c_p, _c_i64, _c_p, _c_sz],
+                  ctypes.c_int),
     "rq_sample_qrcp": ([_c_p, _c_i32, _c_i64, _c_i32, _c_p, _c_i64, _c_p, _c_p, _c_sz, _c_p], ctypes.c_int),
     "rq_small_svd": ([_c_p, _c_i32, _c_p, _c_i64, _c_p, _c_i64, _c_p, _c_p, _c_i64, _c_p, _c_sz], ctypes.c_int),
+    "rq_batch_workspace_bytes": ([_c_p, _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_sz)],
+                                 ctypes.c_int),
+    "rq_batch_plan_create": ([_c_p, _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_i32, _c_p, _c_sz,
+                              ctypes.POINTER(_c_p)], ctypes.c_int),
+    "rq_tuxv_batched": ([_c_p, _c_p], ctypes.c_int),
+    "rq_batch_plan_destroy": ([_c_p], ctypes.c_int),
     "rq_profile_start": ([], ctypes.c_int),
     "rq_profile_stop": ([], ctypes.c_int),
     "rq_profile_select": ([ctypes.c_uint32], ctypes.c_int),
@@ -117,20 +124,25 @@ def _ld(X):
     return max(1, X.stride(1)) if n > 1 else max(1, m)
 
 
-def rq_workspace_bytes(op, m, n, k, b, p):
+def _prec(precision):
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def rq_workspace_bytes(op, m, n, k, b, p, precision=RQ_FP64):
     out = _c_sz(0)
-    _check(load().rq_workspace_bytes(op, m, n, k, b, p, ctypes.byref(out)), "rq_workspace_bytes")
+    _check(load().rq_workspace_bytes(op, m, n, k, b, p, _prec(precision), ctypes.byref(out)), "rq_workspace_bytes")
     return out.value
 
 
-def workspace(op, m, n, k, b, p, device):
-    nbytes = rq_workspace_bytes(op, m, n, k, b, p)
+def workspace(op, m, n, k, b, p, device, precision=RQ_FP64):
+    nbytes = rq_workspace_bytes(op, m, n, k, b, p, precision)
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
-def rq_rqrcp(A, b, p, seed=0, Omega=None, work=None, stream=None):
+def rq_rqrcp(A, b, p, seed=0, Omega=None, work=None, stream=None, precision=RQ_FP64):
     """Alg. 4.  Returns (F, tau, jpvt, info): F = R above/on the diagonal and
-    reflectors below (column-major m x n); A is not modified."""
+    reflectors below (column-major m x n); A is not modified.  precision:
+    RQ_FP64, RQ_MIXED or RQ_MIXED_BF16 (or "fp64", "mixed", "mixed_bf16")."""
     F = fortran(A).clone()
     m, n = F.shape
     k = min(m, n)
@@ -138,14 +150,17 @@ def rq_rqrcp(A, b, p, seed=0, Omega=None, work=None, stream=None):
     jpvt = torch.empty(n, dtype=torch.int64, device=dev)
     tau = torch.empty(k, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
+    prec = _prec(precision)
     if work is None:
-        work = workspace(RQ_OP_RQRCP, m, n, k, b, p, dev)
+        work = workspace(RQ_OP_RQRCP, m, n, k, b, p, dev, prec)
     L = load()
     if Omega is None:
-        rc = L.rq_rqrcp(_stream(stream), m, n, _ptr(F), _ld(F), b, p, seed, _ptr(jpvt), _ptr(tau), _ptr(work),
+        rc = L.rq_rqrcp(_stream(stream), m, n, _ptr(F), _ld(F), b, p, seed, prec, _ptr(jpvt), _ptr(tau), _ptr(work),
                         work.numel(), _ptr(info))
         _check(rc, "rq_rqrcp")
     else:
+        if prec != RQ_FP64:
+            raise ValueError("a caller-supplied Omega takes the FP64 path")
         Om = fortran(Omega)
         rc = L.rq_rqrcp_omega(_stream(stream), m, n, _ptr(F), _ld(F), b, p, _ptr(Om), _ld(Om), _ptr(jpvt), _ptr(tau),
                               _ptr(work), work.numel(), _ptr(info))
@@ -171,29 +186,27 @@ def rq_rsrqrcp(A, b, p, seed=0, work=None, stream=None):
     return F, tau, jpvt, info
 
 
-def rq_trqrcp(A, k, b, p, seed=0, Omega=None, work=None, stream=None, mixed=False):
+def rq_trqrcp(A, k, b, p, seed=0, Omega=None, work=None, stream=None, precision=RQ_FP64):
     """Alg. 6.  Returns (F, tau, jpvt, info) (layout as in include/rqrcp.h).
-    mixed: rq_trqrcp_mixed (FP32 sketch and Y2^T A; no Omega argument)."""
+    precision RQ_MIXED / RQ_MIXED_BF16: lower-precision sketch and Y2^T A
+    (seeded Omega only)."""
     F = fortran(A).clone()
     m, n = F.shape
     dev = F.device
     jpvt = torch.empty(n, dtype=torch.int64, device=dev)
     tau = torch.empty(k, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
+    prec = _prec(precision)
     if work is None:
-        work = workspace(RQ_OP_TRQRCP_MIXED if mixed else RQ_OP_TRQRCP, m, n, k, b, p, dev)
+        work = workspace(RQ_OP_TRQRCP, m, n, k, b, p, dev, prec)
     L = load()
-    if mixed:
-        if Omega is not None:
-            raise ValueError("the mixed-precision TRQRCP draws its own Omega")
-        rc = L.rq_trqrcp_mixed(_stream(stream), m, n, k, _ptr(F), _ld(F), b, p, seed, _ptr(jpvt), _ptr(tau),
-                               _ptr(work), work.numel(), _ptr(info))
-        _check(rc, "rq_trqrcp_mixed")
-    elif Omega is None:
-        rc = L.rq_trqrcp(_stream(stream), m, n, k, _ptr(F), _ld(F), b, p, seed, _ptr(jpvt), _ptr(tau), _ptr(work),
-                         work.numel(), _ptr(info))
+    if Omega is None:
+        rc = L.rq_trqrcp(_stream(stream), m, n, k, _ptr(F), _ld(F), b, p, seed, prec, _ptr(jpvt), _ptr(tau),
+                         _ptr(work), work.numel(), _ptr(info))
         _check(rc, "rq_trqrcp")
     else:
+        if prec != RQ_FP64:
+            raise ValueError("a caller-supplied Omega takes the FP64 path")
         Om = fortran(Omega)
         rc = L.rq_trqrcp_omega(_stream(stream), m, n, k, _ptr(F), _ld(F), b, p, _ptr(Om), _ld(Om), _ptr(jpvt),
                                _ptr(tau), _ptr(work), work.numel(), _ptr(info))
@@ -201,10 +214,11 @@ def rq_trqrcp(A, k, b, p, seed=0, Omega=None, work=None, stream=None, mixed=Fals
     return F, tau, jpvt, info
 
 
-def rq_tuxv(A, k, b, p, seed=0, Omega=None, work=None, stream=None, jmax=1, mixed=False):
+def rq_tuxv(A, k, b, p, seed=0, Omega=None, work=None, stream=None, jmax=1, precision=RQ_FP64):
     """Alg. 7 + SVD of X.  Returns (U, sigma, VT, info).  jmax > 1 (seeded
-    Omega only) runs the further LQ/QR steps through rq_tuxv_iter; mixed=True
-    (j_max = 1, seeded Omega) the mixed-precision path rq_tuxv_mixed."""
+    Omega, FP64) runs the further LQ/QR steps through rq_tuxv_iter;
+    precision RQ_MIXED / RQ_MIXED_BF16 (j_max = 1, seeded Omega) the
+    lower-precision products."""
     Af = fortran(A)
     m, n = Af.shape
     dev = Af.device
@@ -212,24 +226,21 @@ def rq_tuxv(A, k, b, p, seed=0, Omega=None, work=None, stream=None, jmax=1, mixe
     VT = torch.empty((n, k), dtype=torch.float64, device=dev).t()  # column-major k x n
     sigma = torch.empty(k, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
+    prec = _prec(precision)
+    if prec != RQ_FP64 and (Omega is not None or jmax != 1):
+        raise ValueError("the mixed-precision path takes j_max = 1 and the seeded compression matrix")
     if work is None:
-        work = workspace(RQ_OP_TUXV_MIXED if mixed else RQ_OP_TUXV, m, n, k, b, p, dev)
+        work = workspace(RQ_OP_TUXV, m, n, k, b, p, dev, prec)
     L = load()
-    if mixed:
-        if Omega is not None or jmax != 1:
-            raise ValueError("the mixed-precision path takes j_max = 1 and the seeded compression matrix")
-        rc = L.rq_tuxv_mixed(_stream(stream), m, n, k, _ptr(Af), _ld(Af), b, p, seed, _ptr(U), m, _ptr(sigma),
-                             _ptr(VT), k, _ptr(work), work.numel(), _ptr(info))
-        _check(rc, "rq_tuxv_mixed")
-    elif jmax != 1:
+    if jmax != 1:
         if Omega is not None:
             raise ValueError("jmax > 1 takes the seeded compression matrix")
         rc = L.rq_tuxv_iter(_stream(stream), m, n, k, _ptr(Af), _ld(Af), b, p, seed, jmax, _ptr(U), m, _ptr(sigma),
                             _ptr(VT), k, _ptr(work), work.numel(), _ptr(info))
         _check(rc, "rq_tuxv_iter")
     elif Omega is None:
-        rc = L.rq_tuxv(_stream(stream), m, n, k, _ptr(Af), _ld(Af), b, p, seed, _ptr(U), m, _ptr(sigma), _ptr(VT), k,
-                       _ptr(work), work.numel(), _ptr(info))
+        rc = L.rq_tuxv(_stream(stream), m, n, k, _ptr(Af), _ld(Af), b, p, seed, prec, _ptr(U), m, _ptr(sigma),
+                       _ptr(VT), k, _ptr(work), work.numel(), _ptr(info))
         _check(rc, "rq_tuxv")
     else:
         Om = fortran(Omega)
@@ -261,14 +272,14 @@ def rq_omega(seed, l, m, device="cuda", stream=None):
     return Om
 
 
-def rq_sketch(A, l, seed, work=None, stream=None):
+def rq_sketch(A, l, seed, work=None, stream=None, precision=RQ_FP64):
     Af = fortran(A)
     m, n = Af.shape
     B = torch.empty((n, l), dtype=torch.float64, device=Af.device).t()
-    if work is None:
-        work = workspace(RQ_OP_RQRCP, m, n, min(m, n), l, 0, Af.device)
-    _check(load().rq_sketch(_stream(stream), m, n, _ptr(Af), _ld(Af), l, seed, _ptr(B), l, _ptr(work), work.numel()),
-           "rq_sketch")
+    if work is None:  # the RQRCP workspace of b + p = l holds Omega and the sample
+        work = workspace(RQ_OP_RQRCP, m, n, min(m, n), min(l, 64), l - min(l, 64), Af.device)
+    _check(load().rq_sketch(_stream(stream), m, n, _ptr(Af), _ld(Af), l, seed, _prec(precision), _ptr(B), l,
+                            _ptr(work), work.numel()), "rq_sketch")
     return B
 
 
@@ -304,6 +315,26 @@ def rq_set_lookahead(on):
     return bool(load().rq_set_lookahead(1 if on else 0))
 
 
+def rq_set_panel_path(mode):
+    """Test hook: 0 = CholeskyQR2 panel with fallback, 1 = column-by-column
+    Householder panel for every block.  Returns the previous mode."""
+    rc = load().rq_set_panel_path(int(mode))
+    if rc < 0:
+        raise RQError(f"rq_set_panel_path returned {rc}")
+    return rc
+
+
+def rq_set_block_dump(buf):
+    """Test hook: dump each block's sample into the float64 CUDA tensor
+    `buf` (None turns the dump off); see include/rqrcp.h for the layout."""
+    if buf is None:
+        _check(load().rq_set_block_dump(ctypes.c_void_p(0), 0), "rq_set_block_dump")
+        return
+    if buf.dtype != torch.float64 or not buf.is_cuda or not buf.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    _check(load().rq_set_block_dump(_ptr(buf), buf.numel()), "rq_set_block_dump")
+
+
 def rq_profile_start(stages=None):
     """Start stage timing; `stages` (names) limits the events to those stages."""
     L = load()
@@ -329,6 +360,76 @@ def rq_profile_stop():
         if cnt.value:
             out[L.rq_profile_name(c).decode()] = dict(count=cnt.value, ms=ms.value, bytes=by.value, flops=fl.value)
     return out
+
+
+class RQBatchMatrix(ctypes.Structure):
+    """rq_batch_matrix of include/rqrcp.h."""
+    _fields_ = [("m", _c_i64), ("n", _c_i64), ("A", _c_p), ("lda", _c_i64), ("U", _c_p), ("ldu", _c_i64),
+                ("sigma", _c_p), ("VT", _c_p), ("ldvt", _c_i64), ("jpvt", _c_p), ("info", _c_p), ("seed", _c_u64)]
+
+
+RQ_TILE_64x64, RQ_TILE_32x32, RQ_TILE_128x64 = 0, 1, 2
+
+
+class BatchTUXV:
+    """A planned batch of rq_tuxv solves (rq_batch_plan_create): the inputs
+    are float64 CUDA matrices (kept referenced; they must not change shape),
+    the outputs U[i] (m_i x k), sigma[i] (k), VT[i] (k x n_i), jpvt[i] (k)
+    and info (count) are allocated here.  run() enqueues the whole batch on
+    the stream (capturable in a CUDA/HIP graph)."""
+
+    def __init__(self, mats, k, b, p, seeds, precision=RQ_FP64, tile=RQ_TILE_64x64, device=None):
+        L = load()
+        self.mats = [fortran(A) for A in mats]
+        count = len(self.mats)
+        dev = self.mats[0].device if count else torch.device("cuda")
+        self.k, self.b, self.p, self.precision, self.tile = k, b, p, _prec(precision), tile
+        self.U = [torch.empty((k, A.shape[0]), dtype=torch.float64, device=dev).t() for A in self.mats]
+        self.sigma = [torch.empty(k, dtype=torch.float64, device=dev) for _ in self.mats]
+        self.VT = [torch.empty((A.shape[1], k), dtype=torch.float64, device=dev).t() for A in self.mats]
+        self.jpvt = [torch.empty(k, dtype=torch.int64, device=dev) for _ in self.mats]
+        self.info = torch.zeros(max(count, 1), dtype=torch.int32, device=dev)
+        items = (RQBatchMatrix * max(count, 1))()
+        for i, A in enumerate(self.mats):
+            m, n = A.shape
+            items[i] = RQBatchMatrix(m, n, A.data_ptr(), _ld(A), self.U[i].data_ptr(), m, self.sigma[i].data_ptr(),
+                                     self.VT[i].data_ptr(), k, self.jpvt[i].data_ptr(),
+                                     self.info.data_ptr() + 4 * i, int(seeds[i]))
+        self._items = items
+        nbytes = _c_sz(0)
+        _check(L.rq_batch_workspace_bytes(ctypes.byref(items), count, k, b, p, self.precision, ctypes.byref(nbytes)),
+               "rq_batch_workspace_bytes")
+        self.work = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+        plan = _c_p(0)
+        torch.cuda.synchronize()
+        _check(L.rq_batch_plan_create(ctypes.byref(items), count, k, b, p, self.precision, tile, _ptr(self.work),
+                                      self.work.numel(), ctypes.byref(plan)), "rq_batch_plan_create")
+        self._plan = plan
+
+    def run(self, stream=None):
+        _check(load().rq_tuxv_batched(_stream(stream), self._plan), "rq_tuxv_batched")
+
+    def close(self):
+        if self._plan is not None and self._plan.value:
+            load().rq_batch_plan_destroy(self._plan)
+        self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover
+            pass
+
+
+def batch_workspace_bytes(shapes, k, b, p, precision=RQ_FP64):
+    """rq_batch_workspace_bytes for matrices of the given (m, n) shapes (host only)."""
+    items = (RQBatchMatrix * max(len(shapes), 1))()
+    for i, (m, n) in enumerate(shapes):
+        items[i] = RQBatchMatrix(m, n, 1, m, 1, m, 1, 1, k, 0, 0, 0)
+    out = _c_sz(0)
+    _check(load().rq_batch_workspace_bytes(ctypes.byref(items), len(shapes), k, b, p, _prec(precision),
+                                           ctypes.byref(out)), "rq_batch_workspace_bytes")
+    return out.value
 
 
 # short aliases

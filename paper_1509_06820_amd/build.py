@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librqrcp.so")
 
-SOURCES = ["philox.hip", "gemm.hip", "qrcp.hip", "panel.hip", "svd.hip", "cholqr.hip", "prof.hip", "capi.hip"]
+SOURCES = ["philox.hip", "gemm.hip", "sketch.hip", "qrcp.hip", "panel.hip", "svd.hip", "cholqr.hip", "prof.hip", "capi.hip", "batched.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -5,8 +5,8 @@
 // indices and all intermediate state stay on the device (no host
 // synchronisation).
 #include <atomic>
-#include <cstdlib>
 #include <mutex>
+#include <type_traits>
 
 #include "rqrcp.h"
 #include "kernels.hpp"
@@ -17,19 +17,32 @@ namespace rq {
 namespace {
 
 constexpr int FLAG_STRIDE = 512;  // 32-bit flag words per block (sample QRCP + panel)
-constexpr int RQ_ERR_WORKSPACE = -100;
 
 __global__ void iota64_kernel(int64_t n, int64_t* v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = i;
 }
 
+// info: the sample QRCP's non-finite-norm step, or -(error word) when a
+// stage failed (1: a cross-workgroup wait timed out, 2: the SVD of X hit its
+// sweep limit, 3: the fallback panel was needed and does not fit the device)
 __global__ void finish_kernel(const int* err, const int* info_ws, int32_t* info) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     int v = *info_ws;
-    if (*err) v = -1;
+    if (*err) v = -*err;
     *info = v;
   }
+}
+
+// *w = v when the gate word is nonzero (or always, without a gate)
+__global__ void set_word_kernel(int* w, int v, const int* gate) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && (!gate || *gate != 0)) *w = v;
+}
+
+int launch_set_word(hipStream_t s, int* w, int v, const int* gate = nullptr) {
+  hipLaunchKernelGGL(set_word_kernel, dim3(1), dim3(64), 0, s, w, v, gate);
+  RQ_HIP(hipGetLastError());
+  return 0;
 }
 
 __global__ void transpose_kernel(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
@@ -145,6 +158,36 @@ SampleQrcpWork sq_work(const SampleBufs& sb, const Common& c, int64_t J) {
 
 int64_t nblocks(int64_t k, int b) { return (k + b - 1) / b; }
 
+// Algorithmic flops of a block's sample QRCP: Householder steps t < bJ on
+// the l x nJ sample, each a norm and a reflector on rows t..l-1 applied to the
+// nJ - t - 1 columns to its right (norm maintenance, which an implementation
+// may do by recomputation or downdating, is not counted).
+double sample_qrcp_flops(int l, int64_t nJ, int bJ) {
+  double f = 0.0;
+  for (int t = 0; t < bJ; ++t) f += 4.0 * (double)(l - t) * (double)(nJ - t - 1) + 3.0 * (double)(l - t);
+  return f;
+}
+
+// Test hooks (process-wide): the panel path and the per-block sample dump.
+std::atomic<int> g_panel_mode{0};
+std::atomic<double*> g_dump{nullptr};
+std::atomic<int64_t> g_dump_cap{0};
+
+// Copies block J's sample (l x nJ, ld ls) into the dump buffer, if one is set
+// and the block fits; `off` accumulates the element offset across blocks.
+int dump_sample(hipStream_t s, const double* smp, int ls, int l, int64_t nJ, int64_t& off) {
+  double* buf = g_dump.load(std::memory_order_relaxed);
+  if (!buf) return 0;
+  const int64_t need = (int64_t)l * nJ;
+  if (off >= 0 && off + need <= g_dump_cap.load(std::memory_order_relaxed)) {
+    RQ_TRY(launch_copy2d(s, l, nJ, smp, ls, buf + off, l));
+    off += need;
+  } else {
+    off = -1;  // this block and the later ones are not stored
+  }
+  return 0;
+}
+
 // ------------------------------------------------------------------ pieces
 // Panel QR of A(i0:m, i0:i0+bJ) + connection matrix T of its reflectors:
 // CholeskyQR2 + Householder reconstruction (preconditioned by the sample's
@@ -159,28 +202,52 @@ int panel_and_t(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t i0, in
   PanelWork pw = panel_work(bb, c, J);
   int* st = (int*)pw.gate;
   ProfScope ps(PC_PANEL, s, 32.0 * dm * db, 6.0 * dm * db * db);
-  RQ_TRY(launch_panel_cholqr(s, A + i0 + i0 * lda, lda, mJ, bJ, S11, srs, scs, tau, Y, ldy, bb.T, bb.cq, bb.splitk,
-                             bb.splitk_elems, st, W11));
-  RQ_TRY(launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, pw));
+  const bool forced = g_panel_mode.load(std::memory_order_relaxed) == 1;
+  if (forced) {
+    RQ_TRY(launch_set_word(s, st, 1));  // the status word that selects the column panel
+  } else {
+    RQ_TRY(launch_panel_cholqr(s, A + i0 + i0 * lda, lda, mJ, bJ, S11, srs, scs, tau, Y, ldy, bb.T, bb.cq, bb.splitk,
+                               bb.splitk_elems, st, W11));
+  }
+  const int rc = launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, pw);
+  if (rc == RQ_PANEL_TOO_TALL) {
+    // the column panel's workgroups cannot all be resident at this height:
+    // forced, that is an enqueue error; as the fallback, a failed CholeskyQR
+    // (status word set) makes the call report info = -3 instead
+    if (forced) return rc;
+    RQ_TRY(launch_set_word(s, c.err, 3, st));
+  } else if (rc) {
+    return rc;
+  }
   RQ_TRY(launch_larft_gated(s, mJ, bJ, Y, ldy, tau, bb.T, st));
   return 0;
 }
 
-// Trailing update Q^T C = C - Y (T^T (Y^T C)) of C = A(i0:m, i0+bJ:n).
+// C = alpha op(A) op(B) + beta C in FP64, or with `mixed` on the FP32 matrix
+// cores (operands rounded to FP32, FP32 accumulation, added to FP64 C).
+int gemm_prec(hipStream_t s, bool mixed, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+              double* scratch, size_t scratch_elems) {
+  if (mixed) return launch_gemm_f32(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch, scratch_elems);
+  return launch_gemm(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch, scratch_elems);
+}
+
+// Trailing update Q^T C = C - Y (T^T (Y^T C)) of C = A(i0:m, i0+bJ:n); with
+// `mixed` the two products with C on the FP32 matrix cores.
 int trailing_update(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t n, int64_t i0, int bJ, const double* Y,
-                    int64_t ldy, const BlockBufs& bb) {
+                    int64_t ldy, const BlockBufs& bb, bool mixed = false) {
   const int64_t mJ = m - i0, Nt = n - i0 - bJ;
   if (Nt <= 0) return 0;
   double* C = A + i0 + (i0 + bJ) * lda;
   const double dm = (double)mJ, dn = (double)Nt, db = (double)bJ;
   {
     ProfScope ps(PC_GEMM_YTA, s, 8.0 * (dm * dn + dm * db + db * dn), 2.0 * db * dn * dm + 2.0 * db * db * dn);
-    RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y, ldy, C, lda, 0.0, bb.zbuf, bJ, bb.splitk,
-                       bb.splitk_elems));
+    RQ_TRY(gemm_prec(s, mixed, true, false, bJ, Nt, mJ, 1.0, Y, ldy, C, lda, 0.0, bb.zbuf, bJ, bb.splitk,
+                     bb.splitk_elems));
     RQ_TRY(launch_gemm(s, true, false, bJ, Nt, bJ, 1.0, bb.T, bJ, bb.zbuf, bJ, 0.0, bb.wt, bJ, nullptr, 0));
   }
   ProfScope ps(PC_GEMM_UPDATE, s, 8.0 * (2.0 * dm * dn + dm * db + db * dn), 2.0 * dm * dn * db);
-  RQ_TRY(launch_gemm(s, false, false, mJ, Nt, bJ, -1.0, Y, ldy, bb.wt, bJ, 1.0, C, lda, nullptr, 0));
+  RQ_TRY(gemm_prec(s, mixed, false, false, mJ, Nt, bJ, -1.0, Y, ldy, bb.wt, bJ, 1.0, C, lda, nullptr, 0));
   return 0;
 }
 
@@ -190,9 +257,8 @@ int trailing_update(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t n,
 // which nothing reads until the next block's swaps.  The rows below run on a
 // second, library-owned stream per device, beside the sample update and the
 // next block's sample QRCP on the caller's stream; the caller's stream waits
-// for them right before those swaps.  rq_set_lookahead(0), or
-// RQRCP_LOOKAHEAD=0 in the environment, keeps everything on the caller's
-// stream.
+// for them right before those swaps.  rq_set_lookahead(0) keeps everything
+// on the caller's stream.
 hipStream_t bulk_stream() {
   static std::mutex mu;
   static hipStream_t streams[64] = {};
@@ -204,17 +270,9 @@ hipStream_t bulk_stream() {
   return streams[dev];
 }
 
-std::atomic<int> g_lookahead{-1};  // -1: not set through the API
+std::atomic<int> g_lookahead{1};
 
-bool lookahead_enabled() {
-  const int v = g_lookahead.load(std::memory_order_relaxed);
-  if (v >= 0) return v != 0;
-  static const bool env_on = [] {
-    const char* e = std::getenv("RQRCP_LOOKAHEAD");
-    return !(e && e[0] == '0');
-  }();
-  return env_on;
-}
+bool lookahead_enabled() { return g_lookahead.load(std::memory_order_relaxed) != 0; }
 
 struct Lookahead {
   hipStream_t s2 = nullptr;
@@ -240,19 +298,19 @@ struct Lookahead {
 // Trailing update with look-ahead: W^T = T^T (Y^T C) and R12 on s, the rows
 // below R12 on la.s2 after them (the event la.done marks their end).
 int trailing_update_split(hipStream_t s, const Lookahead& la, double* A, int64_t lda, int64_t m, int64_t n,
-                          int64_t i0, int bJ, const double* Y, int64_t ldy, const BlockBufs& bb) {
+                          int64_t i0, int bJ, const double* Y, int64_t ldy, const BlockBufs& bb, bool mixed) {
   const int64_t mJ = m - i0, Nt = n - i0 - bJ;
   double* C = A + i0 + (i0 + bJ) * lda;
   const double dm = (double)mJ, dn = (double)Nt, db = (double)bJ;
   {
     ProfScope ps(PC_GEMM_YTA, s, 8.0 * (dm * dn + dm * db + db * dn), 2.0 * db * dn * dm + 2.0 * db * db * dn);
-    RQ_TRY(launch_gemm(s, true, false, bJ, Nt, mJ, 1.0, Y, ldy, C, lda, 0.0, bb.zbuf, bJ, bb.splitk,
-                       bb.splitk_elems));
+    RQ_TRY(gemm_prec(s, mixed, true, false, bJ, Nt, mJ, 1.0, Y, ldy, C, lda, 0.0, bb.zbuf, bJ, bb.splitk,
+                     bb.splitk_elems));
     RQ_TRY(launch_gemm(s, true, false, bJ, Nt, bJ, 1.0, bb.T, bJ, bb.zbuf, bJ, 0.0, bb.wt, bJ, nullptr, 0));
   }
   {
     ProfScope ps(PC_GEMM_UPDATE, s, 8.0 * (2.0 * db * dn + db * db + db * dn), 2.0 * db * dn * db);
-    RQ_TRY(launch_gemm(s, false, false, bJ, Nt, bJ, -1.0, Y, ldy, bb.wt, bJ, 1.0, C, lda, nullptr, 0));
+    RQ_TRY(gemm_prec(s, mixed, false, false, bJ, Nt, bJ, -1.0, Y, ldy, bb.wt, bJ, 1.0, C, lda, nullptr, 0));
   }
   RQ_HIP(hipEventRecord(la.ready, s));
   RQ_HIP(hipStreamWaitEvent(la.s2, la.ready, 0));
@@ -271,7 +329,8 @@ int trailing_update_split(hipStream_t s, const Lookahead& la, double* A, int64_t
         cus = 256;
     }
     const int64_t wgs = std::max<int64_t>(cus / 4, cus - sample_qrcp_workgroups(Nt) - 16);
-    RQ_TRY(launch_gemm_persistent(la.s2, mJ - bJ, Nt, bJ, -1.0, Y + bJ, ldy, bb.wt, bJ, 1.0, C + bJ, lda, (int)wgs));
+    RQ_TRY(launch_gemm_persistent(la.s2, mJ - bJ, Nt, bJ, -1.0, Y + bJ, ldy, bb.wt, bJ, 1.0, C + bJ, lda, (int)wgs,
+                                  mixed));
   }
   RQ_HIP(hipEventRecord(la.done, la.s2));
   return 0;
@@ -297,12 +356,22 @@ int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, 
 }
 
 // Sketch: S (l x n, ld ls) = Omega A with Omega l x m (ld ldo); rows l..ls-1
-// of S are zeroed.  With scratch the product is split along m.
-int sketch(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, int l, const double* Omega,
-           int64_t ldo, double* S, int ls, double* scratch = nullptr, size_t scratch_elems = 0) {
+// of S are zeroed.  With scratch the product is split along m.  `prec`:
+// RQ_FP64, RQ_MIXED (FP32 matrix cores) or RQ_MIXED_BF16 (BF16 matrix cores,
+// Omega and A rounded to BF16, FP32 accumulation).
+template <typename TA>
+int sketch(hipStream_t s, int64_t m, int64_t n, const TA* A, int64_t lda, int l, const double* Omega, int64_t ldo,
+           double* S, int ls, double* scratch, size_t scratch_elems, int prec) {
   const double dm = (double)m, dn = (double)n, dl = (double)l;
-  ProfScope ps(PC_SKETCH, s, 8.0 * (dm * dn + dl * dm + dl * dn), 2.0 * dl * dm * dn);
-  RQ_TRY(launch_gemm(s, false, false, l, n, m, 1.0, Omega, ldo, A, lda, 0.0, S, ls, scratch, scratch_elems));
+  ProfScope ps(PC_SKETCH, s, (double)sizeof(TA) * dm * dn + 8.0 * (dl * dm + dl * dn), 2.0 * dl * dm * dn);
+  if (prec == RQ_MIXED_BF16) {
+    RQ_TRY(launch_sketch_bf16(s, l, n, m, Omega, ldo, A, lda, S, ls, scratch, scratch_elems));
+  } else if (prec == RQ_MIXED || !std::is_same<TA, double>::value) {
+    RQ_TRY(launch_gemm_f32(s, false, false, l, n, m, 1.0, Omega, ldo, A, lda, 0.0, S, ls, scratch, scratch_elems));
+  } else {
+    RQ_TRY(launch_gemm(s, false, false, l, n, m, 1.0, Omega, ldo, (const double*)A, lda, 0.0, S, ls, scratch,
+                       scratch_elems));
+  }
   return launch_zero_rows(s, l, ls, n, S, ls);
 }
 
@@ -328,16 +397,17 @@ void carve_factor(Carve& cv, int64_t m, int64_t n, int b, int p, bool pivoting, 
 // and there is no sample update.
 int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int b, int p, uint64_t seed,
                 const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work, size_t wbytes,
-                int32_t* info, bool pivoting, bool resample = false) {
+                int32_t* info, bool pivoting, bool resample, int prec, int iwork, bool allow_lookahead = true) {
+  const bool mixed = prec != RQ_FP64;
   FactorWS f;
   Carve cv(work, wbytes);
   carve_factor(cv, m, n, b, p, pivoting, f);
-  if (!cv.ok) return RQ_ERR_WORKSPACE;
+  if (!cv.ok) return -iwork;
   const int64_t k = std::min(m, n);
   const int l = b + p;
   RQ_TRY(launch_fill(s, f.c.flags, f.c.flag_words));
   if (pivoting) RQ_TRY(launch_iota(s, n, jpvt));
-  Lookahead la(pivoting && !resample);
+  Lookahead la(pivoting && !resample && allow_lookahead);
   bool bulk_pending = false;  // la.done guards A's rows below the last R12
   if (pivoting && !resample) {
     const double* Om = Omega;
@@ -348,8 +418,10 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
       Om = f.sb.omega;
       ldom = l;
     }
-    RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, f.sb.smp, f.sb.ls, f.bb.splitk, f.bb.splitk_elems));
+    RQ_TRY(sketch(s, m, n, (const double*)A, lda, l, Om, ldom, f.sb.smp, f.sb.ls, f.bb.splitk, f.bb.splitk_elems,
+                  prec));
   }
+  int64_t dump_off = 0;
   for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
     const int bJ = (int)std::min<int64_t>(b, k - i0);
     const int64_t mJ = m - i0, nJ = n - i0;
@@ -360,11 +432,12 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
           ProfScope ps(PC_OMEGA, s, 8.0 * l * mJ, 0.0);
           RQ_TRY(launch_omega(s, seed, l, mJ, f.sb.omega, 1, l, (uint64_t)J));
         }
-        RQ_TRY(sketch(s, mJ, nJ, A + i0 + i0 * lda, lda, l, f.sb.omega, l, s_blk, f.sb.ls, f.bb.splitk,
-                      f.bb.splitk_elems));
+        RQ_TRY(sketch(s, mJ, nJ, (const double*)(A + i0 + i0 * lda), lda, l, f.sb.omega, l, s_blk, f.sb.ls,
+                      f.bb.splitk, f.bb.splitk_elems, RQ_FP64));
       }
+      if (!resample) RQ_TRY(dump_sample(s, s_blk, f.sb.ls, l, nJ, dump_off));
       {
-        ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, 4.0 * l * nJ * bJ);
+        ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, sample_qrcp_flops(l, nJ, bJ));
         RQ_TRY(launch_sample_qrcp(s, s_blk, f.sb.ls, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J)));
       }
       if (bulk_pending) {
@@ -378,10 +451,10 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
     RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J, s_blk, 1, f.sb.ls,
                        upd ? f.sb.w11 : nullptr));
     if (upd && la.ok) {
-      RQ_TRY(trailing_update_split(s, la, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
+      RQ_TRY(trailing_update_split(s, la, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb, mixed));
       bulk_pending = true;
     } else {
-      RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb));
+      RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb, mixed));
     }
     if (upd) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb, panel_work(f.bb, f.c, J).gate));
     i0 += bJ;
@@ -403,6 +476,7 @@ struct TrqWS {
   double* wt;     // k x n
   double* gk;     // b x k
   float* a32 = nullptr;  // mixed precision: FP32 copy of A (ld m), permuted with A
+  int prec = RQ_FP64;    // with a32: RQ_MIXED or RQ_MIXED_BF16 (the sketch's arithmetic)
 };
 
 void carve_trq(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TrqWS& t) {
@@ -428,22 +502,20 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
     Om = t.sb.omega;
     ldom = l;
   }
-  if (t.a32) {
-    // mixed precision: Omega A on the FP32 matrix cores from the FP32 copy
-    const double dm = (double)m, dn = (double)n, dl = (double)l;
-    ProfScope ps(PC_SKETCH, s, 4.0 * dm * dn + 8.0 * (dl * dm + dl * dn), 2.0 * dl * dm * dn);
-    RQ_TRY(launch_gemm_f32(s, false, false, l, n, m, 1.0, Om, ldom, t.a32, m, 0.0, t.sb.smp, t.sb.ls, t.bb.splitk,
-                           t.bb.splitk_elems));
-    RQ_TRY(launch_zero_rows(s, l, t.sb.ls, n, t.sb.smp, t.sb.ls));
-  } else {
-    RQ_TRY(sketch(s, m, n, A, lda, l, Om, ldom, t.sb.smp, t.sb.ls, t.bb.splitk, t.bb.splitk_elems));
-  }
+  if (t.a32)  // mixed precision: from the FP32 copy
+    RQ_TRY(sketch(s, m, n, (const float*)t.a32, m, l, Om, ldom, t.sb.smp, t.sb.ls, t.bb.splitk, t.bb.splitk_elems,
+                  t.prec));
+  else
+    RQ_TRY(sketch(s, m, n, (const double*)A, lda, l, Om, ldom, t.sb.smp, t.sb.ls, t.bb.splitk, t.bb.splitk_elems,
+                  RQ_FP64));
+  int64_t dump_off = 0;
   for (int64_t i0 = 0, J = 0; i0 < k; ++J) {
     const int bJ = (int)std::min<int64_t>(b, k - i0);
     const int64_t mJ = m - i0, nJ = n - i0, Nt = n - i0 - bJ;
     double* s_blk = t.sb.smp + i0 * t.sb.ls;
+    RQ_TRY(dump_sample(s, s_blk, t.sb.ls, l, nJ, dump_off));
     {
-      ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, 4.0 * l * nJ * bJ);
+      ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, sample_qrcp_flops(l, nJ, bJ));
       RQ_TRY(launch_sample_qrcp(s, s_blk, t.sb.ls, l, nJ, bJ, t.sb.piv, t.c.info, (int)i0, sq_work(t.sb, t.c, J)));
     }
     {
@@ -569,7 +641,8 @@ struct TuxvWS {
   double* vperm;   // mixed precision: n x k, rows of V in the column order of A P
 };
 
-void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS& t, bool mixed = false) {
+void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS& t, int prec = RQ_FP64) {
+  const bool mixed = prec != RQ_FP64;
   carve_trq(cv, m, n, k, b, p, t.trq);
   carve_qr(cv, n, k, b, t.qz);
   carve_qr(cv, m, k, b, t.qu);
@@ -593,6 +666,7 @@ void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS
   t.vperm = nullptr;
   if (mixed) {
     t.trq.a32 = cv.take<float>((size_t)m * n);
+    t.trq.prec = prec;
     t.vperm = cv.take<double>((size_t)n * k);
   }
 }
@@ -601,11 +675,12 @@ void carve_tuxv(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int p, TuxvWS
 // SVD of the last connection matrix X: A ~ (U Ux) diag(sigma) (Vx^T V^T).
 int tuxv_impl(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int b, int p,
               uint64_t seed, const double* Omega, int64_t ldo, double* U, int64_t ldu, double* sigma, double* VT,
-              int64_t ldvt, void* work, size_t wbytes, int32_t* info, int jmax = 1, bool mixed = false) {
+              int64_t ldvt, void* work, size_t wbytes, int32_t* info, int jmax, int prec, int iwork) {
+  const bool mixed = prec != RQ_FP64;
   TuxvWS t;
   Carve cv(work, wbytes);
-  carve_tuxv(cv, m, n, k, b, p, t, mixed);
-  if (!cv.ok) return RQ_ERR_WORKSPACE;
+  carve_tuxv(cv, m, n, k, b, p, t, prec);
+  if (!cv.ok) return -iwork;
 
   // TRQRCP on a copy: A itself is needed again for Z1 = A V.
   {
@@ -701,20 +776,34 @@ using namespace rq;
 
 extern "C" {
 
-const char* rq_version(void) { return "rqrcp-gfx950 0.1"; }
+const char* rq_version(void) { return "rqrcp-gfx950 0.2"; }
 
 int rq_set_lookahead(int32_t on) {
-  const int prev = lookahead_enabled() ? 1 : 0;
-  g_lookahead.store(on ? 1 : 0, std::memory_order_relaxed);
-  return prev;
+  return g_lookahead.exchange(on ? 1 : 0, std::memory_order_relaxed) != 0 ? 1 : 0;
 }
 
-int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, int32_t p, size_t* bytes) {
-  if (!bytes) return -7;
+int rq_set_panel_path(int32_t mode) {
+  if (mode != 0 && mode != 1) return -1;
+  return g_panel_mode.exchange(mode, std::memory_order_relaxed);
+}
+
+int rq_set_block_dump(double* buf, int64_t capacity) {
+  if (capacity < 0) return -2;
+  g_dump_cap.store(buf ? capacity : 0, std::memory_order_relaxed);
+  g_dump.store(buf, std::memory_order_relaxed);
+  return 0;
+}
+
+int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, int32_t p, int32_t precision,
+                       size_t* bytes) {
+  if (!bytes) return -8;
   if (m < 0) return -2;
   if (n < 0) return -3;
   if (b < 1 || b > 64) return -5;
   if (p < 0 || b + p > 128) return -6;
+  if (precision < RQ_FP64 || precision > RQ_MIXED_BF16) return -7;
+  if (precision != RQ_FP64 && op != RQ_OP_RQRCP && op != RQ_OP_TRQRCP && op != RQ_OP_TUXV) return -7;
+  const bool mixed = precision != RQ_FP64;
   size_t sz = 0;
   switch (op) {
     case RQ_OP_RQRCP:
@@ -726,22 +815,20 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
       sz = cv.off;
       break;
     }
-    case RQ_OP_TRQRCP:
-    case RQ_OP_TRQRCP_MIXED: {
+    case RQ_OP_TRQRCP: {
       if (k < 1 || k > std::min(m, n)) return -4;
       TrqWS t;
       Carve cv(nullptr, 0);
       carve_trq(cv, m, n, k, b, p, t);
-      if (op == RQ_OP_TRQRCP_MIXED) t.a32 = cv.take<float>((size_t)m * n);
+      if (mixed) t.a32 = cv.take<float>((size_t)m * n);
       sz = cv.off;
       break;
     }
-    case RQ_OP_TUXV:
-    case RQ_OP_TUXV_MIXED: {
+    case RQ_OP_TUXV: {
       if (k < 1 || k > std::min(m, n) || k > 1024) return -4;
       TuxvWS t;
       Carve cv(nullptr, 0);
-      carve_tuxv(cv, m, n, k, b, p, t, op == RQ_OP_TUXV_MIXED);
+      carve_tuxv(cv, m, n, k, b, p, t, precision);
       sz = cv.off;
       break;
     }
@@ -767,12 +854,13 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
 }
 
 int rq_rqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
-             int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
+             int32_t precision, int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
   int rc = check_common(m, n, lda, b, p, 2, 3, 5, 6, 7);
   if (rc) return rc;
+  if (precision < RQ_FP64 || precision > RQ_MIXED_BF16) return -9;
   if (m == 0 || n == 0) return empty_result((hipStream_t)stream, n, jpvt, info);
   return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes, info,
-                     true);
+                     true, false, precision, 13);
 }
 
 int rq_rqrcp_omega(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p,
@@ -783,7 +871,8 @@ int rq_rqrcp_omega(void* stream, int64_t m, int64_t n, double* A, int64_t lda, i
   if (!Omega) return -8;
   if (ldo < b + p) return -9;
   if (m == 0 || n == 0) return empty_result((hipStream_t)stream, n, jpvt, info);
-  return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, 0, Omega, ldo, jpvt, tau, work, work_bytes, info, true);
+  return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, 0, Omega, ldo, jpvt, tau, work, work_bytes, info, true,
+                     false, RQ_FP64, 13);
 }
 
 int rq_rsrqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
@@ -792,7 +881,7 @@ int rq_rsrqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32
   if (rc) return rc;
   if (m == 0 || n == 0) return empty_result((hipStream_t)stream, n, jpvt, info);
   return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes, info,
-                     true, true);
+                     true, true, RQ_FP64, 12);
 }
 
 int rq_unpivoted_qr(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, double* tau, void* work,
@@ -801,17 +890,21 @@ int rq_unpivoted_qr(void* stream, int64_t m, int64_t n, double* A, int64_t lda, 
   if (rc) return rc;
   if (m == 0 || n == 0) return empty_result((hipStream_t)stream, 0, nullptr, info);
   return factor_impl((hipStream_t)stream, m, n, A, lda, b, 0, 0, nullptr, 0, nullptr, tau, work, work_bytes, info,
-                     false);
+                     false, false, RQ_FP64, 9);
 }
 
 static int trqrcp_entry(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int b, int p,
                         uint64_t seed, const double* Omega, int64_t ldo, int64_t* jpvt, double* tau, void* work,
-                        size_t wbytes, int32_t* info, bool mixed = false) {
+                        size_t wbytes, int32_t* info, int prec, int iwork) {
+  const bool mixed = prec != RQ_FP64;
   TrqWS t;
   Carve cv(work, wbytes);
   carve_trq(cv, m, n, k, b, p, t);
-  if (mixed) t.a32 = cv.take<float>((size_t)m * n);
-  if (!cv.ok) return -100;
+  if (mixed) {
+    t.a32 = cv.take<float>((size_t)m * n);
+    t.prec = prec;
+  }
+  if (!cv.ok) return -iwork;
   if (mixed) {
     // the FP32 copy of A that the sketch and the per-block Y2^T A read
     ProfScope ps(PC_SKETCH, s, 12.0 * m * n, 0.0);
@@ -827,21 +920,14 @@ static int trqrcp_entry(hipStream_t s, int64_t m, int64_t n, int64_t k, double* 
 }
 
 int rq_trqrcp(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
-              uint64_t seed, int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
+              uint64_t seed, int32_t precision, int64_t* jpvt, double* tau, void* work, size_t work_bytes,
+              int32_t* info) {
   int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
   if (rc) return rc;
   if (k < 1 || k > std::min(m, n)) return -4;
+  if (precision < RQ_FP64 || precision > RQ_MIXED_BF16) return -10;
   return trqrcp_entry((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes,
-                      info);
-}
-
-int rq_trqrcp_mixed(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
-                    uint64_t seed, int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info) {
-  int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
-  if (rc) return rc;
-  if (k < 1 || k > std::min(m, n)) return -4;
-  return trqrcp_entry((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes,
-                      info, true);
+                      info, precision, 14);
 }
 
 int rq_trqrcp_omega(void* stream, int64_t m, int64_t n, int64_t k, double* A, int64_t lda, int32_t b, int32_t p,
@@ -852,19 +938,21 @@ int rq_trqrcp_omega(void* stream, int64_t m, int64_t n, int64_t k, double* A, in
   if (k < 1 || k > std::min(m, n)) return -4;
   if (!Omega) return -9;
   if (ldo < b + p) return -10;
-  return trqrcp_entry((hipStream_t)stream, m, n, k, A, lda, b, p, 0, Omega, ldo, jpvt, tau, work, work_bytes, info);
+  return trqrcp_entry((hipStream_t)stream, m, n, k, A, lda, b, p, 0, Omega, ldo, jpvt, tau, work, work_bytes, info,
+                      RQ_FP64, 14);
 }
 
 int rq_tuxv(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
-            uint64_t seed, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt, void* work,
-            size_t work_bytes, int32_t* info) {
+            uint64_t seed, int32_t precision, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt,
+            void* work, size_t work_bytes, int32_t* info) {
   int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
   if (rc) return rc;
   if (k < 1 || k > std::min(m, n) || k > 1024) return -4;
-  if (ldu < m) return -11;
-  if (ldvt < k) return -14;
+  if (precision < RQ_FP64 || precision > RQ_MIXED_BF16) return -10;
+  if (ldu < m) return -12;
+  if (ldvt < k) return -15;
   return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, U, ldu, sigma, VT, ldvt, work,
-                   work_bytes, info);
+                   work_bytes, info, 1, precision, 17);
 }
 
 int rq_tuxv_iter(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
@@ -877,19 +965,7 @@ int rq_tuxv_iter(void* stream, int64_t m, int64_t n, int64_t k, const double* A,
   if (ldu < m) return -12;
   if (ldvt < k) return -15;
   return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, U, ldu, sigma, VT, ldvt, work,
-                   work_bytes, info, jmax);
-}
-
-int rq_tuxv_mixed(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
-                  uint64_t seed, double* U, int64_t ldu, double* sigma, double* VT, int64_t ldvt, void* work,
-                  size_t work_bytes, int32_t* info) {
-  int rc = check_common(m, n, lda, b, p, 2, 3, 6, 7, 8);
-  if (rc) return rc;
-  if (k < 1 || k > std::min(m, n) || k > 1024) return -4;
-  if (ldu < m) return -11;
-  if (ldvt < k) return -14;
-  return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, seed, nullptr, 0, U, ldu, sigma, VT, ldvt, work,
-                   work_bytes, info, 1, true);
+                   work_bytes, info, jmax, RQ_FP64, 17);
 }
 
 int rq_tuxv_omega(void* stream, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t b, int32_t p,
@@ -903,7 +979,7 @@ int rq_tuxv_omega(void* stream, int64_t m, int64_t n, int64_t k, const double* A
   if (ldu < m) return -12;
   if (ldvt < k) return -15;
   return tuxv_impl((hipStream_t)stream, m, n, k, A, lda, b, p, 0, Omega, ldo, U, ldu, sigma, VT, ldvt, work,
-                   work_bytes, info);
+                   work_bytes, info, 1, RQ_FP64, 17);
 }
 
 int rq_omega(void* stream, uint64_t seed, int64_t l, int64_t m, double* Omega, int64_t ldo) {
@@ -914,18 +990,19 @@ int rq_omega(void* stream, uint64_t seed, int64_t l, int64_t m, double* Omega, i
   return launch_omega((hipStream_t)stream, seed, l, m, Omega, 1, ldo);
 }
 
-int rq_sketch(void* stream, int64_t m, int64_t n, const double* A, int64_t lda, int32_t l, uint64_t seed, double* B,
-              int64_t ldb, void* work, size_t work_bytes) {
+int rq_sketch(void* stream, int64_t m, int64_t n, const double* A, int64_t lda, int32_t l, uint64_t seed,
+              int32_t precision, double* B, int64_t ldb, void* work, size_t work_bytes) {
   if (m < 0) return -2;
   if (n < 0) return -3;
   if (lda < std::max<int64_t>(1, m)) return -5;
   if (l < 1 || l > 128) return -6;
-  if (ldb < l) return -9;
+  if (precision < RQ_FP64 || precision > RQ_MIXED_BF16) return -8;
+  if (ldb < l) return -10;
   Carve cv(work, work_bytes);
   const int ls = std::max(sample_rows_padded(l), (int)l);
   double* om = cv.take<double>((size_t)l * m);
   double* smp = cv.take<double>((size_t)n * ls);
-  if (!cv.ok) return -100;
+  if (!cv.ok) return -12;
   // the split-K scratch of the factorizations' sketch, when the workspace has room for it
   Carve cv2 = cv;
   const size_t sce = gemm_scratch_elems(l, n, m);
@@ -935,7 +1012,7 @@ int rq_sketch(void* stream, int64_t m, int64_t n, const double* A, int64_t lda, 
   hipStream_t s = (hipStream_t)stream;
   if (m == 0) return launch_zero_rows(s, 0, l, n, B, ldb);  // Omega A = 0
   RQ_TRY(launch_omega(s, seed, l, m, om, 1, l));
-  RQ_TRY(sketch(s, m, n, A, lda, l, om, l, smp, ls, sc, sc ? sce : 0));
+  RQ_TRY(sketch(s, m, n, A, lda, l, om, l, smp, ls, sc, sc ? sce : 0, precision));
   RQ_TRY(launch_copy2d(s, l, n, smp, ls, B, ldb));
   return 0;
 }
@@ -951,7 +1028,7 @@ int rq_sample_qrcp(void* stream, int32_t l, int64_t n, int32_t bsteps, double* B
   carve_common(cv, 1, c);
   SampleBufs sb;
   carve_sample(cv, 0, n, bsteps, l, sb);
-  if (!cv.ok) return -100;
+  if (!cv.ok) return -9;
   hipStream_t s = (hipStream_t)stream;
   RQ_TRY(launch_fill(s, c.flags, c.flag_words));
   RQ_TRY(launch_copy2d(s, l, n, B, ldb, sb.smp, sb.ls));
@@ -975,7 +1052,7 @@ int rq_small_svd(void* stream, int32_t k, double* X, int64_t ldx, double* U, int
   double* tmp = cv.take<double>((size_t)k * k);
   int* err = cv.take<int>(16);
   unsigned* flags = cv.take<unsigned>(128);
-  if (!cv.ok) return -100;
+  if (!cv.ok) return -11;
   RQ_TRY(launch_fill((hipStream_t)stream, err, 16));
   SvdWork sw;
   sw.colnorm = nullptr; sw.order = nullptr; sw.flags = flags; sw.err = err; sw.tmp = tmp;

@@ -90,7 +90,9 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, doubl
   // column of accumulator register r: cj + 16 b + CR * r
   const int64_t cj = j0 + wn * WTN + (F64 ? (lane >> 4) : 4 * (lane >> 4));
   constexpr int CR = F64 ? 4 : 1;
-  if (beta != 0.0) {
+  // (FP32 accumulators start from zero instead: beta C is added in FP64 in
+  // the epilogue, so that C keeps its FP64 precision.)
+  if (F64 && beta != 0.0) {
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -211,7 +213,11 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, doubl
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = ri + a * 16, gj = cj + b * 16 + CR * r;
-        if (gi < M && gj < N) Cz[gi + gj * ldc] = (double)acc[a][b][r];
+        if (gi < M && gj < N) {
+          double v = (double)acc[a][b][r];
+          if (!F64 && beta != 0.0) v += beta * Cz[gi + gj * ldc];
+          Cz[gi + gj * ldc] = v;
+        }
       }
 }
 
@@ -238,6 +244,25 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
     gemm_tile<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
                                                                split_stride, B2, ldb2, nsplit, blockIdx.x,
                                                                blockIdx.y, blockIdx.z);
+  }
+}
+
+// Grouped products (the batched engine): the tiles of many independent
+// products in one persistent launch.  Workgroup g walks the tile list
+// t = g, g + gridDim.x, ...; tile t belongs to product tile_prob[t] and is
+// its tile t - tile0 in row-major tile order (no split-K: every tile runs
+// its whole reduction).
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename Acc>
+__global__ void __launch_bounds__(256, 2) gemm_grouped_kernel(const GroupedGemm* __restrict__ probs,
+                                                           const int* __restrict__ tile_prob, int64_t ntiles) {
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int pi = __builtin_amdgcn_readfirstlane(tile_prob[t]);
+    const GroupedGemm& g = probs[pi];
+    const int64_t lt = t - g.tile0;
+    gemm_tile<BM, BN, BK, WM, WN, TA, TB, double, double, Acc, false>(
+        g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc, g.K, 0, nullptr, 0, 0, lt % g.tiles_x,
+        lt / g.tiles_x, 0);
+    __syncthreads();  // the next tile's LDS stores after every wave's last reads
   }
 }
 
@@ -436,16 +461,72 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
                                                scratch_elems);
 }
 
+namespace {
+template <int BM, int BN, bool TA, bool TB, typename Acc>
+int launch_grouped_one(hipStream_t s, const GroupedGemm* probs, const int* tile_prob, int64_t ntiles, int wgs) {
+  constexpr size_t lds = gemm_lds_bytes<BM, BN, 16, Acc>();
+  auto fn = gemm_grouped_kernel<BM, BN, 16, 2, 2, TA, TB, Acc>;
+  static bool attr = false;
+  if (!attr) {
+    RQ_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, wgs));
+  hipLaunchKernelGGL(fn, dim3(g), dim3(256), lds, s, probs, tile_prob, ntiles);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
+
+template <int BM, int BN, typename Acc>
+int launch_grouped_tr(hipStream_t s, bool ta, bool tb, const GroupedGemm* probs, const int* tile_prob, int64_t ntiles,
+                      int wgs) {
+  if (!ta && !tb) return launch_grouped_one<BM, BN, false, false, Acc>(s, probs, tile_prob, ntiles, wgs);
+  if (ta && !tb) return launch_grouped_one<BM, BN, true, false, Acc>(s, probs, tile_prob, ntiles, wgs);
+  if constexpr (std::is_same<Acc, double>::value) {
+    if (!ta && tb) return launch_grouped_one<BM, BN, false, true, Acc>(s, probs, tile_prob, ntiles, wgs);
+    return launch_grouped_one<BM, BN, true, true, Acc>(s, probs, tile_prob, ntiles, wgs);
+  } else {
+    return -2;  // FP32 grouped products: no transposed second operand
+  }
+}
+}  // namespace
+
+void grouped_tile_shape(int cfg, int* bm, int* bn) {
+  *bm = (cfg == GT_128x64) ? 128 : (cfg == GT_32x32) ? 32 : 64;
+  *bn = (cfg == GT_32x32) ? 32 : 64;
+}
+
+int launch_gemm_grouped(hipStream_t s, int cfg, bool ta, bool tb, bool f32, const GroupedGemm* probs,
+                        const int* tile_prob, int64_t ntiles, int wgs) {
+  if (ntiles <= 0) return 0;
+  switch (cfg) {
+    case GT_32x32:
+      return f32 ? launch_grouped_tr<32, 32, float>(s, ta, tb, probs, tile_prob, ntiles, wgs)
+                 : launch_grouped_tr<32, 32, double>(s, ta, tb, probs, tile_prob, ntiles, wgs);
+    case GT_128x64:
+      return f32 ? launch_grouped_tr<128, 64, float>(s, ta, tb, probs, tile_prob, ntiles, wgs)
+                 : launch_grouped_tr<128, 64, double>(s, ta, tb, probs, tile_prob, ntiles, wgs);
+    default:
+      return f32 ? launch_grouped_tr<64, 64, float>(s, ta, tb, probs, tile_prob, ntiles, wgs)
+                 : launch_grouped_tr<64, 64, double>(s, ta, tb, probs, tile_prob, ntiles, wgs);
+  }
+}
+
 int launch_gemm_persistent(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
-                           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int wgs) {
+                           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int wgs, bool f32) {
   if (M <= 0 || N <= 0) return 0;
-  if (K <= 0 || wgs <= 0)
+  if (K <= 0 || wgs <= 0) {
+    if (f32) return launch_gemm_f32(s, false, false, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, 0);
     return launch_gemm(s, false, false, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, 0);
+  }
   const int64_t tx = (N + 63) / 64, ty = (M + 127) / 128;
   PairB pb;
   pb.persist_tiles_x = tx;
   pb.persist_tiles = tx * ty;
   const unsigned g = (unsigned)std::min<int64_t>(tx * ty, wgs);
+  if (f32)
+    return launch_one<128, 64, 16, 2, 2, false, false, double, double, float, false, true>(
+        s, dim3(g), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, K, 0, pb);
   return launch_one<128, 64, 16, 2, 2, false, false, double, double, double, false, true>(
       s, dim3(g), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, K, 0, pb);
 }
@@ -478,6 +559,13 @@ int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64
                     size_t scratch_elems) {
   return gemm_dispatch<double, float, float>(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch,
                                              scratch_elems);
+}
+
+int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                    int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
+                    size_t scratch_elems) {
+  return gemm_dispatch<double, double, float>(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch,
+                                              scratch_elems);
 }
 
 namespace {

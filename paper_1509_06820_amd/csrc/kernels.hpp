@@ -9,6 +9,16 @@ namespace rq {
 // Omega(r, c) -> out[r*rs + c*cs], r < l, c < m (Philox4x64-10 + Box-Muller).
 int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out, int64_t rs, int64_t cs,
                  uint64_t key1 = 0);
+// Omega of each matrix of a batch: job j writes the l x m matrix of its seed
+// (column-major, ld) -- the same numbers as launch_omega.  jobs: device array;
+// max_elems bounds l * m over the jobs.
+struct OmegaJob {
+  uint64_t seed;
+  int64_t l, m;
+  double* out;
+  int64_t ld;
+};
+int launch_omega_batched(hipStream_t s, const OmegaJob* jobs, int count, int64_t max_elems);
 
 // C = alpha * opA * opB + beta * C  (see gemm.hip).  `scratch` (may be null)
 // enables split-K for short-wide outputs; gemm_scratch_elems gives its size.
@@ -20,12 +30,38 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
 // C = alpha A B + beta C (no transposes) with 128 x 64 tiles on a grid of at
 // most `wgs` workgroups that walk the tiles, so that the launch leaves CUs
 // free for a kernel beside it.
+// With f32, the products on the FP32 matrix cores (added to FP64 C).
 int launch_gemm_persistent(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
-                           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int wgs);
+                           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int wgs,
+                           bool f32 = false);
 int launch_gemm_pair(hipStream_t s, int64_t M, int64_t N1, int64_t K, double alpha, const double* A, int64_t lda,
                      const double* B1, int64_t ldb1, const double* B2, int64_t ldb2, double beta, double* C,
                      int64_t ldc, double* scratch, size_t scratch_elems);
 size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K);
+// One product of a grouped launch: C = alpha op(A) op(B) + beta C (M x N,
+// reduction K), tiles_x = tiles per row of output tiles, tile0 = index of
+// its first tile in the launch's tile list.
+struct GroupedGemm {
+  int64_t M, N, K;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  double alpha, beta;
+  int64_t tiles_x, tile0;
+};
+// Tile shapes of the grouped launches (output rows x columns per workgroup).
+enum { GT_64x64 = 0, GT_32x32 = 1, GT_128x64 = 2, GT_NCFG = 3 };
+void grouped_tile_shape(int cfg, int* bm, int* bn);
+// All tiles of the products probs[0..] (device arrays; tile_prob[t] = the
+// product of tile t) in one persistent launch of at most wgs workgroups.
+// f32: operands rounded to FP32 on the FP32 matrix cores (no transposed
+// second operand), FP64 C.  Every product of a launch has the same
+// transposes.
+int launch_gemm_grouped(hipStream_t s, int cfg, bool ta, bool tb, bool f32, const GroupedGemm* probs,
+                        const int* tile_prob, int64_t ntiles, int wgs);
 // The same products on the FP32 matrix cores (operands rounded to FP32,
 // FP32 accumulation, FP64 C), with one operand stored in FP32.
 int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A,
@@ -34,6 +70,16 @@ int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64
 int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                     int64_t lda, const float* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
                     size_t scratch_elems);
+int launch_gemm_f32(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                    int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* scratch,
+                    size_t scratch_elems);
+// Sketch S (l x n, ld lds) = Omega (l x m, ld ldo) A (m x n, ld lda) on the
+// BF16 matrix cores: both operands rounded to BF16, FP32 accumulation, FP64
+// output; split along m when scratch (gemm_scratch_elems(l, n, m)) is given.
+int launch_sketch_bf16(hipStream_t s, int64_t l, int64_t n, int64_t m, const double* Omega, int64_t ldo,
+                       const double* A, int64_t lda, double* S, int64_t lds, double* scratch, size_t scratch_elems);
+int launch_sketch_bf16(hipStream_t s, int64_t l, int64_t n, int64_t m, const double* Omega, int64_t ldo,
+                       const float* A, int64_t lda, double* S, int64_t lds, double* scratch, size_t scratch_elems);
 // dst (FP32, rows x cols, ld ldd) = src (FP64, ld lds) rounded to nearest;
 // with dst64, also an FP64 copy in the same pass.
 int launch_to_f32(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst, int64_t ldd,
@@ -79,6 +125,8 @@ struct PanelWork {
   const int* gate;
 };
 size_t panel_slot_elems(int64_t mmax, int bmax);
+// launch_panel's return value when its workgroups cannot all be resident.
+constexpr int RQ_PANEL_TOO_TALL = RQ_ERR_HIP_BASE + (int)hipErrorCooperativeLaunchTooLarge;
 int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, double* tau, double* Y, int64_t ldy,
                  const PanelWork& w);
 

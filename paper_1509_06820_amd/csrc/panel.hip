@@ -175,11 +175,21 @@ int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, doub
   // An ordinary launch, not a cooperative one: the kernel is the fallback of
   // the CholeskyQR panel and almost always leaves at its gate, before any
   // exchange, and a cooperative dispatch costs the queue tens of
-  // microseconds per block.  When the gate is set, the NP workgroups (one
-  // per 256 rows, 512 threads each) are resident together on an otherwise
-  // idle device; the exchange waits are bounded, so a workgroup that was not
-  // resident in time makes the call report failure (info = -1) instead of
-  // hanging.
+  // microseconds per block.  Its NP workgroups (one per 256 rows, 512
+  // threads each) wait on each other, so they must fit the device at once:
+  // checked here against one CU's occupancy times the CU count (the caller
+  // turns a panel too tall for that into an error).  The exchange waits are
+  // bounded, so a workgroup held back by other work on the device makes the
+  // call report failure (info = -1) instead of hanging.
+  static int resident = 0;
+  if (!resident) {
+    int occ = 0, dev = 0, cus = 0;
+    RQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, panel_kernel, PN_THREADS, 0));
+    RQ_HIP(hipGetDevice(&dev));
+    RQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    resident = std::max(1, occ * cus);
+  }
+  if (a.NP > resident) return RQ_PANEL_TOO_TALL;
   hipLaunchKernelGGL(panel_kernel, dim3(a.NP), dim3(PN_THREADS), 0, s, a);
   RQ_HIP(hipGetLastError());
   return 0;

@@ -68,7 +68,44 @@ __global__ void __launch_bounds__(256) omega_kernel(uint64_t seed, uint64_t key1
   }
 }
 
+// The same numbers for the matrices of a batch: grid.y walks the jobs.
+__global__ void __launch_bounds__(256) omega_batched_kernel(const OmegaJob* __restrict__ jobs, int count) {
+  for (int j = blockIdx.y; j < count; j += gridDim.y) {
+    const OmegaJob jb = jobs[j];
+    const int64_t total = jb.l * jb.m;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q * 4 < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+      uint64_t w[4];
+      philox_block((uint64_t)q, jb.seed, 0, w);
+      const double two_pi = 2.0 * M_PI;
+      const double r01 = sqrt(-2.0 * log(u52(w[0])));
+      const double r23 = sqrt(-2.0 * log(u52(w[2])));
+      const double a01 = two_pi * u52(w[1]);
+      const double a23 = two_pi * u52(w[3]);
+      const double z[4] = {r01 * cos(a01), r01 * sin(a01), r23 * cos(a23), r23 * sin(a23)};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t t = q * 4 + i;
+        if (t < total) {
+          const int64_t r = t / jb.m, c = t - r * jb.m;
+          jb.out[r + c * jb.ld] = z[i];
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
+
+int launch_omega_batched(hipStream_t s, const OmegaJob* jobs, int count, int64_t max_elems) {
+  if (count <= 0 || max_elems <= 0) return 0;
+  const int64_t blocks = (max_elems + 3) / 4;
+  const unsigned gx = (unsigned)std::min<int64_t>((blocks + 255) / 256, 64);
+  const unsigned gy = (unsigned)std::min(count, 65535);
+  hipLaunchKernelGGL(omega_batched_kernel, dim3(gx, gy), dim3(256), 0, s, jobs, count);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
 
 int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out, int64_t rs, int64_t cs,
                  uint64_t key1) {

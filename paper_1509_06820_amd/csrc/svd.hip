@@ -1,5 +1,5 @@
-// SVD of the k x k connection matrix X of TUXV (Section 6: "feasible to obtain
-// slightly better approximations by taking the SVD of X").
+// SVD of the k x k connection matrix X of TUXV (Section 6: a small SVD of X
+// turns U X V^T into a truncated SVD and refines the approximation).
 //
 // One-sided Jacobi (Hestenes): plane rotations orthogonalise pairs of columns
 // of X; the rotations are accumulated in V, so that on convergence
@@ -34,14 +34,15 @@ __device__ __forceinline__ void rr_pair(int r, int idx, int kk, int& p, int& q) 
   }
 }
 
-// Rotation sweeps spread over P workgroups (cooperative launch): in each
+// Rotation sweeps spread over P workgroups (all resident at once): in each
 // round wave w of workgroup me takes pairs idx = 4 me + w, 4 me + w + 4 P,
 // ... of the round-robin order, and the workgroups meet at an arrival
 // barrier before the next round reads the rotated columns.  A wave that
 // rotated during the sweep marks the sweep's flag; after the sweep's last
 // barrier every workgroup reads it, so all of them stop after the same sweep.
 // flags[0]: arrival counter, flags[1 + s]: sweep s rotated (zeroed by the
-// caller).
+// caller).  A last sweep that still rotated sets the error word to 2 (no
+// convergence within max_sweeps) unless an earlier failure set it.
 constexpr int JW_T = 256;             // threads of a sweep workgroup: four waves, one column pair each
 constexpr int JW_PAIRS = JW_T / WAVE;  // column pairs a workgroup rotates at once
 constexpr int JW_MAXK = 1024;
@@ -145,6 +146,7 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
     }
     const unsigned rot = __hip_atomic_load(&flags[1 + sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (__builtin_amdgcn_readfirstlane(rot) == 0u) break;
+    if (sweep == max_sweeps - 1 && blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(err, 0, 2);
   }
 }
 
@@ -207,12 +209,34 @@ int launch_jacobi_svd(hipStream_t s, int k, double* X, int64_t ldx, double* U, i
   int ksw = k;
   int64_t ldt = k;
   int maxs = MAX_SWEEPS;
-  void* args[] = {&ksw, &X, &ldx, (void*)&w.tmp, &ldt, &tol, &maxs, (void*)&w.flags, (void*)&w.err};
-  const void* fn = (k <= 4 * WAVE)   ? (const void*)jacobi_sweeps_kernel<4>
-                   : (k <= 8 * WAVE) ? (const void*)jacobi_sweeps_kernel<8>
-                                     : (const void*)jacobi_sweeps_kernel<16>;
   static_assert(16 * WAVE >= JW_MAXK, "rows per lane");
-  RQ_HIP(hipLaunchCooperativeKernel(fn, dim3(P), dim3(JW_T), args, 0, s));
+  // An ordinary launch after a residency check (occupancy of one CU times
+  // the CU count; at most k/8 = 128 workgroups of 256 threads): the
+  // workgroups wait on each other at the round barriers, whose waits are
+  // bounded, so a workgroup held back by other work makes the call report
+  // info = -1 instead of hanging.
+  static int resident[3] = {0, 0, 0};
+  const int which = (k <= 4 * WAVE) ? 0 : (k <= 8 * WAVE) ? 1 : 2;
+  const void* fns[3] = {(const void*)jacobi_sweeps_kernel<4>, (const void*)jacobi_sweeps_kernel<8>,
+                        (const void*)jacobi_sweeps_kernel<16>};
+  if (!resident[which]) {
+    int occ = 0, dev = 0, cus = 0;
+    RQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fns[which], JW_T, 0));
+    RQ_HIP(hipGetDevice(&dev));
+    RQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    resident[which] = std::max(1, occ * cus);
+  }
+  if (P > resident[which]) return RQ_ERR_HIP_BASE + (int)hipErrorCooperativeLaunchTooLarge;
+  if (which == 0)
+    hipLaunchKernelGGL(jacobi_sweeps_kernel<4>, dim3(P), dim3(JW_T), 0, s, ksw, X, ldx, w.tmp, ldt, tol, maxs,
+                       w.flags, w.err);
+  else if (which == 1)
+    hipLaunchKernelGGL(jacobi_sweeps_kernel<8>, dim3(P), dim3(JW_T), 0, s, ksw, X, ldx, w.tmp, ldt, tol, maxs,
+                       w.flags, w.err);
+  else
+    hipLaunchKernelGGL(jacobi_sweeps_kernel<16>, dim3(P), dim3(JW_T), 0, s, ksw, X, ldx, w.tmp, ldt, tol, maxs,
+                       w.flags, w.err);
+  RQ_HIP(hipGetLastError());
   hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(SVD_THREADS), 0, s, k, (const double*)X, ldx,
                      (const double*)w.tmp, (int64_t)k, U, ldu, sigma, V, ldv, (const int*)w.err);
   RQ_HIP(hipGetLastError());

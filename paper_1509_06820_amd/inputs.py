@@ -14,9 +14,13 @@ Fortran-ordered (column-major) arrays.
 * ``with_spectrum``     U diag(sigma) V^T with Haar-random orthonormal
                         factors (QR of a Gaussian with the R-diagonal sign
                         fix), U drawn before V.
-* ``spectrum_geometric`` etc. give the singular value profiles of the
-                        configurations (sigma_i = 10^(-10 i/n), 0.9^(i/10),
-                        10^(-6 i/n), 0.95^i), index i starting at 0.
+* ``sigma_decade``, ``sigma_power`` give the singular value profiles of the
+                        configurations (sigma_i = 10^(-10 i/n), 0.9^(i/10)),
+                        index i starting at 0.
+* ``batch_c4``          the batched workload (512 uneven matrices,
+                        sigma_j = 10^(-6 j/n)).
+* ``serving_c5``, ``serving_matrix``  the served request stream
+                        (sigma_i = 0.95^i).
 """
 
 import numpy as np
@@ -86,6 +90,55 @@ def optimal_truncation_error(sigma, k):
     of a matrix with singular values sigma (a closed form, not the method)."""
     s2 = np.asarray(sigma, dtype=np.float64) ** 2
     return float(np.sqrt(s2[k:].sum() / s2.sum()))
+
+
+def batch_c4(count=512, seed=4000):
+    """The batched workload: matrix i draws from default_rng(seed + i)
+    m = round(exp(U(ln 64, ln 2048))), n = round(U(64, m)) (uniform on
+    [64, m]), then U diag(sigma) V^T with sigma_j = 10^(-6 j / n) and Haar
+    factors (U before V).  Returns a list of (A, params) with k = 32, p = 8."""
+    out = []
+    for i in range(count):
+        rng = _rng(seed + i)
+        m = int(round(np.exp(rng.uniform(np.log(64), np.log(2048)))))
+        n = int(round(rng.uniform(64, m)))
+        q = min(m, n)
+        sig = 10.0 ** (-6.0 * np.arange(q) / n)
+        U = haar_columns(rng, m, q)
+        V = haar_columns(rng, n, q)
+        out.append((np.asfortranarray((U * sig) @ V.T), dict(m=m, n=n, k=min(n, 32), p=8, seed=seed + i)))
+    return out
+
+
+def serving_c5(count=2000, seed=5, smin=256, smax=8192):
+    """The served request stream: request i (rng = default_rng(seed), drawn in
+    order) has m, n = max and min of two log-uniform draws on [smin, smax],
+    k uniform in {16, 32, 64, 128, 256} (at most n), precision FP64 or mixed
+    with probability 1/2, and an inter-arrival gap drawn as Exp(1) (scaled
+    to the arrival rate by the caller).  The matrix itself is drawn by
+    serving_matrix(i, m, n), sigma_i = 0.95^i, Haar factors."""
+    rng = _rng(seed)
+    reqs = []
+    for i in range(count):
+        a, b = np.exp(rng.uniform(np.log(smin), np.log(smax), size=2))
+        m, n = int(round(max(a, b))), int(round(min(a, b)))
+        k = int(min(n, rng.choice([16, 32, 64, 128, 256])))
+        mixed = bool(rng.uniform() < 0.5)
+        gap = float(rng.exponential(1.0))
+        reqs.append(dict(i=i, m=m, n=n, k=k, mixed=mixed, gap=gap))
+    return reqs
+
+
+def serving_matrix(i, m, n, seed=5):
+    """The matrix of served request i: U diag(0.95^j) V^T, Haar factors from
+    default_rng(seed * 100003 + i); triplets below 1e-17 sigma_0 dropped."""
+    rng = _rng(seed * 100003 + i)
+    q = min(m, n)
+    r = min(q, int(np.ceil(np.log(1e-17) / np.log(0.95))))
+    sig = 0.95 ** np.arange(r)
+    U = haar_columns(rng, m, r)
+    V = haar_columns(rng, n, r)
+    return np.asfortranarray((U * sig) @ V.T)
 
 
 # The configurations of the benchmark plan, by name.

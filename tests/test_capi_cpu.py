@@ -68,26 +68,35 @@ def test_workspace_query(lib, op, m, n, k, b, p):
 
 def test_workspace_query_rejects_bad_arguments(lib):
     out = ctypes.c_size_t(0)
-    assert lib.rq_workspace_bytes(0, -1, 5, 0, 8, 0, ctypes.byref(out)) == -2
-    assert lib.rq_workspace_bytes(0, 5, -1, 0, 8, 0, ctypes.byref(out)) == -3
-    assert lib.rq_workspace_bytes(0, 5, 5, 0, 0, 0, ctypes.byref(out)) == -5
-    assert lib.rq_workspace_bytes(0, 5, 5, 0, 65, 0, ctypes.byref(out)) == -5
-    assert lib.rq_workspace_bytes(0, 5, 5, 0, 64, 65, ctypes.byref(out)) == -6
-    assert lib.rq_workspace_bytes(1, 5, 5, 6, 4, 0, ctypes.byref(out)) == -4
-    assert lib.rq_workspace_bytes(99, 5, 5, 1, 4, 0, ctypes.byref(out)) == -1
+    assert lib.rq_workspace_bytes(0, -1, 5, 0, 8, 0, 0, ctypes.byref(out)) == -2
+    assert lib.rq_workspace_bytes(0, 5, -1, 0, 8, 0, 0, ctypes.byref(out)) == -3
+    assert lib.rq_workspace_bytes(0, 5, 5, 0, 0, 0, 0, ctypes.byref(out)) == -5
+    assert lib.rq_workspace_bytes(0, 5, 5, 0, 65, 0, 0, ctypes.byref(out)) == -5
+    assert lib.rq_workspace_bytes(0, 5, 5, 0, 64, 65, 0, ctypes.byref(out)) == -6
+    assert lib.rq_workspace_bytes(1, 5, 5, 6, 4, 0, 0, ctypes.byref(out)) == -4
+    assert lib.rq_workspace_bytes(99, 5, 5, 1, 4, 0, 0, ctypes.byref(out)) == -1
+    # precision: one of the three levels, and only for RQRCP, TRQRCP and TUXV
+    assert lib.rq_workspace_bytes(0, 5, 5, 0, 4, 0, 3, ctypes.byref(out)) == -7
+    assert lib.rq_workspace_bytes(0, 5, 5, 0, 4, 0, -1, ctypes.byref(out)) == -7
+    assert lib.rq_workspace_bytes(binding.RQ_OP_QR, 5, 5, 0, 4, 0, 1, ctypes.byref(out)) == -7
+    assert lib.rq_workspace_bytes(0, 5, 5, 0, 4, 0, 0, None) == -8
 
 
 def test_entry_points_reject_bad_arguments_before_any_launch(lib):
     null = ctypes.c_void_p(0)
-    # m < 0, n < 0, lda < m, b out of range, p out of range
-    assert lib.rq_rqrcp(null, -1, 4, null, 1, 8, 0, 1, null, null, null, 0, null) == -2
-    assert lib.rq_rqrcp(null, 4, -1, null, 4, 8, 0, 1, null, null, null, 0, null) == -3
-    assert lib.rq_rqrcp(null, 4, 4, null, 3, 8, 0, 1, null, null, null, 0, null) == -5
-    assert lib.rq_rqrcp(null, 4, 4, null, 4, 0, 0, 1, null, null, null, 0, null) == -6
-    assert lib.rq_rqrcp(null, 4, 4, null, 4, 8, -1, 1, null, null, null, 0, null) == -7
-    assert lib.rq_trqrcp(null, 10, 10, 11, null, 10, 4, 4, 1, null, null, null, 0, null) == -4
-    assert lib.rq_tuxv(null, 10, 10, 0, null, 10, 4, 4, 1, null, 10, null, null, 1, null, 0, null) == -4
-    assert lib.rq_tuxv(null, 10, 10, 3, null, 10, 4, 4, 1, null, 9, null, null, 3, null, 0, null) == -11
+    # m < 0, n < 0, lda < m, b out of range, p out of range, precision out of range
+    assert lib.rq_rqrcp(null, -1, 4, null, 1, 8, 0, 1, 0, null, null, null, 0, null) == -2
+    assert lib.rq_rqrcp(null, 4, -1, null, 4, 8, 0, 1, 0, null, null, null, 0, null) == -3
+    assert lib.rq_rqrcp(null, 4, 4, null, 3, 8, 0, 1, 0, null, null, null, 0, null) == -5
+    assert lib.rq_rqrcp(null, 4, 4, null, 4, 0, 0, 1, 0, null, null, null, 0, null) == -6
+    assert lib.rq_rqrcp(null, 4, 4, null, 4, 8, -1, 1, 0, null, null, null, 0, null) == -7
+    assert lib.rq_rqrcp(null, 4, 4, null, 4, 8, 0, 1, 3, null, null, null, 0, null) == -9
+    assert lib.rq_trqrcp(null, 10, 10, 11, null, 10, 4, 4, 1, 0, null, null, null, 0, null) == -4
+    assert lib.rq_trqrcp(null, 10, 10, 3, null, 10, 4, 4, 1, 7, null, null, null, 0, null) == -10
+    assert lib.rq_tuxv(null, 10, 10, 0, null, 10, 4, 4, 1, 0, null, 10, null, null, 1, null, 0, null) == -4
+    assert lib.rq_tuxv(null, 10, 10, 3, null, 10, 4, 4, 1, 5, null, 10, null, null, 3, null, 0, null) == -10
+    assert lib.rq_tuxv(null, 10, 10, 3, null, 10, 4, 4, 1, 0, null, 9, null, null, 3, null, 0, null) == -12
+    assert lib.rq_tuxv(null, 10, 10, 3, null, 10, 4, 4, 1, 1, null, 10, null, null, 2, null, 0, null) == -15
     assert lib.rq_rqrcp_omega(null, 4, 4, null, 4, 2, 2, null, 4, null, null, null, 0, null) == -8
     assert lib.rq_unpivoted_qr(null, 4, 4, null, 2, 2, null, null, 0, null) == -5
     assert lib.rq_sample_qrcp(null, 0, 4, 1, null, 1, null, null, 0, null) == -2
@@ -95,6 +104,8 @@ def test_entry_points_reject_bad_arguments_before_any_launch(lib):
     assert lib.rq_small_svd(null, 0, null, 1, null, 1, null, null, 1, null, 0) == -2
     assert lib.rq_rsrqrcp(null, 4, 4, null, 3, 8, 0, 1, null, null, null, 0, null) == -5
     assert lib.rq_rsrqrcp(null, 4, 4, null, 4, 8, -1, 1, null, null, null, 0, null) == -7
+    assert lib.rq_sketch(null, 4, 4, null, 4, 2, 1, 9, null, 2, null, 0) == -8
+    assert lib.rq_sketch(null, 4, 4, null, 4, 2, 1, 0, null, 1, null, 0) == -10
     # j_max outside [1, RQ_TUXV_MAX_ITER], then ldu < m and ldvt < k
     for jmax in (0, -3, binding.RQ_TUXV_MAX_ITER + 1):
         assert lib.rq_tuxv_iter(null, 10, 10, 3, null, 10, 4, 4, 1, jmax, null, 10, null, null, 3, null, 0,
@@ -104,25 +115,36 @@ def test_entry_points_reject_bad_arguments_before_any_launch(lib):
     assert lib.rq_tuxv_iter(null, 10, 10, 11, null, 10, 4, 4, 1, 2, null, 10, null, null, 11, null, 0, null) == -4
     # empty matrices are valid and enqueue nothing
     assert lib.rq_rsrqrcp(null, 0, 4, null, 1, 8, 0, 1, null, null, null, 0, null) == 0
-    assert lib.rq_rqrcp(null, 0, 4, null, 1, 8, 0, 1, null, null, null, 0, null) == 0
-    # workspace too small
-    assert lib.rq_rqrcp(null, 40, 40, null, 40, 8, 0, 1, null, null, null, 16, null) == -100
-    assert lib.rq_rsrqrcp(null, 40, 40, null, 40, 8, 0, 1, null, null, null, 16, null) == -100
-    assert lib.rq_tuxv_iter(null, 40, 40, 8, null, 40, 8, 0, 1, 3, null, 40, null, null, 8, null, 16, null) == -100
+    assert lib.rq_rqrcp(null, 0, 4, null, 1, 8, 0, 1, 0, null, null, null, 0, null) == 0
+    # a workspace below the size query makes the size argument invalid
+    assert lib.rq_rqrcp(null, 40, 40, null, 40, 8, 0, 1, 0, null, null, null, 16, null) == -13
+    assert lib.rq_rqrcp_omega(null, 40, 40, null, 40, 8, 0, ctypes.c_void_p(256), 8, null, null, null, 16,
+                              null) == -13
+    assert lib.rq_rsrqrcp(null, 40, 40, null, 40, 8, 0, 1, null, null, null, 16, null) == -12
+    assert lib.rq_unpivoted_qr(null, 40, 40, null, 40, 8, null, null, 16, null) == -9
+    assert lib.rq_trqrcp(null, 40, 40, 8, null, 40, 8, 0, 1, 1, null, null, null, 16, null) == -14
+    assert lib.rq_tuxv(null, 40, 40, 8, null, 40, 8, 0, 1, 2, null, 40, null, null, 8, null, 16, null) == -17
+    assert lib.rq_tuxv_iter(null, 40, 40, 8, null, 40, 8, 0, 1, 3, null, 40, null, null, 8, null, 16, null) == -17
+    assert lib.rq_sample_qrcp(null, 8, 40, 4, null, 8, null, null, 16, null) == -9
+    assert lib.rq_small_svd(null, 40, null, 40, null, 40, null, null, 40, null, 16) == -11
+    assert lib.rq_sketch(null, 40, 40, null, 40, 8, 1, 0, null, 8, null, 16) == -12
 
 
-def test_mixed_tuxv_workspace_and_arguments(lib):
-    """The mixed path adds the FP32 copy of A (4 m n bytes) and the permuted
-    V (8 n k bytes) to the TUXV workspace."""
-    m, n, k, b, p = 20000, 10000, 256, 64, 8
-    extra = (binding.rq_workspace_bytes(binding.RQ_OP_TUXV_MIXED, m, n, k, b, p)
-             - binding.rq_workspace_bytes(binding.RQ_OP_TUXV, m, n, k, b, p))
-    assert 4 * m * n + 8 * n * k <= extra <= 4 * m * n + 8 * n * k + 1024
-    null = ctypes.c_void_p(0)
-    assert lib.rq_tuxv_mixed(null, 10, 10, 0, null, 10, 4, 4, 1, null, 10, null, null, 1, null, 0, null) == -4
-    assert lib.rq_tuxv_mixed(null, 10, 10, 3, null, 10, 4, 4, 1, null, 9, null, null, 3, null, 0, null) == -11
-    assert lib.rq_tuxv_mixed(null, 10, 10, 3, null, 10, 4, 4, 1, null, 10, null, null, 2, null, 0, null) == -14
-    assert lib.rq_tuxv_mixed(null, 40, 40, 8, null, 40, 8, 0, 1, null, 40, null, null, 8, null, 16, null) == -100
+@pytest.mark.parametrize("op,k", [(binding.RQ_OP_TUXV, 256), (binding.RQ_OP_TRQRCP, 256), (binding.RQ_OP_RQRCP, 0)])
+def test_mixed_workspace(lib, op, k):
+    """The mixed levels of TRQRCP and TUXV add the FP32 copy of A (4 m n
+    bytes; TUXV also the permuted V, 8 n k bytes); the mixed RQRCP updates A
+    in place and needs nothing more.  Both mixed levels need the same space."""
+    m, n, b, p = 20000, 10000, 64, 8
+    base = binding.rq_workspace_bytes(op, m, n, k, b, p, binding.RQ_FP64)
+    for prec in (binding.RQ_MIXED, binding.RQ_MIXED_BF16):
+        extra = binding.rq_workspace_bytes(op, m, n, k, b, p, prec) - base
+        if op == binding.RQ_OP_TUXV:
+            assert 4 * m * n + 8 * n * k <= extra <= 4 * m * n + 8 * n * k + 1024
+        elif op == binding.RQ_OP_TRQRCP:
+            assert 4 * m * n <= extra <= 4 * m * n + 512
+        else:
+            assert extra == 0
 
 
 def test_rsrqrcp_workspace_matches_rqrcp(lib):
@@ -133,23 +155,48 @@ def test_rsrqrcp_workspace_matches_rqrcp(lib):
                 == binding.rq_workspace_bytes(binding.RQ_OP_RQRCP, m, n, 0, b, p))
 
 
-def test_lookahead_switch_is_host_only(lib):
+def test_host_switches_are_host_only(lib):
+    """The look-ahead, panel-path and block-dump switches touch no GPU and
+    report the previous setting (or reject an invalid one)."""
     prev = lib.rq_set_lookahead(0)
     assert prev in (0, 1)
     assert lib.rq_set_lookahead(1) == 0
     assert lib.rq_set_lookahead(prev) == 1
+    assert lib.rq_set_panel_path(1) == 0
+    assert lib.rq_set_panel_path(0) == 1
+    assert lib.rq_set_panel_path(2) == -1
+    assert lib.rq_set_block_dump(ctypes.c_void_p(0), -1) == -2
+    assert lib.rq_set_block_dump(ctypes.c_void_p(0), 0) == 0
 
 
-def test_mixed_trqrcp_workspace_and_arguments(lib):
-    """The mixed TRQRCP adds the FP32 copy of A (4 m n bytes) to the TRQRCP
-    workspace; arguments are checked as for rq_trqrcp."""
-    m, n, k, b, p = 20000, 10000, 256, 64, 8
-    extra = (binding.rq_workspace_bytes(binding.RQ_OP_TRQRCP_MIXED, m, n, k, b, p)
-             - binding.rq_workspace_bytes(binding.RQ_OP_TRQRCP, m, n, k, b, p))
-    assert 4 * m * n <= extra <= 4 * m * n + 512
-    null = ctypes.c_void_p(0)
-    assert lib.rq_trqrcp_mixed(null, 10, 10, 0, null, 10, 4, 4, 1, null, null, null, 0, null) == -4
-    assert lib.rq_trqrcp_mixed(null, 10, 10, 11, null, 10, 4, 4, 1, null, null, null, 0, null) == -4
-    assert lib.rq_trqrcp_mixed(null, 10, 10, 3, null, 9, 4, 4, 1, null, null, null, 0, null) == -6
-    assert lib.rq_trqrcp_mixed(null, 10, 10, 3, null, 10, 65, 4, 1, null, null, null, 0, null) == -7
-    assert lib.rq_trqrcp_mixed(null, 40, 40, 8, null, 40, 8, 0, 1, null, null, null, 16, null) == -100
+def test_batch_workspace_query_and_argument_checks(lib):
+    """rq_batch_workspace_bytes: grows with the matrices and rejects what the
+    batched engine cannot take (k > 64, b not dividing k, b + p > 64, an item
+    with k > min(m, n) or n > 8192, the BF16 level)."""
+    small = binding.batch_workspace_bytes([(100, 80)], 16, 8, 8)
+    two = binding.batch_workspace_bytes([(100, 80), (300, 200)], 16, 8, 8)
+    assert 0 < small < two
+    for args in [([(100, 80)], 65, 8, 8), ([(100, 80)], 16, 6, 8), ([(100, 80)], 16, 8, 57),
+                 ([(10, 80)], 16, 8, 8), ([(9000, 8500)], 16, 8, 8)]:
+        with pytest.raises(binding.RQError):
+            binding.batch_workspace_bytes(*args)
+    with pytest.raises(binding.RQError):
+        binding.batch_workspace_bytes([(100, 80)], 16, 8, 8, precision=binding.RQ_MIXED_BF16)
+    assert binding.batch_workspace_bytes([], 16, 8, 8) > 0
+
+
+def test_autotune_host_logic(tmp_path):
+    """Block candidates divide k and keep b + p <= 64; the size signature
+    groups matrices by (log2 m, log2 n); a cached choice is found again."""
+    import json
+
+    from paper_1509_06820_amd import autotune
+    assert autotune.block_candidates(32, 8) == [8, 16, 32]
+    assert autotune.block_candidates(32, 40) == [8, 16]
+    assert autotune.block_candidates(24, 8) == [8]
+    assert autotune.signature([(100, 80), (120, 70), (1000, 900)]) == "6x6:2;9x9:1"
+    shapes = [(100, 80), (300, 200)]
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({autotune.key(shapes, 16, 8, 0): {"b": 8, "tile": 1, "ms": 1.0}}))
+    assert autotune.lookup(shapes, 16, 8, 0, str(path))["tile"] == 1
+    assert autotune.lookup(shapes, 32, 8, 0, str(path)) is None

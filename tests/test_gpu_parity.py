@@ -294,57 +294,134 @@ def test_tuxv_matches_oracle(m, n, k, b, p, seed):
 
 
 # ---------------------------------------------------------------- full size
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_pivot_golden(name):
+    """(jpvt, gaps, |R_jj|, header lines) of a golden written by
+    tests/golden/make_full_size_goldens.py (oracle only)."""
+    path = os.path.join(GOLDEN, name)
+    header = [ln[1:].strip() for ln in open(path) if ln.startswith("#")]
+    rows = np.loadtxt(path, comments="#")
+    return rows[:, 1].astype(np.int64), rows[:, 2], rows[:, 3], header
+
+
+def gpu_residual_orth(At, F, tau, jpvt, k=None):
+    """||A P - Q R||_F / ||A||_F and ||Q^T Q - I||_F on the GPU (Q formed
+    from the reflectors by torch.linalg.householder_product)."""
+    n = At.shape[1]
+    k = min(At.shape) if k is None else k
+    Q = torch.linalg.householder_product(F[:, :k], tau[:k])
+    R = torch.triu(F[:k, :])
+    res = (torch.linalg.norm(At[:, jpvt] - Q @ R) / torch.linalg.norm(At)).item()
+    orth = torch.linalg.norm(Q.T @ Q - torch.eye(k, dtype=torch.float64, device="cuda")).item()
+    del Q, R
+    return res, orth
+
+
 def test_rqrcp_8192_full_size_gaussian():
-    """8192 x 8192 i.i.d. N(0,1), b = 64, p = 8, seed 2 (the benchmark launch):
-    pivots of the first two blocks against the oracle (TRQRCP(128) has the
-    same first 128 pivots), residual and orthogonality of the whole GPU
-    factorization checked on the GPU."""
+    """8192 x 8192 i.i.d. N(0,1), b = 64, p = 8, seed 2 (the benchmark
+    launch), the whole factorization against the oracle's full RQRCP
+    (tests/golden/c2_iid_rqrcp.txt): every pivot up to the oracle's first
+    near tie (there is none: its smallest gap is 2.3e-6), |R_jj| for all
+    8192 steps within 1e-12 ||A||_F, rows 0..127 of R element by element
+    against the oracle's TRQRCP(128) (which forms the same rows), residual
+    and orthogonality on the GPU."""
     say("rqrcp 8192x8192 gaussian b=64 p=8 seed=2")
     A, prm = inputs.config_matrix("c2_iid")
+    gj, gg, grd, _ = load_pivot_golden("c2_iid_rqrcp.txt")
     At = dev(A)
     F, tau, jpvt, info = binding.rq_rqrcp(At, prm["b"], prm["p"], prm["seed"])
     torch.cuda.synchronize()
     assert int(info.item()) == 0
-    ref = oracle.trqrcp(A, 128, prm["b"], prm["p"], seed=prm["seed"])
     jp = host(jpvt)
-    t = trusted_prefix(ref["gaps"], 128)
-    assert np.array_equal(jp[:t], ref["jpvt"][:t])
+    t = trusted_prefix(gg, 8192)
+    say(f"c2 trusted prefix {t}")
+    assert np.array_equal(jp[:t], gj[:t])
     assert sorted(jp.tolist()) == list(range(8192))
-    Q = torch.linalg.householder_product(F, tau)
-    R = torch.triu(F)
-    Ap = At[:, jpvt]
-    res = (torch.linalg.norm(Ap - Q @ R) / torch.linalg.norm(At)).item()
-    orth = torch.linalg.norm(Q.T @ Q - torch.eye(8192, dtype=torch.float64, device="cuda")).item()
+    nrm = np.linalg.norm(A)
+    rd = np.abs(host(torch.diagonal(F)))
+    assert np.abs(rd[:t] - grd[:t]).max() <= 1e-12 * nrm
+    # rows 0..127 of R compared un-permuted (R P^T): past column 127 the two
+    # runs order the remaining columns differently (TRQRCP(128) stops after
+    # two blocks of swaps, RQRCP applies 126 more)
+    ref = oracle.trqrcp(A, 128, prm["b"], prm["p"], seed=prm["seed"])
+    assert np.array_equal(ref["jpvt"][:128], gj[:128])
+    Zg = np.zeros((128, 8192))
+    Zg[:, jp] = np.triu(host(F[:128, :]))
+    Zo = np.zeros((128, 8192))
+    Zo[:, ref["jpvt"]] = np.triu(ref["F"][:128])
+    assert np.abs(Zg - Zo).max() <= 1e-12 * nrm
+    res, orth = gpu_residual_orth(At, F, tau, jpvt)
     say(f"8192 residual {res:.3e} orthogonality {orth:.3e}")
+    assert res <= 1e-12
+    assert orth <= 1e-12
+
+
+def test_rqrcp_8192_rank512_plus_noise():
+    """8192 x 8192 rank-512 product of Gaussians + 1e-8 N(0,1), b = 64,
+    p = 8, seed 2 (the second input family of the benchmark): the first 512
+    pivots equal the oracle's (tests/golden/c2_lr_trqrcp640.txt; its
+    smallest gap among them is 2.6e-8, no near tie), as do |R_jj| for
+    j < 512; the numerical rank #{j : |R_jj| > 1e-6 |R_00|} is exactly 512;
+    residual and orthogonality at the FP64 bar.  Past the rank the sample
+    holds noise of relative size 1e-8 / ||A|| ~ 4e-13, below the rounding of
+    the first 512 steps, so later pivots are not compared."""
+    say("rqrcp 8192x8192 rank-512 + 1e-8 noise b=64 p=8 seed=2")
+    A, prm = inputs.config_matrix("c2_lr")
+    gj, gg, grd, hdr = load_pivot_golden("c2_lr_trqrcp640.txt")
+    assert any("numerical rank" in h and h.endswith(": 512") for h in hdr)
+    assert trusted_prefix(gg, 512) == 512
+    At = dev(A)
+    nrm = np.linalg.norm(A)
+    del A
+    F, tau, jpvt, info = binding.rq_rqrcp(At, prm["b"], prm["p"], prm["seed"])
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    jp = host(jpvt)
+    assert np.array_equal(jp[:512], gj[:512])
+    assert sorted(jp.tolist()) == list(range(8192))
+    rd = np.abs(host(torch.diagonal(F)))
+    assert np.abs(rd[:512] - grd[:512]).max() <= 1e-12 * nrm
+    rank = int(np.sum(rd > 1e-6 * rd[0]))
+    say(f"c2_lr numerical rank {rank}, |R_511| {rd[511]:.3e} |R_512| {rd[512]:.3e}")
+    assert rank == 512
+    res, orth = gpu_residual_orth(At, F, tau, jpvt)
+    say(f"c2_lr residual {res:.3e} orthogonality {orth:.3e}")
     assert res <= 1e-12
     assert orth <= 1e-12
 
 
 def test_trqrcp_tuxv_c3_full_size():
     """20000 x 10000, sigma_i = 0.9^(i/10), k = 256, b = 64, p = 8, seed 3
-    (the benchmark's TRQRCP/TUXV launch): the first block's pivots against
-    the oracle's TRQRCP(64); on the GPU, the residual of the k factored
-    columns, the orthonormality of U and V, and the truncation error of TUXV
-    within 1.05x of the oracle's (stored in tests/golden, written by
-    make_c3_tuxv_error.py from the oracle) and not below the Eckart-Young
-    optimum."""
+    (the benchmark's TRQRCP/TUXV launch): all 256 pivots and |R_jj| against
+    the oracle's TRQRCP(256) (tests/golden/c3_trqrcp256.txt, smallest gap
+    1e-4); on the GPU, the residual of the k factored columns, the
+    orthonormality of U and V, and the truncation error of TUXV within 1.05x
+    of the oracle's (tests/golden/c3_tuxv_oracle_error.txt) and not below the
+    Eckart-Young optimum."""
     say("trqrcp/tuxv 20000x10000 k=256 b=64 p=8 seed=3")
     A, prm = inputs.config_matrix("c3")
     k, b, p, seed = prm["k"], prm["b"], prm["p"], prm["seed"]
+    gj, gg, grd, _ = load_pivot_golden("c3_trqrcp256.txt")
     At = dev(A)
     nrm = torch.linalg.norm(At).item()
+    del A
     F, tau, jpvt, info = binding.rq_trqrcp(At, k, b, p, seed)
     torch.cuda.synchronize()
     assert int(info.item()) == 0
-    ref = oracle.trqrcp(A, b, b, p, seed=seed)
     jp = host(jpvt)
-    t = trusted_prefix(ref["gaps"], b)
-    assert np.array_equal(jp[:t], ref["jpvt"][:t])
-    assert sorted(jp.tolist()) == list(range(A.shape[1]))
+    t = trusted_prefix(gg, k)
+    assert t == k
+    assert np.array_equal(jp[:k], gj)
+    assert sorted(jp.tolist()) == list(range(At.shape[1]))
+    rd = np.abs(host(torch.diagonal(F[:k, :k])))
+    assert np.abs(rd - grd).max() <= 1e-12 * nrm
     Qk = torch.linalg.householder_product(F[:, :k], tau)
     res = (torch.linalg.norm(At[:, jpvt[:k]] - Qk @ torch.triu(F[:k, :k])) / nrm).item()
     say(f"c3 trqrcp residual {res:.3e}")
     assert res <= 1e-12
+    del Qk, F
     U, s, VT, info = binding.rq_tuxv(At, k, b, p, seed)
     torch.cuda.synchronize()
     assert int(info.item()) == 0
@@ -356,7 +433,7 @@ def test_trqrcp_tuxv_c3_full_size():
     e = (torch.linalg.norm(At - (U * s) @ VT) / nrm).item()
     opt = inputs.optimal_truncation_error(inputs.sigma_power(10000, 0.9, 10.0), k)
     gold = {}
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_tuxv_oracle_error.txt")) as f:
+    with open(os.path.join(GOLDEN, "c3_tuxv_oracle_error.txt")) as f:
         for ln in f:
             if ":" in ln and not ln.startswith("#"):
                 key, val = ln.split(":", 1)
@@ -379,8 +456,9 @@ def test_empty_matrices():
         for fn in (L.rq_rqrcp, L.rq_rsrqrcp):
             jpvt.fill_(-7)
             info.fill_(77)
-            rc = fn(None, m, n, A.data_ptr(), max(1, m), 8, 4, 1, jpvt.data_ptr(), tau.data_ptr(), work.data_ptr(),
-                    work.numel(), info.data_ptr())
+            prec = (binding.RQ_FP64,) if fn is L.rq_rqrcp else ()
+            rc = fn(None, m, n, A.data_ptr(), max(1, m), 8, 4, 1, *prec, jpvt.data_ptr(), tau.data_ptr(),
+                    work.data_ptr(), work.numel(), info.data_ptr())
             assert rc == 0
             torch.cuda.synchronize()
             assert host(jpvt)[:n].tolist() == list(range(n))
@@ -392,7 +470,8 @@ def test_empty_matrices():
     B = torch.full((4, 7), 3.0, dtype=torch.float64, device="cuda").t().contiguous().t()
     work = binding.workspace(binding.RQ_OP_RQRCP, 0, 7, 0, 4, 0, torch.device("cuda"))
     A = torch.empty((0, 7), dtype=torch.float64, device="cuda")
-    rc = L.rq_sketch(None, 0, 7, A.data_ptr(), 1, 4, 5, B.data_ptr(), 4, work.data_ptr(), work.numel())
+    rc = L.rq_sketch(None, 0, 7, A.data_ptr(), 1, 4, 5, binding.RQ_FP64, B.data_ptr(), 4, work.data_ptr(),
+                     work.numel())
     assert rc == 0
     assert np.all(host(B) == 0.0)
 
