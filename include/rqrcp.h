@@ -140,6 +140,28 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
 int rq_rqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p, uint64_t seed,
              int32_t precision, int64_t* jpvt, double* tau, void* work, size_t work_bytes, int32_t* info);
 
+/*
+ * RQRCP without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  The factorization is rq_rqrcp's (same kernels,
+ * bitwise the same results), with every kernel on the caller's stream (no
+ * look-ahead stream), and its scratch is a static device array of
+ * RQ_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends.  The call allocates nothing.  Calls on one device
+ * share that array: calls that overlap on one device (different streams, or
+ * host threads without ordering) race and give wrong results; calls ordered
+ * on one stream are fine (each clears what must start at zero).
+ * Sizes whose rq_workspace_bytes(RQ_OP_RQRCP, ...) exceeds the array are
+ * rejected with RQ_ERR_SCRATCH_TOO_SMALL before anything is enqueued
+ * (8192 x 8192 with b = 64, p = 8 needs 91 MiB and fits).
+ * Arguments: as rq_rqrcp without work and work_bytes: 1 stream, 2 m, 3 n,
+ * 4 A, 5 lda, 6 b, 7 p, 8 seed, 9 precision, 10 jpvt, 11 tau, 12 info.
+ */
+#define RQ_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+#define RQ_ERR_SCRATCH_TOO_SMALL 2002
+int rq_rqrcp_noalloc(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p,
+                     uint64_t seed, int32_t precision, int64_t* jpvt, double* tau, int32_t* info);
+
 /* As rq_rqrcp in FP64 with a caller-supplied compression matrix Omega
  * (l x m, column-major, leading dimension ldo >= l, device; a test hook):
  * arguments 1-7 as rq_rqrcp, 8 Omega, 9 ldo, 10 jpvt, 11 tau, 12 work,

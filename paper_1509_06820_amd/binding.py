@@ -35,6 +35,8 @@ _SIGS = {
                            ctypes.c_int),
     "rq_rqrcp": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_i32, _c_p, _c_p, _c_p, _c_sz, _c_p],
                  ctypes.c_int),
+    "rq_rqrcp_noalloc": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_i32, _c_p, _c_p, _c_p],
+                         ctypes.c_int),
     "rq_rqrcp_omega": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_p, _c_p, _c_p, _c_sz,
                         _c_p], ctypes.c_int),
     "rq_rsrqrcp": ([_c_p, _c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_u64, _c_p, _c_p, _c_p, _c_sz, _c_p],
@@ -165,6 +167,25 @@ def rq_rqrcp(A, b, p, seed=0, Omega=None, work=None, stream=None, precision=RQ_F
         rc = L.rq_rqrcp_omega(_stream(stream), m, n, _ptr(F), _ld(F), b, p, _ptr(Om), _ld(Om), _ptr(jpvt), _ptr(tau),
                               _ptr(work), work.numel(), _ptr(info))
         _check(rc, "rq_rqrcp_omega")
+    return F, tau, jpvt, info
+
+
+RQ_NOALLOC_SCRATCH_BYTES = 96 << 20
+RQ_ERR_SCRATCH_TOO_SMALL = 2002
+
+
+def rq_rqrcp_noalloc(A, b, p, seed=0, stream=None, precision=RQ_FP64):
+    """rq_rqrcp without a workspace (the library's static per-device scratch).
+    Returns (F, tau, jpvt, info); A is not modified."""
+    F = fortran(A).clone()
+    m, n = F.shape
+    dev = F.device
+    jpvt = torch.empty(n, dtype=torch.int64, device=dev)
+    tau = torch.empty(min(m, n), dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    rc = load().rq_rqrcp_noalloc(_stream(stream), m, n, _ptr(F), _ld(F), b, p, seed, _prec(precision), _ptr(jpvt),
+                                 _ptr(tau), _ptr(info))
+    _check(rc, "rq_rqrcp_noalloc")
     return F, tau, jpvt, info
 
 

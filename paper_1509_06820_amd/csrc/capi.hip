@@ -769,6 +769,29 @@ int check_common(int64_t m, int64_t n, int64_t lda, int b, int p, int im, int in
   return 0;
 }
 
+// ------------------------------------------------------------------ allocation-free RQRCP
+// The workspace of rq_rqrcp_noalloc: one static array per device, its device
+// address looked up once per device (in host code the array's name is only
+// a stand-in; kernels get the looked-up address).
+static __device__ __align__(256) unsigned char scratch[RQ_NOALLOC_SCRATCH_BYTES];
+
+int scratch_address(void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = 0;
+  RQ_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return RQ_ERR_HIP_BASE + (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    RQ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return RQ_ERR_HIP_BASE + (int)hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return 0;
+}
+
 }  // namespace
 }  // namespace rq
 
@@ -861,6 +884,23 @@ int rq_rqrcp(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t
   if (m == 0 || n == 0) return empty_result((hipStream_t)stream, n, jpvt, info);
   return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work, work_bytes, info,
                      true, false, precision, 13);
+}
+
+int rq_rqrcp_noalloc(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p,
+                     uint64_t seed, int32_t precision, int64_t* jpvt, double* tau, int32_t* info) {
+  int rc = check_common(m, n, lda, b, p, 2, 3, 5, 6, 7);
+  if (rc) return rc;
+  if (precision < RQ_FP64 || precision > RQ_MIXED_BF16) return -9;
+  if (m == 0 || n == 0) return empty_result((hipStream_t)stream, n, jpvt, info);
+  size_t need = 0;
+  rc = rq_workspace_bytes(RQ_OP_RQRCP, m, n, 0, b, p, precision, &need);
+  if (rc) return rc;
+  if (need > RQ_NOALLOC_SCRATCH_BYTES) return RQ_ERR_SCRATCH_TOO_SMALL;
+  void* work = nullptr;
+  RQ_TRY(scratch_address(&work));
+  // everything on the caller's stream: no second stream and no events
+  return factor_impl((hipStream_t)stream, m, n, A, lda, b, p, seed, nullptr, 0, jpvt, tau, work,
+                     RQ_NOALLOC_SCRATCH_BYTES, info, true, false, precision, 0, false);
 }
 
 int rq_rqrcp_omega(void* stream, int64_t m, int64_t n, double* A, int64_t lda, int32_t b, int32_t p,

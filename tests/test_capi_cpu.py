@@ -200,3 +200,16 @@ def test_autotune_host_logic(tmp_path):
     path.write_text(json.dumps({autotune.key(shapes, 16, 8, 0): {"b": 8, "tile": 1, "ms": 1.0}}))
     assert autotune.lookup(shapes, 16, 8, 0, str(path))["tile"] == 1
     assert autotune.lookup(shapes, 32, 8, 0, str(path)) is None
+
+
+def test_noalloc_rejects_oversize_before_any_launch(lib):
+    """rq_rqrcp_noalloc checks its arguments and the size of its static
+    scratch on the host: a factorization that needs more than
+    RQ_NOALLOC_SCRATCH_BYTES is rejected with RQ_ERR_SCRATCH_TOO_SMALL, bad
+    arguments with -i, neither touching a GPU."""
+    null = ctypes.c_void_p(0)
+    m, n, b, p = 30000, 20000, 64, 64
+    assert binding.rq_workspace_bytes(binding.RQ_OP_RQRCP, m, n, 0, b, p) > binding.RQ_NOALLOC_SCRATCH_BYTES
+    assert lib.rq_rqrcp_noalloc(null, m, n, null, m, b, p, 1, 0, null, null, null) == binding.RQ_ERR_SCRATCH_TOO_SMALL
+    assert lib.rq_rqrcp_noalloc(null, -1, 4, null, 1, 8, 0, 1, 0, null, null, null) == -2
+    assert lib.rq_rqrcp_noalloc(null, 4, 4, null, 4, 8, 0, 1, 7, null, null, null) == -9
