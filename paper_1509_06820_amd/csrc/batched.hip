@@ -51,6 +51,8 @@ constexpr int BT_W = BT_T / WAVE;
 constexpr int BT_NMAX = 8192;   // sample columns (norms in LDS)
 constexpr int BT_KMAX = 64;
 constexpr int BT_LD = BT_KMAX + 1;  // LDS pitch of the small matrices
+// dynamic LDS of the sample QRCP: nmax norms (double) and nmax reference norms (float)
+inline size_t sample_lds_bytes(int64_t nmax) { return (size_t)((std::max<int64_t>(nmax, 1) * 12 + 15) / 16 * 16); }
 
 // Per-matrix state of a batched run (device resident, built by the plan).
 struct BMat {
@@ -88,14 +90,23 @@ __device__ __forceinline__ double wsum(double v) { return wave_sum_x(v); }
 
 // ---------------------------------------------------------------- sample QRCP
 // Alg. 1 for b steps on the l x nJ sample S (ld l, l <= 64) of one matrix:
-// one workgroup, one wave per column at a time (lane = row).  Trailing norms
-// are recomputed from the updated columns at every step (as the oracle
-// does), ties go to the lowest position, a NaN norm never wins; swaps are
-// sequential (step t exchanges positions t and p) and are applied to the
-// matrix's column order jp at positions i0 + t.
+// one workgroup, a wave takes four columns at a time (lane = row; the four
+// inner products with the reflector are independent reductions).  Trailing
+// norms start exact and are downdated after each step with the column's new
+// row-t entry (the reflector keeps the norm of rows >= t), recomputed
+// exactly once a norm has fallen below a tenth of its last exact value (as
+// the single-matrix kernel does: relative error about 64 eps * 10); ties go
+// to the lowest position, a NaN norm never wins; swaps are sequential (step
+// t exchanges positions t and p) and are applied to the matrix's column
+// order jp at positions i0 + t.
+// Dynamic LDS: nmax doubles (norms) then nmax floats (the last exact norm of
+// each column, used only by the recomputation test); nmax = the batch's
+// largest n, so small matrices leave room for more workgroups per CU.
 __global__ void __launch_bounds__(BT_T) bt_sample_qrcp_kernel(BMat* __restrict__ mats, int count, int l, int b,
-                                                              int64_t i0) {
-  __shared__ double nu[BT_NMAX];
+                                                              int64_t i0, int64_t nmax) {
+  extern __shared__ double bt_norms[];
+  double* nu = bt_norms;
+  float* nuref = reinterpret_cast<float*>(bt_norms + nmax);
   __shared__ double v[64];
   __shared__ double rv[BT_W];
   __shared__ int rp[BT_W];
@@ -111,7 +122,10 @@ __global__ void __launch_bounds__(BT_T) bt_sample_qrcp_kernel(BMat* __restrict__
     for (int64_t c = w; c < nJ; c += BT_W) {
       const double x = inrow ? S[lane + c * l] : 0.0;
       const double s2 = wsum(x * x);
-      if (lane == 0) nu[c] = s2;
+      if (lane == 0) {
+        nu[c] = s2;
+        nuref[c] = (float)s2;
+      }
     }
     __syncthreads();
     for (int t = 0; t < b; ++t) {
@@ -154,6 +168,9 @@ __global__ void __launch_bounds__(BT_T) bt_sample_qrcp_kernel(BMat* __restrict__
             const double tmp = nu[t];
             nu[t] = nu[p];
             nu[p] = tmp;
+            const float tr = nuref[t];
+            nuref[t] = nuref[p];
+            nuref[p] = tr;
           }
           xt = xp;
         }
@@ -178,14 +195,34 @@ __global__ void __launch_bounds__(BT_T) bt_sample_qrcp_kernel(BMat* __restrict__
       __syncthreads();
       const double tau = s_tau;
       const double vl = inrow ? v[lane] : 0.0;
-      // apply to the columns right of t and recompute their trailing norms (rows > t)
-      for (int64_t c = t + 1 + w; c < nJ; c += BT_W) {
-        double x = inrow ? S[lane + c * l] : 0.0;
-        const double d = tau * wsum(vl * x);
-        x = fma(-d, vl, x);
-        if (inrow && tau != 0.0) S[lane + c * l] = x;
-        const double s2 = wsum((lane > t && inrow) ? x * x : 0.0);
-        if (lane == 0) nu[c] = s2;
+      // apply to the columns right of t, four per wave at a time, and
+      // downdate their trailing norms (rows > t)
+      constexpr int CPW = 4;
+      for (int64_t c0 = t + 1 + CPW * w; c0 < nJ; c0 += CPW * BT_W) {
+        double x[CPW], d[CPW];
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) x[j] = (inrow && c0 + j < nJ) ? S[lane + (c0 + j) * l] : 0.0;
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) d[j] = wsum(vl * x[j]);
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+          x[j] = fma(-tau * d[j], vl, x[j]);
+          if (inrow && c0 + j < nJ && tau != 0.0) S[lane + (c0 + j) * l] = x[j];
+        }
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+          const int64_t c = c0 + j;
+          if (c < nJ) {
+            const double xt = __shfl(x[j], t, WAVE);  // the new row-t entry
+            double nn = nu[c] - xt * xt;
+            const float ref = nuref[c];
+            if (!(nn >= 0.1 * (double)ref)) {
+              nn = wsum((lane > t && inrow) ? x[j] * x[j] : 0.0);
+              if (lane == 0) nuref[c] = (float)nn;
+            }
+            if (lane == 0) nu[c] = nn;
+          }
+        }
       }
       if (tid == 0) {
         // sequential swap in the column order
@@ -371,76 +408,103 @@ __global__ void __launch_bounds__(256) bt_w11_kernel(BMat* __restrict__ mats, in
 }
 
 // ---------------------------------------------------------------- SVD of X
-// One-sided Jacobi on the k x k X in LDS (cyclic sweeps over pairs i < j,
-// the rotation of the single-matrix SVD), V accumulated; singular values in
-// descending order (ties by index), Ux = X V / sigma, Vx = V.
-__global__ void __launch_bounds__(256) bt_svd_kernel(BMat* __restrict__ mats, int count, int k) {
+// One-sided Jacobi on the k x k X in LDS (the rotation of the single-matrix
+// SVD over the round-robin pairs of each sweep), V accumulated; singular
+// values in descending order (ties by index), Ux = X V / sigma, Vx = V.
+// A pair is rotated by a half wave (32 lanes, one row each) when k <= 32,
+// by a whole wave otherwise, so a round's pairs run 16 or 8 at a time
+// across the eight waves.
+template <bool HALF>
+__device__ __forceinline__ double pair_sum(double v) {
+  const int lane = (int)(threadIdx.x & (WAVE - 1));
+  v += xchg_d<1>(v, lane);
+  v += xchg_d<2>(v, lane);
+  v += xchg_d<4>(v, lane);
+  v += xchg_d<8>(v, lane);
+  v += xchg_d<16>(v, lane);
+  if (!HALF) v += xchg_d<32>(v, lane);
+  return v;
+}
+
+template <bool HALF>
+__device__ void svd_sweeps(double* X, double* V, int k, int* s_rot, bool& converged) {
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+  const int row = HALF ? (lane & 31) : lane;
+  const int slot = HALF ? 2 * w + (lane >> 5) : w;
+  constexpr int NSLOT = HALF ? 2 * BT_W : BT_W;
+  const int kk = k + (k & 1);
+  converged = kk <= 1;
+  for (int sweep = 0; sweep < 60 && kk > 1; ++sweep) {
+    if (tid == 0) *s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < kk - 1; ++r) {
+      for (int base = 0; base < kk / 2; base += NSLOT) {
+        // every lane takes part in the reductions (zeros for a missing pair)
+        const int idx = base + slot;
+        int p = 0, q = 0;
+        if (idx == 0) { p = kk - 1; q = r; }
+        else { p = (r + idx) % (kk - 1); q = (r - idx + kk - 1) % (kk - 1); }
+        const bool valid = idx < kk / 2 && p < k && q < k;
+        const int i = min(p, q), j = max(p, q);
+        const bool in = valid && row < k;
+        const double xi = in ? X[row + i * BT_LD] : 0.0;
+        const double xj = in ? X[row + j * BT_LD] : 0.0;
+        const double sa = pair_sum<HALF>(xi * xi), sb = pair_sum<HALF>(xj * xj), sgm = pair_sum<HALF>(xi * xj);
+        if (valid && sgm != 0.0 && fabs(sgm) > 1e-15 * sqrt(sa * sb)) {
+          const double z = (sb - sa) / (2.0 * sgm);
+          const double t = ((z >= 0.0) ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn_ = cs * t;
+          if (in) {
+            const double vi = V[row + i * BT_LD], vj = V[row + j * BT_LD];
+            X[row + i * BT_LD] = cs * xi - sn_ * xj;
+            X[row + j * BT_LD] = sn_ * xi + cs * xj;
+            V[row + i * BT_LD] = cs * vi - sn_ * vj;
+            V[row + j * BT_LD] = sn_ * vi + cs * vj;
+          }
+          if (row == 0) *s_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int rot = *s_rot;
+    __syncthreads();
+    if (!rot) { converged = true; break; }
+  }
+}
+
+__global__ void __launch_bounds__(BT_T) bt_svd_kernel(BMat* __restrict__ mats, int count, int k) {
   __shared__ double X[BT_KMAX * BT_LD];
   __shared__ double V[BT_KMAX * BT_LD];
   __shared__ double sn[BT_KMAX];
   __shared__ int s_rot;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
-  constexpr int NW = 256 / WAVE;
   for (int mi = blockIdx.x; mi < count; mi += gridDim.x) {
     BMat& M = mats[mi];
-    for (int e = tid; e < k * k; e += 256) {
+    for (int e = tid; e < k * k; e += BT_T) {
       const int j = e / k, i = e - j * k;
       X[i + j * BT_LD] = M.X[i + j * k];
       V[i + j * BT_LD] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    const int kk = k + (k & 1);
-    bool converged = false;
-    for (int sweep = 0; sweep < 60 && kk > 1; ++sweep) {
-      if (tid == 0) s_rot = 0;
-      __syncthreads();
-      // round-robin rounds: the kk/2 pairs of a round touch disjoint columns
-      for (int r = 0; r < kk - 1; ++r) {
-        for (int idx = w; idx < kk / 2; idx += NW) {
-          int p, q;
-          if (idx == 0) { p = kk - 1; q = r; }
-          else { p = (r + idx) % (kk - 1); q = (r - idx + kk - 1) % (kk - 1); }
-          if (p >= k || q >= k) continue;
-          const int i = min(p, q), j = max(p, q);
-          const double xi = (lane < k) ? X[lane + i * BT_LD] : 0.0;
-          const double xj = (lane < k) ? X[lane + j * BT_LD] : 0.0;
-          const double sa = wsum(xi * xi), sb = wsum(xj * xj), sgm = wsum(xi * xj);
-          if (sgm != 0.0 && fabs(sgm) > 1e-15 * sqrt(sa * sb)) {
-            const double z = (sb - sa) / (2.0 * sgm);
-            const double t = ((z >= 0.0) ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-            const double cs = 1.0 / sqrt(1.0 + t * t), sn_ = cs * t;
-            if (lane < k) {
-              const double vi = V[lane + i * BT_LD], vj = V[lane + j * BT_LD];
-              X[lane + i * BT_LD] = cs * xi - sn_ * xj;
-              X[lane + j * BT_LD] = sn_ * xi + cs * xj;
-              V[lane + i * BT_LD] = cs * vi - sn_ * vj;
-              V[lane + j * BT_LD] = sn_ * vi + cs * vj;
-            }
-            if (lane == 0) s_rot = 1;
-          }
-        }
-        __syncthreads();
-      }
-      const int rot = s_rot;
-      __syncthreads();
-      if (!rot) { converged = true; break; }
-    }
-    if (!converged && kk > 1 && tid == 0) atomicCAS(M.info, 0, -2);
-    for (int j = w; j < k; j += NW) {
+    bool converged;
+    if (k <= 32) svd_sweeps<true>(X, V, k, &s_rot, converged);
+    else svd_sweeps<false>(X, V, k, &s_rot, converged);
+    if (!converged && tid == 0) atomicCAS(M.info, 0, -2);
+    for (int j = w; j < k; j += BT_W) {
       const double x = (lane < k) ? X[lane + j * BT_LD] : 0.0;
       const double s = wsum(x * x);
       if (lane == 0) sn[j] = sqrt(s);
     }
     __syncthreads();
-    for (int j = tid; j < k; j += 256) {
+    for (int j = tid; j < k; j += BT_T) {
       const double v = sn[j];
       int rank = 0;
       for (int i = 0; i < k; ++i) rank += (sn[i] > v || (sn[i] == v && i < j)) ? 1 : 0;
       M.sigma[rank] = v;
       const double inv = (v > 0.0) ? 1.0 / v : 0.0;
-      for (int row = 0; row < k; ++row) {
-        M.Ux[row + rank * k] = X[row + j * BT_LD] * inv;
-        M.Vx[row + rank * k] = V[row + j * BT_LD];
+      for (int rw = 0; rw < k; ++rw) {
+        M.Ux[rw + rank * k] = X[rw + j * BT_LD] * inv;
+        M.Vx[rw + rank * k] = V[rw + j * BT_LD];
       }
     }
     __syncthreads();
@@ -698,6 +762,12 @@ int rq_batch_plan_create(const rq_batch_matrix* items, int32_t count, int64_t k,
   if (!cv.ok) { delete plan; return -9; }
   plan->max_n = max_n;
   plan->max_m = max_m;
+  if (sample_lds_bytes(max_n) > 65536 &&
+      hipFuncSetAttribute((const void*)bt_sample_qrcp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)sample_lds_bytes(max_n)) != hipSuccess) {
+    delete plan;
+    return -9;
+  }
   plan->max_mb = max_m * b;
   plan->mats = (BMat*)(B.dev + B.put_raw(B.mats.data(), sizeof(BMat) * count));
   const OmegaJob* djobs = (const OmegaJob*)(B.dev + B.put_raw(jobs.data(), sizeof(OmegaJob) * count));
@@ -820,7 +890,8 @@ int rq_tuxv_batched(void* stream, const rq_batch_plan* plan) {
         RQ_TRY_RAW(launch_gemm_grouped(s, op.cfg, op.ta, op.tb, op.f32, op.probs, op.tiles, op.ntiles, plan->wgs));
         break;
       case BatchOp::SQRCP:
-        hipLaunchKernelGGL(bt_sample_qrcp_kernel, dim3(mg), dim3(BT_T), 0, s, plan->mats, count, l, b, op.i0);
+        hipLaunchKernelGGL(bt_sample_qrcp_kernel, dim3(mg), dim3(BT_T), sample_lds_bytes(plan->max_n), s,
+                           plan->mats, count, l, b, op.i0, plan->max_n);
         break;
       case BatchOp::GATHER: {
         const int64_t e = (op.mode == GATHER_PANEL) ? plan->max_mb : (op.mode == GATHER_ROWS) ? plan->max_n * b : k;
@@ -836,7 +907,7 @@ int rq_tuxv_batched(void* stream, const rq_batch_plan* plan) {
         hipLaunchKernelGGL(bt_w11_kernel, dim3(mg), dim3(256), 0, s, plan->mats, count, l, b, op.i0);
         break;
       case BatchOp::SVD:
-        hipLaunchKernelGGL(bt_svd_kernel, dim3(mg), dim3(256), 0, s, plan->mats, count, k);
+        hipLaunchKernelGGL(bt_svd_kernel, dim3(mg), dim3(BT_T), 0, s, plan->mats, count, k);
         break;
     }
     RQ_HIP(hipGetLastError());
