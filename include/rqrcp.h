@@ -341,7 +341,7 @@ int rq_small_svd(void* stream, int32_t k, double* X, int64_t ldx, double* U, int
  *   precision: RQ_FP64 or RQ_MIXED (the sketch, Q_J^T A and A V on the FP32
  *   matrix cores).  tile: the output tile of the grouped products
  *   (RQ_TILE_64x64, RQ_TILE_32x32, RQ_TILE_128x64).
- *   Limits: 1 <= k <= 64, b divides k, b + p <= 64, k <= m_i, k <= n_i <= 4096.
+ *   Limits: 1 <= k <= 64, b divides k, b + p <= 64, k <= m_i, k <= n_i <= 8192.
  *   info (per matrix, optional): 0, j > 0 (non-finite sample norm at pivot
  *   step j), -2 (the SVD of X did not converge), -4 (a CholeskyQR pass met a
  *   non-positive pivot: numerically rank-deficient columns; the result is

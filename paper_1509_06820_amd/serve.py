@@ -48,7 +48,7 @@ class Request:
     @property
     def batched(self):
         m, n = self.A.shape
-        return self.k <= BATCH_KMAX and n <= 4096 and self.precision != binding.RQ_MIXED_BF16
+        return self.k <= BATCH_KMAX and n <= 8192 and self.precision != binding.RQ_MIXED_BF16
 
 
 def block_size(k, batched):
