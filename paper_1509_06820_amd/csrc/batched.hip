@@ -51,6 +51,8 @@ constexpr int BT_W = BT_T / WAVE;
 constexpr int BT_NMAX = 8192;   // sample columns (norms in LDS)
 constexpr int BT_KMAX = 64;
 constexpr int BT_LD = BT_KMAX + 1;  // LDS pitch of the small matrices
+// rows of the batched sample: l rounded up to a multiple of 8 (the rows past l are zero)
+__host__ __device__ inline int sample_rows(int l) { return (l + 7) & ~7; }
 // dynamic LDS of the sample QRCP: nmax norms (double) and nmax reference norms (float)
 inline size_t sample_lds_bytes(int64_t nmax) { return (size_t)((std::max<int64_t>(nmax, 1) * 12 + 15) / 16 * 16); }
 
@@ -65,8 +67,8 @@ struct BMat {
   int64_t ldvt;
   int64_t* jpvt_out;  // optional: the k pivots
   uint64_t seed;
-  double* om;     // l x m, ld l
-  double* smp;    // l x n, ld l
+  double* om;     // Omega^T: m x l, ld m (Omega(r, c) at om[c + r m])
+  double* smp;    // sample, row-major: S(r, c) at smp[c + r n], rows padded to a multiple of 8 (zero past l)
   int* jp;        // n: original column at each position
   int* piv;       // b: swap partners of the current block (local positions)
   double* Q;      // m x k, ld m
@@ -89,25 +91,31 @@ struct BMat {
 __device__ __forceinline__ double wsum(double v) { return wave_sum_x(v); }
 
 // ---------------------------------------------------------------- sample QRCP
-// Alg. 1 for b steps on the l x nJ sample S (ld l, l <= 64) of one matrix:
-// one workgroup, a wave takes four columns at a time (lane = row; the four
-// inner products with the reflector are independent reductions).  Trailing
-// norms start exact and are downdated after each step with the column's new
+// Alg. 1 for b steps on the l x nJ sample S of one matrix (row-major: row r
+// of the columns i0.. at smp + i0 + r n), one workgroup per matrix and one
+// thread per column: a thread holds its column's l rows in registers
+// (LMAX >= l), so the inner product with the reflector and the update need
+// no cross-lane reduction and the rows of consecutive columns are read and
+// written coalesced.  Rows above t are read and written back unchanged (the
+// reflector is zero there), which keeps every register index a constant.  Trailing norms
+// start exact and are downdated after each step with the column's new
 // row-t entry (the reflector keeps the norm of rows >= t), recomputed
-// exactly once a norm has fallen below a tenth of its last exact value (as
-// the single-matrix kernel does: relative error about 64 eps * 10); ties go
-// to the lowest position, a NaN norm never wins; swaps are sequential (step
-// t exchanges positions t and p) and are applied to the matrix's column
-// order jp at positions i0 + t.
+// exactly once a norm has fallen below a tenth of its last exact value
+// (as the single-matrix kernel does: relative error about 64 eps * 10);
+// ties go to the lowest position, a NaN norm never wins; swaps are
+// sequential (step t exchanges positions t and p) and are applied to the
+// matrix's column order jp at positions i0 + t.
 // Dynamic LDS: nmax doubles (norms) then nmax floats (the last exact norm of
 // each column, used only by the recomputation test); nmax = the batch's
 // largest n, so small matrices leave room for more workgroups per CU.
+// LMAX = sample_rows(l): the padding rows are zero, so no row needs a test.
+template <int LMAX>
 __global__ void __launch_bounds__(BT_T) bt_sample_qrcp_kernel(BMat* __restrict__ mats, int count, int l, int b,
                                                               int64_t i0, int64_t nmax) {
   extern __shared__ double bt_norms[];
   double* nu = bt_norms;
   float* nuref = reinterpret_cast<float*>(bt_norms + nmax);
-  __shared__ double v[64];
+  __shared__ double v[LMAX];
   __shared__ double rv[BT_W];
   __shared__ int rp[BT_W];
   __shared__ double s_tau;
@@ -115,17 +123,19 @@ __global__ void __launch_bounds__(BT_T) bt_sample_qrcp_kernel(BMat* __restrict__
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
   for (int mi = blockIdx.x; mi < count; mi += gridDim.x) {
     BMat& M = mats[mi];
-    const int64_t nJ = M.n - i0;
-    double* S = M.smp + i0 * l;
-    const bool inrow = lane < l;
+    const int64_t n = M.n, nJ = n - i0;
+    const int n32 = (int)n;  // l n < 2^31
+    double* S = M.smp + i0;  // S(r, c) at S[c + r n]
     // initial trailing norms (all rows)
-    for (int64_t c = w; c < nJ; c += BT_W) {
-      const double x = inrow ? S[lane + c * l] : 0.0;
-      const double s2 = wsum(x * x);
-      if (lane == 0) {
-        nu[c] = s2;
-        nuref[c] = (float)s2;
+    for (int c = tid; c < (int)nJ; c += BT_T) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int r = 0; r < LMAX; ++r) {
+        const double x = S[c + r * n32];
+        s2 = fma(x, x, s2);
       }
+      nu[c] = s2;
+      nuref[c] = (float)s2;
     }
     __syncthreads();
     for (int t = 0; t < b; ++t) {
@@ -156,13 +166,14 @@ __global__ void __launch_bounds__(BT_T) bt_sample_qrcp_kernel(BMat* __restrict__
           if (ov > fv || (ov == fv && op < fp)) { fv = ov; fp = op; }
         }
         const int p = (fp == INT_MAX) ? t : fp;
-        // swap columns t and p of the sample and their norms
-        double xt = inrow ? S[lane + (int64_t)t * l] : 0.0;
-        double xp = inrow ? S[lane + (int64_t)p * l] : 0.0;
+        // swap columns t and p of the sample (lane = row) and their norms
+        const bool inrow = lane < l;
+        double xt = inrow ? S[t + lane * n] : 0.0;
+        double xp = inrow ? S[p + lane * n] : 0.0;
         if (p != t) {
           if (inrow) {
-            S[lane + (int64_t)t * l] = xp;
-            S[lane + (int64_t)p * l] = xt;
+            S[t + lane * n] = xp;
+            S[p + lane * n] = xt;
           }
           if (lane == 0) {
             const double tmp = nu[t];
@@ -184,8 +195,8 @@ __global__ void __launch_bounds__(BT_T) bt_sample_qrcp_kernel(BMat* __restrict__
           tau = (beta - alpha) / beta;
           scal = 1.0 / (alpha - beta);
         }
-        v[lane] = (lane < t) ? 0.0 : ((lane == t) ? 1.0 : xt * scal);
-        if (inrow) S[lane + (int64_t)t * l] = (lane < t) ? xt : ((lane == t) ? beta : 0.0);
+        if (lane < LMAX) v[lane] = (lane < t || !inrow) ? 0.0 : ((lane == t) ? 1.0 : xt * scal);
+        if (inrow) S[t + lane * n] = (lane < t) ? xt : ((lane == t) ? beta : 0.0);
         if (lane == 0) {
           s_tau = tau;
           s_p = p;
@@ -194,35 +205,43 @@ __global__ void __launch_bounds__(BT_T) bt_sample_qrcp_kernel(BMat* __restrict__
       }
       __syncthreads();
       const double tau = s_tau;
-      const double vl = inrow ? v[lane] : 0.0;
-      // apply to the columns right of t, four per wave at a time, and
-      // downdate their trailing norms (rows > t)
-      constexpr int CPW = 4;
-      for (int64_t c0 = t + 1 + CPW * w; c0 < nJ; c0 += CPW * BT_W) {
-        double x[CPW], d[CPW];
+      // apply to the columns right of t (rows t..l-1) and downdate their
+      // trailing norms (rows > t) with the new row-t entry x_t - d (v_t = 1)
+      for (int c = t + 1 + tid; c < (int)nJ; c += BT_T) {
+        // one running 32-bit offset per pass (recomputed for the store pass,
+        // so that no per-row address stays live beside the column)
+        double x[LMAX];
+        {
+          int off = c;
 #pragma unroll
-        for (int j = 0; j < CPW; ++j) x[j] = (inrow && c0 + j < nJ) ? S[lane + (c0 + j) * l] : 0.0;
-#pragma unroll
-        for (int j = 0; j < CPW; ++j) d[j] = wsum(vl * x[j]);
-#pragma unroll
-        for (int j = 0; j < CPW; ++j) {
-          x[j] = fma(-tau * d[j], vl, x[j]);
-          if (inrow && c0 + j < nJ && tau != 0.0) S[lane + (c0 + j) * l] = x[j];
+          for (int r = 0; r < LMAX; ++r, off += n32) x[r] = S[off];
         }
+        const double xt0 = S[c + t * n32];
+        // v is read from LDS (one address for the whole workgroup) rather
+        // than held in registers next to the column
+        double dsum = 0.0;
 #pragma unroll
-        for (int j = 0; j < CPW; ++j) {
-          const int64_t c = c0 + j;
-          if (c < nJ) {
-            const double xt = __shfl(x[j], t, WAVE);  // the new row-t entry
-            double nn = nu[c] - xt * xt;
-            const float ref = nuref[c];
-            if (!(nn >= 0.1 * (double)ref)) {
-              nn = wsum((lane > t && inrow) ? x[j] * x[j] : 0.0);
-              if (lane == 0) nuref[c] = (float)nn;
-            }
-            if (lane == 0) nu[c] = nn;
+        for (int r = 0; r < LMAX; ++r) dsum = fma(v[r], x[r], dsum);
+        const double d = tau * dsum;
+        if (tau != 0.0) {
+          int off = c;
+          asm volatile("" : "+v"(off));
+#pragma unroll
+          for (int r = 0; r < LMAX; ++r, off += n32) {
+            x[r] = fma(-d, v[r], x[r]);
+            S[off] = x[r];
           }
         }
+        const double xt = xt0 - d;
+        double nn = nu[c] - xt * xt;
+        if (!(nn >= 0.1 * (double)nuref[c])) {
+          double s2 = 0.0;
+#pragma unroll
+          for (int r = 0; r < LMAX; ++r) s2 = (r > t) ? fma(x[r], x[r], s2) : s2;
+          nn = s2;
+          nuref[c] = (float)nn;
+        }
+        nu[c] = nn;
       }
       if (tid == 0) {
         // sequential swap in the column order
@@ -267,12 +286,15 @@ __global__ void __launch_bounds__(256) bt_gather_kernel(BMat* __restrict__ mats,
   }
 }
 
-// jp = identity, info = 0
-__global__ void __launch_bounds__(256) bt_init_kernel(BMat* __restrict__ mats, int count) {
+// jp = identity, info = 0, the sample's padding rows l..L-1 zero
+__global__ void __launch_bounds__(256) bt_init_kernel(BMat* __restrict__ mats, int count, int l) {
+  const int L = sample_rows(l);
   for (int mi = blockIdx.y; mi < count; mi += gridDim.y) {
     const BMat& M = mats[mi];
-    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < M.n; c += (int64_t)gridDim.x * 256)
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < M.n; c += (int64_t)gridDim.x * 256) {
       M.jp[c] = (int)c;
+      for (int r = l; r < L; ++r) M.smp[c + r * M.n] = 0.0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) *M.info = 0;
   }
 }
@@ -391,13 +413,13 @@ __global__ void __launch_bounds__(256) bt_w11_kernel(BMat* __restrict__ mats, in
   const int tid = threadIdx.x;
   for (int mi = blockIdx.x; mi < count; mi += gridDim.x) {
     const BMat& M = mats[mi];
-    const double* S = M.smp + i0 * l;
+    const double* S = M.smp + i0;  // S(i, j) at S[j + i n]
     // thread i < b computes row i of W11, left to right
     if (tid < b) {
       const int i = tid;
       for (int j = 0; j < b; ++j) {
         const double d = M.Rg[j + (int64_t)j * b];
-        double s = (i <= j) ? S[i + (int64_t)j * l] : 0.0;
+        double s = (i <= j) ? S[j + (int64_t)i * M.n] : 0.0;
         for (int q = 0; q < j; ++q) s -= W[i + q * BT_LD] * M.Rg[q + (int64_t)j * b];
         W[i + j * BT_LD] = (d == 0.0) ? 0.0 : s / d;
       }
@@ -451,9 +473,8 @@ __device__ void svd_sweeps(double* X, double* V, int k, int* s_rot, bool& conver
         const double xj = in ? X[row + j * BT_LD] : 0.0;
         const double sa = pair_sum<HALF>(xi * xi), sb = pair_sum<HALF>(xj * xj), sgm = pair_sum<HALF>(xi * xj);
         if (valid && sgm != 0.0 && fabs(sgm) > 1e-15 * sqrt(sa * sb)) {
-          const double z = (sb - sa) / (2.0 * sgm);
-          const double t = ((z >= 0.0) ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn_ = cs * t;
+          double cs, sn_;
+          jacobi_rotation(sa, sb, sgm, cs, sn_);
           if (in) {
             const double vi = V[row + i * BT_LD], vj = V[row + j * BT_LD];
             X[row + i * BT_LD] = cs * xi - sn_ * xj;
@@ -567,7 +588,7 @@ int check_items(const rq_batch_matrix* items, int32_t count, int64_t k, int32_t 
 // Per-matrix buffers, carved in this order from the matrix's region.
 void carve_matrix(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int l, BMat& M) {
   M.om = cv.take<double>((size_t)l * m);
-  M.smp = cv.take<double>((size_t)l * n);
+  M.smp = cv.take<double>((size_t)sample_rows(l) * n);
   M.jp = cv.take<int>((size_t)n);
   M.piv = cv.take<int>((size_t)b);
   M.Q = cv.take<double>((size_t)m * k);
@@ -637,10 +658,23 @@ struct Builder {
   // with an empty output contributes no tile)
   template <class F>
   void gemm(bool ta, bool tb, bool f32, F spec) {
-    int bm, bn;
-    grouped_tile_shape(plan.cfg, &bm, &bn);
     std::vector<GroupedGemm> probs(plan.count);
     std::vector<int> tiles;
+    // the tile of the plan, unless the products are at most 64 columns wide
+    // and wider than its tile (the sketch's l = b + p columns with 32 x 32
+    // tiles): then 64 x 64, so the long operand is read once
+    int cfg = plan.cfg, bm, bn;
+    grouped_tile_shape(cfg, &bm, &bn);
+    int64_t maxn = 0;
+    for (int i = 0; i < plan.count; ++i) {
+      GroupedGemm g{};
+      spec(i, mats[i], g);
+      maxn = std::max<int64_t>(maxn, g.N);
+    }
+    if (maxn > bn && maxn <= 64) {
+      cfg = GT_64x64;
+      grouped_tile_shape(cfg, &bm, &bn);
+    }
     for (int i = 0; i < plan.count; ++i) {
       GroupedGemm g{};
       spec(i, mats[i], g);
@@ -653,7 +687,7 @@ struct Builder {
     }
     BatchOp op;
     op.kind = BatchOp::GEMM;
-    op.cfg = plan.cfg;
+    op.cfg = cfg;
     op.ta = ta;
     op.tb = tb;
     op.f32 = f32;
@@ -748,25 +782,41 @@ int rq_batch_plan_create(const rq_batch_matrix* items, int32_t count, int64_t k,
   Carve cv((char*)work + dbytes, work_bytes - dbytes);
   std::vector<OmegaJob> jobs(count);
   int64_t max_n = 0, max_m = 0;
+  // matrices in descending size (n, then m): the one-workgroup-per-matrix
+  // kernels then start the largest first, so the small ones fill in behind
+  // them instead of a large one starting last; every matrix keeps its own
+  // buffers, so the order changes no result
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return items[x].n != items[y].n ? items[x].n > items[y].n : items[x].m > items[y].m;
+  });
   for (int i = 0; i < count; ++i) {
-    const rq_batch_matrix& it = items[i];
+    const rq_batch_matrix& it = items[order[i]];
     BMat& M = B.mats[i];
     carve_matrix(cv, it.m, it.n, k, b, l, M);
     M.m = it.m; M.n = it.n; M.lda = it.lda; M.A = it.A; M.U = it.U; M.ldu = it.ldu; M.sigma = it.sigma;
     M.VT = it.VT; M.ldvt = it.ldvt; M.jpvt_out = it.jpvt; M.seed = it.seed;
     if (it.info) M.info = it.info;
-    jobs[i] = OmegaJob{it.seed, (int64_t)l, it.m, M.om, (int64_t)l};
+    jobs[i] = OmegaJob{it.seed, (int64_t)l, it.m, M.om, it.m, 1};  // Omega(r, c) at om[c + r m]
     max_n = std::max(max_n, it.n);
     max_m = std::max(max_m, it.m);
   }
   if (!cv.ok) { delete plan; return -9; }
   plan->max_n = max_n;
   plan->max_m = max_m;
-  if (sample_lds_bytes(max_n) > 65536 &&
-      hipFuncSetAttribute((const void*)bt_sample_qrcp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)sample_lds_bytes(max_n)) != hipSuccess) {
-    delete plan;
-    return -9;
+  if (sample_lds_bytes(max_n) > 65536) {
+    const void* fns[8] = {(const void*)bt_sample_qrcp_kernel<8>,  (const void*)bt_sample_qrcp_kernel<16>,
+                          (const void*)bt_sample_qrcp_kernel<24>, (const void*)bt_sample_qrcp_kernel<32>,
+                          (const void*)bt_sample_qrcp_kernel<40>, (const void*)bt_sample_qrcp_kernel<48>,
+                          (const void*)bt_sample_qrcp_kernel<56>, (const void*)bt_sample_qrcp_kernel<64>};
+    for (const void* fn : fns) {
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sample_lds_bytes(max_n)) !=
+          hipSuccess) {
+        delete plan;
+        return -9;
+      }
+    }
   }
   plan->max_mb = max_m * b;
   plan->mats = (BMat*)(B.dev + B.put_raw(B.mats.data(), sizeof(BMat) * count));
@@ -783,8 +833,8 @@ int rq_batch_plan_create(const rq_batch_matrix* items, int32_t count, int64_t k,
     plan->ops.push_back(op);
   }
   // the sketch B = Omega A (Section 3)
-  B.gemm(false, false, mixed, [&](int, BMat& M, GroupedGemm& g) {
-    Builder::set(g, l, M.n, M.m, 1.0, M.om, l, M.A, M.lda, 0.0, M.smp, l);
+  B.gemm(true, false, mixed, [&](int, BMat& M, GroupedGemm& g) {
+    Builder::set(g, M.n, l, M.m, 1.0, M.A, M.lda, M.om, M.m, 0.0, M.smp, M.n);
   });
   for (int J = 0; J < nb; ++J) {
     const int64_t i0 = (int64_t)J * b;
@@ -809,8 +859,8 @@ int rq_batch_plan_create(const rq_batch_matrix* items, int32_t count, int64_t k,
     if (J + 1 < nb) {  // the sample update, eq. (update1)
       B.simple(BatchOp::GATHER, i0, GATHER_ROWS);
       B.simple(BatchOp::W11, i0);
-      B.gemm(false, false, false, [&](int, BMat& M, GroupedGemm& g) {
-        Builder::set(g, b, M.n - i0 - b, b, -1.0, M.W11, b, M.Rg + (int64_t)b * b, b, 1.0, M.smp + (i0 + b) * l, l);
+      B.gemm(true, true, false, [&](int, BMat& M, GroupedGemm& g) {
+        Builder::set(g, M.n - i0 - b, b, b, -1.0, M.Rg + (int64_t)b * b, b, M.W11, b, 1.0, M.smp + (i0 + b), M.n);
       });
     }
   }
@@ -881,7 +931,7 @@ int rq_tuxv_batched(void* stream, const rq_batch_plan* plan) {
     switch (op.kind) {
       case BatchOp::INIT:
         hipLaunchKernelGGL(bt_init_kernel, dim3((unsigned)std::max<int64_t>(1, (plan->max_n + 255) / 256), gy),
-                           dim3(256), 0, s, plan->mats, count);
+                           dim3(256), 0, s, plan->mats, count, l);
         break;
       case BatchOp::OMEGA:
         RQ_TRY_RAW(launch_omega_batched(s, op.jobs, count, (int64_t)l * plan->max_m));
@@ -890,8 +940,17 @@ int rq_tuxv_batched(void* stream, const rq_batch_plan* plan) {
         RQ_TRY_RAW(launch_gemm_grouped(s, op.cfg, op.ta, op.tb, op.f32, op.probs, op.tiles, op.ntiles, plan->wgs));
         break;
       case BatchOp::SQRCP:
-        hipLaunchKernelGGL(bt_sample_qrcp_kernel, dim3(mg), dim3(BT_T), sample_lds_bytes(plan->max_n), s,
-                           plan->mats, count, l, b, op.i0, plan->max_n);
+        switch (sample_rows(l)) {
+#define RQ_BT_SQ(L)                                                                                             \
+  case L:                                                                                                     \
+    hipLaunchKernelGGL(bt_sample_qrcp_kernel<L>, dim3(mg), dim3(BT_T), sample_lds_bytes(plan->max_n), s,      \
+                       plan->mats, count, l, b, op.i0, plan->max_n);                                          \
+    break;
+          RQ_BT_SQ(8) RQ_BT_SQ(16) RQ_BT_SQ(24) RQ_BT_SQ(32) RQ_BT_SQ(40) RQ_BT_SQ(48) RQ_BT_SQ(56) RQ_BT_SQ(64)
+#undef RQ_BT_SQ
+          default:
+            return -5;
+        }
         break;
       case BatchOp::GATHER: {
         const int64_t e = (op.mode == GATHER_PANEL) ? plan->max_mb : (op.mode == GATHER_ROWS) ? plan->max_n * b : k;

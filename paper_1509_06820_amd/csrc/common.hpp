@@ -107,6 +107,42 @@ __device__ __forceinline__ void wave_argmax(double& v, long& p) {
 // kernel instead of hanging it.
 constexpr long SPIN_LIMIT = 1L << 20;
 
+// Jacobi rotation of a column pair with squared norms a, b and inner
+// product g (Rutishauser's form): z = (b - a) / (2 g),
+// t = sign(z) / (|z| + sqrt(1 + z^2)), c = 1 / sqrt(1 + t^2), s = c t.
+// The quotients and square roots use the hardware reciprocal and
+// reciprocal-square-root estimates refined by two Newton steps each (a few
+// ulps, which the rotation's own rounding dwarfs), so the dependent chain
+// is a couple of dozen FMAs instead of the long expansions of the correctly
+// rounded operations.  For |z| > 1e150 (1 + z^2 would overflow)
+// t = 1 / (2 z) to working accuracy.
+__device__ __forceinline__ double jr_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double jr_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+__device__ __forceinline__ void jacobi_rotation(double a, double b, double g, double& c, double& s) {
+  const double z = (b - a) * jr_rcp(2.0 * g);
+  const double az = fabs(z);
+  double t;
+  if (az > 1e150) {
+    t = 0.5 * jr_rcp(z);
+  } else {
+    const double q = fma(z, z, 1.0);
+    const double sq = q * jr_rsqrt(q);
+    t = jr_rcp(az + sq);
+    t = (z >= 0.0) ? t : -t;
+  }
+  c = jr_rsqrt(fma(t, t, 1.0));
+  s = c * t;
+}
+
 // A cooperative kernel starts by checking the error word: once one stage has
 // timed out, the later stages of the same call return at once.
 // Thread 0 reads the word and broadcasts it, so the whole workgroup takes

@@ -15,8 +15,8 @@ int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out
 struct OmegaJob {
   uint64_t seed;
   int64_t l, m;
-  double* out;
-  int64_t ld;
+  double* out;   // Omega(r, c) at out[r * rs + c * cs]
+  int64_t rs, cs;
 };
 int launch_omega_batched(hipStream_t s, const OmegaJob* jobs, int count, int64_t max_elems);
 

@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) omega_batched_kernel(const OmegaJob* __re
         const int64_t t = q * 4 + i;
         if (t < total) {
           const int64_t r = t / jb.m, c = t - r * jb.m;
-          jb.out[r + c * jb.ld] = z[i];
+          jb.out[r * jb.rs + c * jb.cs] = z[i];
         }
       }
     }

@@ -14,7 +14,8 @@
 // Singular values are returned in descending order with U = X V / sigma
 // (a column with sigma == 0 is left zero).  The rounds of a sweep run on
 // k/8 workgroups (one wave per column pair, four pairs each) that meet at an
-// arrival barrier after every round.
+// arrival barrier after every round (k < 128 and k > 576; in between, the
+// block kernel below).
 #include "kernels.hpp"
 
 namespace rq {
@@ -124,10 +125,8 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
         sb = wave_sum_x(sb);
         sg = wave_sum_x(sg);
         if (sg != 0.0 && fabs(sg) > tol * sqrt(sa * sb)) {
-          const double z = (sb - sa) / (2.0 * sg);
-          const double t = ((z >= 0.0) ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-          const double cs = 1.0 / sqrt(1.0 + t * t);
-          const double sn_ = cs * t;
+          double cs, sn_;
+          jacobi_rotation(sa, sb, sg, cs, sn_);
 #pragma unroll
           for (int e = 0; e < RPT; ++e) {
             const int row = lane + e * WAVE;
@@ -148,6 +147,284 @@ __global__ void __launch_bounds__(JW_T) jacobi_sweeps_kernel(int k, double* X, i
     if (__builtin_amdgcn_readfirstlane(rot) == 0u) break;
     if (sweep == max_sweeps - 1 && blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(err, 0, 2);
   }
+}
+
+// ---------------------------------------------------------------- block Jacobi
+// For larger k the rounds above cost a device-wide barrier each (k - 1 per
+// sweep), which dominates.  The block variant splits the columns into nb
+// blocks of BW and pairs the blocks in the same round-robin order: in each
+// outer round workgroup g takes block pair (I, J), copies those 2 BW columns
+// of X and of V into LDS, rotates column pairs there (a group of
+// G = 512 / BW lanes per pair, BW pairs at a time, a workgroup barrier
+// between inner rounds) and writes both back; the workgroups meet at a
+// device-wide barrier after each outer round only (nb - 1 per sweep).  Each
+// column pair is rotated once per sweep, as in the round kernel: the pairs
+// inside a block in the sweep's first outer round (where every block meets
+// one other: the full round-robin over the 2 BW columns), the pairs across
+// I and J in the round where I and J meet (BW inner rounds, column l of I
+// with column (l + s) mod BW of J).  Running full round-robin sweeps over
+// the 2 BW columns in every outer round instead rotated each column 2 BW - 1
+// times per round and cost V twice the loss of orthogonality.  Every
+// rotation is the scalar one (same formulas, same threshold); a sweep in
+// which no workgroup rotated ends the iteration.
+constexpr int BJ_T = 512;
+constexpr size_t BJ_LDS_MAX = 150 * 1024;
+constexpr int BJ_MINK = 128;  // smaller k: the round kernel (few rounds, cheap barriers)
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  const int lane = (int)(threadIdx.x & (WAVE - 1));
+  if constexpr (G >= 2) v += xchg_d<1>(v, lane);
+  if constexpr (G >= 4) v += xchg_d<2>(v, lane);
+  if constexpr (G >= 8) v += xchg_d<4>(v, lane);
+  if constexpr (G >= 16) v += xchg_d<8>(v, lane);
+  if constexpr (G >= 32) v += xchg_d<16>(v, lane);
+  if constexpr (G >= 64) v += xchg_d<32>(v, lane);
+  return v;
+}
+
+// LDS of a block pair: 2 BW columns of X and of V, kpad = RPL * (512 / BW)
+// rows each (rows past k zero), pitch kpad + 1.
+template <int BW, int RPL>
+constexpr size_t bj_lds_bytes() {
+  return (size_t)2 * (2 * BW) * (RPL * (BJ_T / BW) + 1) * sizeof(double);
+}
+
+// BW columns per block, RPL rows per lane in an inner round (k <= RPL * G).
+template <int BW, int RPL>
+__global__ void __launch_bounds__(BJ_T) jacobi_block_kernel(int k, double* X, int64_t ldx, double* V, int64_t ldv,
+                                                             double tol, int max_sweeps, unsigned* flags, int* err) {
+  constexpr int C2 = 2 * BW;            // columns held by a workgroup
+  constexpr int G = BJ_T / BW;          // lanes per column pair in an inner round
+  constexpr int KPAD = RPL * G;         // rows held per column (zero past k)
+  constexpr int KP = KPAD + 1;          // LDS pitch
+  static_assert(G <= WAVE && (G & (G - 1)) == 0, "group within a wave");
+  static_assert(bj_lds_bytes<BW, RPL>() <= BJ_LDS_MAX, "LDS budget");
+  extern __shared__ __align__(16) double bj_smem[];
+  double* Xs = bj_smem;                 // C2 columns of X
+  double* Vs = bj_smem + (size_t)C2 * KP;  // the same columns of V
+  __shared__ int s_rot;
+  if (earlier_failure(err)) return;
+  const int tid = threadIdx.x, P = gridDim.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int nb = 2 * P;                 // blocks (the last ones may be partly or wholly padding)
+  const int pi = tid / G, gl = tid % G; // inner pair slot and lane within its group
+  unsigned round = 0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    bool any = false;
+    for (int r = 0; r < nb - 1; ++r) {
+      int bi, bj;
+      rr_pair(r, blockIdx.x, nb, bi, bj);
+      auto gcol = [&](int l) { return (l < BW) ? bi * BW + l : bj * BW + (l - BW); };
+      // the two blocks' columns of X and V into LDS: wave w takes columns
+      // w, w + 8, ..., a lane per row (coalesced), zeros past k; all of a
+      // lane's loads are issued before the first LDS store
+      {
+        constexpr int NCW = C2 / (BJ_T / WAVE);     // columns per wave
+        constexpr int NRC = (KPAD + WAVE - 1) / WAVE;  // row chunks per column
+        double lx[NCW][NRC], lv[NCW][NRC];
+#pragma unroll
+        for (int cc = 0; cc < NCW; ++cc) {
+          const int c = gcol(wv + cc * (BJ_T / WAVE));
+          const bool cin = c < k;
+          const double* xc = X + (int64_t)(cin ? c : 0) * ldx;
+          const double* vc = V + (int64_t)(cin ? c : 0) * ldv;
+#pragma unroll
+          for (int h = 0; h < NRC; ++h) {
+            const int row = lane + h * WAVE;
+            const bool in = cin && row < k;
+            lx[cc][h] = in ? xc[row] : 0.0;
+            lv[cc][h] = in ? vc[row] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int cc = 0; cc < NCW; ++cc) {
+          const int l = wv + cc * (BJ_T / WAVE);
+#pragma unroll
+          for (int h = 0; h < NRC; ++h) {
+            const int row = lane + h * WAVE;
+            if (row < KPAD) {
+              Xs[l * KP + row] = lx[cc][h];
+              Vs[l * KP + row] = lv[cc][h];
+            }
+          }
+        }
+      }
+      if (tid == 0) s_rot = 0;
+      __syncthreads();
+      auto rotate_if = [&](double (&u)[RPL], double (&v)[RPL], double (&a2)[RPL], double (&b2)[RPL])
+          __attribute__((always_inline)) {
+        double sa = 0.0, sb = 0.0, sg = 0.0;
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) {
+          sa = fma(u[e], u[e], sa);
+          sb = fma(v[e], v[e], sb);
+          sg = fma(u[e], v[e], sg);
+        }
+        sa = group_sum<G>(sa);
+        sb = group_sum<G>(sb);
+        sg = group_sum<G>(sg);
+        if (sg != 0.0 && fabs(sg) > tol * sqrt(sa * sb)) {
+          double cs, sn_;
+          jacobi_rotation(sa, sb, sg, cs, sn_);
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) {
+            const double x1 = u[e], x2 = v[e], y1 = a2[e], y2 = b2[e];
+            u[e] = cs * x1 - sn_ * x2;
+            v[e] = sn_ * x1 + cs * x2;
+            a2[e] = cs * y1 - sn_ * y2;
+            b2[e] = sn_ * y1 + cs * y2;
+          }
+          if (gl == 0) s_rot = 1;
+          return true;
+        }
+        return false;
+      };
+      if (r == 0) {
+        // every pair of the 2 BW columns once (round-robin), from LDS
+        for (int ir = 0; ir < C2 - 1; ++ir) {
+          int p, q;
+          rr_pair(ir, pi, C2, p, q);
+          const int i = min(p, q), j = max(p, q);
+          double* xi = Xs + i * KP + gl;
+          double* xj = Xs + j * KP + gl;
+          double* vi = Vs + i * KP + gl;
+          double* vj = Vs + j * KP + gl;
+          double u[RPL], v[RPL], a2[RPL], b2[RPL];
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) {
+            u[e] = xi[G * e];
+            v[e] = xj[G * e];
+            a2[e] = vi[G * e];
+            b2[e] = vj[G * e];
+          }
+          if (rotate_if(u, v, a2, b2)) {
+#pragma unroll
+            for (int e = 0; e < RPL; ++e) {
+              xi[G * e] = u[e];
+              xj[G * e] = v[e];
+              vi[G * e] = a2[e];
+              vj[G * e] = b2[e];
+            }
+          }
+          __syncthreads();
+        }
+      } else {
+        // column pi of I against column (pi + s) mod BW of J, s = 0..BW-1:
+        // the group keeps its column of I in registers and reads and writes
+        // only the J columns in LDS
+        double u[RPL], a2[RPL];
+        {
+          const double* xi = Xs + pi * KP + gl;
+          const double* vi = Vs + pi * KP + gl;
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) {
+            u[e] = xi[G * e];
+            a2[e] = vi[G * e];
+          }
+        }
+        for (int ir = 0; ir < BW; ++ir) {
+          const int j = BW + ((pi + ir) & (BW - 1));
+          double* xj = Xs + j * KP + gl;
+          double* vj = Vs + j * KP + gl;
+          double v[RPL], b2[RPL];
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) {
+            v[e] = xj[G * e];
+            b2[e] = vj[G * e];
+          }
+          if (rotate_if(u, v, a2, b2)) {
+#pragma unroll
+            for (int e = 0; e < RPL; ++e) {
+              xj[G * e] = v[e];
+              vj[G * e] = b2[e];
+            }
+          }
+          __syncthreads();
+        }
+        double* xi = Xs + pi * KP + gl;
+        double* vi = Vs + pi * KP + gl;
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) {
+          xi[G * e] = u[e];
+          vi[G * e] = a2[e];
+        }
+        __syncthreads();
+      }
+      if (s_rot) any = true;
+      // the columns back to X and V
+      for (int l = wv; l < C2; l += BJ_T / WAVE) {
+        const int c = gcol(l);
+        if (c < k) {
+          double* xc = X + (int64_t)c * ldx;
+          double* vc = V + (int64_t)c * ldv;
+#pragma unroll
+          for (int row = lane; row < KPAD; row += WAVE) {
+            if (row < k) {
+              xc[row] = Xs[l * KP + row];
+              vc[row] = Vs[l * KP + row];
+            }
+          }
+        }
+      }
+      if (r == nb - 2 && any && tid == 0) atomicOr(&flags[1 + sweep], 1u);
+      if (!jw_barrier(flags, P, ++round, err)) return;
+    }
+    const unsigned rot = __hip_atomic_load(&flags[1 + sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__builtin_amdgcn_readfirstlane(rot) == 0u) break;
+    if (sweep == max_sweeps - 1 && blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(err, 0, 2);
+  }
+}
+
+// Launch of the block kernel for BW, RPL (RPL * 512 / BW >= k).
+template <int BW, int RPL>
+int launch_bj(hipStream_t s, int k, double* X, int64_t ldx, double* V, int64_t ldv, int max_sweeps, unsigned* flags,
+              int* err) {
+  constexpr size_t lds = bj_lds_bytes<BW, RPL>();
+  int nb = (k + BW - 1) / BW;
+  nb += nb & 1;
+  const int P = nb / 2;
+  static int res = 0;
+  auto kern = jacobi_block_kernel<BW, RPL>;
+  const void* fn = (const void*)kern;
+  if (!res) {
+    RQ_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int occ = 0, dev = 0, cus = 0;
+    RQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, BJ_T, lds));
+    RQ_HIP(hipGetDevice(&dev));
+    RQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    res = std::max(1, occ * cus);
+  }
+  if (P > res) return RQ_ERR_HIP_BASE + (int)hipErrorCooperativeLaunchTooLarge;
+  hipLaunchKernelGGL(kern, dim3(P), dim3(BJ_T), lds, s, k, X, ldx, V, ldv, 1e-15, max_sweeps, flags, err);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
+
+// The block kernel for this k (RPL = rows per lane), or 1 when k is outside
+// its range (the round kernel then runs).
+int dispatch_bj(hipStream_t s, int k, double* X, int64_t ldx, double* V, int64_t ldv, int max_sweeps,
+                unsigned* flags, int* err) {
+  if (k < BJ_MINK) return 1;
+  if (k <= 9 * 32) {  // blocks of 16 columns, 32 lanes per pair
+    switch ((k + 31) / 32) {
+      case 4: return launch_bj<16, 4>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+      case 5: return launch_bj<16, 5>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+      case 6: return launch_bj<16, 6>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+      case 7: return launch_bj<16, 7>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+      case 8: return launch_bj<16, 8>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+      default: return launch_bj<16, 9>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+    }
+  }
+  if (k <= 9 * 64) {  // blocks of 8 columns, 64 lanes per pair
+    switch ((k + 63) / 64) {
+      case 5: return launch_bj<8, 5>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+      case 6: return launch_bj<8, 6>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+      case 7: return launch_bj<8, 7>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+      case 8: return launch_bj<8, 8>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+      default: return launch_bj<8, 9>(s, k, X, ldx, V, ldv, max_sweeps, flags, err);
+    }
+  }
+  return 1;
 }
 
 // Column norms of the rotated X, singular values in descending order (ties
@@ -202,6 +479,16 @@ int launch_jacobi_svd(hipStream_t s, int k, double* X, int64_t ldx, double* U, i
   hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((std::max<int64_t>(ke, nflags) + 255) / 256)), dim3(256), 0, s,
                      k, w.tmp, (int64_t)k, w.flags, nflags);
   RQ_HIP(hipGetLastError());
+  {
+    const int rc = dispatch_bj(s, k, X, ldx, w.tmp, (int64_t)k, MAX_SWEEPS, w.flags, w.err);
+    if (rc <= 0) {
+      if (rc < 0) return rc;
+      hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(SVD_THREADS), 0, s, k, (const double*)X, ldx,
+                         (const double*)w.tmp, (int64_t)k, U, ldu, sigma, V, ldv, (const int*)w.err);
+      RQ_HIP(hipGetLastError());
+      return 0;
+    }
+  }
   const int kk = k + (k & 1);
   // one wave per column pair of a round, four per workgroup
   int P = std::max(1, (kk / 2 + JW_PAIRS - 1) / JW_PAIRS);
