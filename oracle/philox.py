@@ -1,5 +1,5 @@
-"""Gaussian compression matrix Omega for the sketch (Section 3; Alg. 4 step
-"Generate random l x m GIID matrix").
+"""Gaussian compression matrix Omega for the sketch (Section 3; drawn in the
+first step of Alg. 4, l x m with i.i.d. standard normal entries).
 
 The paper asks only for an l x m matrix with i.i.d. unit-variance Gaussian
 entries and names no generator.  Reading adopted here (shared with the GPU

@@ -1,11 +1,11 @@
 """RQRCP (Alg. 4), TRQRCP (Alg. 6) and the unpivoted blocked QR the paper
-compares against (Section 7: "qr" is RQRCP with sampling and pivoting removed).
+compares against (Section 7: RQRCP with the sketch and the pivoting taken out).
 
 Conventions (readings of points the paper leaves open):
 
 * Blocks: block J starts at column i0 and has width bJ = min(b, k - i0), so b
   need not divide k (Alg. 4 assumes it does).  Full factorization: k = min(m, n).
-* Sample QRCP ("qrcp(B, b)", Alg. 1 on the sample): trailing squared norms are
+* Sample QRCP (Alg. 1 run on the sample for bJ steps): trailing squared norms are
   recomputed from the current sample at every step (not downdated); the
   pivot is the largest one, ties go to the lowest current position, and a
   NaN norm never wins (it ranks as -1).  Swaps are sequential: step t
@@ -126,25 +126,25 @@ def rqrcp(A, b, p, seed=None, Omega=None, k=None, trace=False):
     jpvt = np.arange(n, dtype=np.int64)
     tau = np.zeros(kk)
     gaps, info, blocks = [], 0, []
-    B = Omega @ A  # the sketch (Alg. 4, "Form the initial sample")
+    B = Omega @ A  # the sketch B = Omega A of Alg. 4
     i0 = 0
     while i0 < kk:
         bJ = min(b, kk - i0)
-        # Get bJ column pivots from the sample.
+        # bJ pivots chosen on the sample (Alg. 1)
         sq = sample_qrcp(B, bJ)
         gaps += sq["gaps"]
         if sq["info"] and not info:
             info = i0 + sq["info"]
-        # Permute A (all rows, completed R rows included) and jpvt.
+        # the same column exchanges on A (every row) and on jpvt
         apply_swaps(A, sq["piv"], i0)
         apply_swaps(jpvt, sq["piv"], i0)
-        # Construct bJ reflectors from the new leading columns.
+        # Householder QR of the bJ chosen columns
         Fp, tp = householder_qr(A[i0:, i0:i0 + bJ])
         A[i0:, i0:i0 + bJ] = Fp
         tau[i0:i0 + bJ] = tp
         Y = unit_lower(Fp, bJ)
         T = larft(Y, tp)
-        # Finish bJ rows of R and update the trailing matrix: Q^T C.
+        # the block's rows of R and the trailing columns: C <- Q^T C
         if i0 + bJ < n:
             C = A[i0:, i0 + bJ:]
             Wt = T.T @ (Y.T @ C)
@@ -153,7 +153,7 @@ def rqrcp(A, b, p, seed=None, Omega=None, k=None, trace=False):
         if trace:
             rec = dict(i0=i0, bJ=bJ, B=B.copy(), S=sq["S"], refl=sq["refl"], piv=list(sq["piv"]),
                        panel=Fp.copy(), tau=tp.copy(), T=T, A_after=A.copy())
-        # Update the sample (eq. update1) unless this was the last block.
+        # next sample by eq. (update1), except after the last block
         if i0 + bJ < kk:
             R11 = np.triu(A[i0:i0 + bJ, i0:i0 + bJ])
             R12 = A[i0:i0 + bJ, i0 + bJ:]
@@ -198,23 +198,24 @@ def trqrcp(A, k, b, p, seed=None, Omega=None):
         gaps += sq["gaps"]
         if sq["info"] and not info:
             info = i0 + sq["info"]
-        # Permute A (and completed rows of R), prior inner products, jpvt.
+        # the column exchanges on A, on the stored inner products and on jpvt
         apply_swaps(A, sq["piv"], i0)
         apply_swaps(Wt, sq["piv"], i0)
         apply_swaps(jpvt, sq["piv"], i0)
         sel = slice(i0, i0 + bJ)
         trail = slice(i0 + bJ, n)
-        # Construct the selected columns from A - Y W^T.
+        # the chosen columns brought up to date: A - Y W^T on them only
         Ahat = A[i0:, sel] - Y[i0:, :i0] @ Wt[:i0, sel]
         Fp, tp = householder_qr(Ahat)
         A[i0:, sel] = Fp
         tau[sel] = tp
         Y2 = unit_lower(Fp, bJ)
         T2 = larft(Y2, tp)
-        # Inner products of the new reflectors with the trailing columns.
+        # the new reflectors' products with the trailing columns (Alg. 6 keeps
+        # them instead of updating A)
         Wt[i0:i0 + bJ, trail] = T2.T @ (Y2.T @ A[i0:, trail] - (Y2.T @ Y[i0:, :i0]) @ Wt[:i0, trail])
         Y[i0:, sel] = Y2
-        # New rows of R from A - Y W^T.
+        # the block's rows of R: the same correction on those rows only
         A[i0:i0 + bJ, trail] = A[i0:i0 + bJ, trail] - Y[i0:i0 + bJ, :i0 + bJ] @ Wt[:i0 + bJ, trail]
         if i0 + bJ < k:
             R11 = np.triu(A[i0:i0 + bJ, sel])
@@ -245,18 +246,20 @@ def rsrqrcp(A, b, p, seed=None, omegas=None, k=None):
     while i0 < kk:
         bJ = min(b, kk - i0)
         mJ = m - i0
-        # Generate Omega^[J] and form the sample of the trailing matrix.
+        # a new compression matrix for this block and the sample of the
+        # trailing matrix it gives
         Om = omegas(J, mJ) if omegas is not None else make_omega(seed, l, mJ, key1=J)
         B = np.asarray(Om, dtype=np.float64) @ A[i0:, i0:]
-        # Get bJ column pivots from the sample.
+        # bJ pivots chosen on the sample (Alg. 1)
         sq = sample_qrcp(B, bJ)
         gaps += sq["gaps"]
         if sq["info"] and not info:
             info = i0 + sq["info"]
-        # Permute A (all rows, completed R rows included) and jpvt.
+        # the same column exchanges on A (every row) and on jpvt
         apply_swaps(A, sq["piv"], i0)
         apply_swaps(jpvt, sq["piv"], i0)
-        # Construct bJ reflectors, finish bJ rows of R, update the trailing matrix.
+        # Householder QR of the chosen columns, then their rows of R and the
+        # trailing update
         Fp, tp = householder_qr(A[i0:, i0:i0 + bJ])
         A[i0:, i0:i0 + bJ] = Fp
         tau[i0:i0 + bJ] = tp

@@ -1,7 +1,7 @@
 // Householder panel by CholeskyQR2 and Householder reconstruction.
 //
-// The paper's panel step is "[Q, R11] = qr(A P(:, 1:b))" (Alg. 4, Alg. 6) and
-// its later steps need the Householder form (reflectors Y, tau, connection
+// The panel step of Alg. 4 and Alg. 6 is an unpivoted QR of the b chosen
+// columns, and the later steps need its Householder form (reflectors Y, tau, connection
 // matrix T).  Instead of b sequential column steps, the mJ x b panel P is
 // orthogonalised with two Cholesky QR passes and the Householder vectors
 // are then recovered from the orthonormal factor (Ballard, Demmel, Grigori,

@@ -1,5 +1,5 @@
-// Sample QRCP (Alg. 4 step "get b column pivots from the sample", i.e. Alg. 1
-// run for bJ steps on the l x nJ sample), column swaps of A, the connection
+// Sample QRCP (the pivot-selection step of Alg. 4: Alg. 1 run for bJ steps on
+// the l x nJ sample), column swaps of A, the connection
 // matrix T of a reflector block, the W11 = S11 R11^-1 factor of the sample
 // update (eq. update1) and small data-movement kernels.
 //
