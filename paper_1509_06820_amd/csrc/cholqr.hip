@@ -27,7 +27,8 @@
 //   chol1 : M1 = chol(G1)^-1                    (1 workgroup)
 //   gemm  : Q1 = X M1, G2 = Q1^T Q1, H = Q1^T P
 //   recon : R2 = chol(G2), Q_top = Q1(0:b, :) R2^-1, LU with sign choice,
-//           T, tau, R = S R2^-T H, Y1, M3 = -R2^-1 S U^-1   (1 workgroup)
+//           then in four workgroups (each forming the factors): R = S R2^-T H
+//           and Y1; tau and T; M3 = -R2^-1 S U^-1; W11
 //   gemm  : Y(b:, :) = Q1(b:, :) M3
 //   copy  : Y(b:, :) back into the panel storage (skipped on failure)
 #include "kernels.hpp"
@@ -218,21 +219,20 @@ __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
 // The last column of a square panel (i = mJ - 1) has no row below: there
 // S_ii = sign(c0) and U(i, i) = 0.  On return A holds L (unit, below the
 // diagonal), U(i, i) on the diagonal and Q' above it; sgn[i] = S_ii.
-// Block k0: lane r holds A(r, k0:k0+16) (the column panel: L and the
-// diagonal block) and A(k0:k0+16, r) for r >= k0 + 16 (the row band of U).
+// Block k0: wave 0 eliminates the 16 columns k0..k0+15 with lane r holding
+// A(r, k0:k0+16) (steps without barriers, the pivot row's entries read with
+// v_readlane); then the row band U12 = L11^-1 A12 (rows k0..k0+15, the
+// columns right of the block) by forward substitution, one thread per
+// column; then A22 -= L21 U12 on the matrix cores.
 __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_t mJ) {
 #pragma unroll
   for (int k0 = 0; k0 < SM_N; k0 += SM_NB) {  // unrolled: every lane index below is a constant
     if (k0 >= b) break;
     if (threadIdx.x < SM_N) {
       const int r = threadIdx.x;
-      const bool band = r >= k0 + SM_NB;
-      double a[SM_NB], u[SM_NB];
+      double a[SM_NB];
 #pragma unroll
-      for (int j = 0; j < SM_NB; ++j) {
-        a[j] = A[r + (k0 + j) * SM_LD];
-        u[j] = A[(k0 + j) + r * SM_LD];
-      }
+      for (int j = 0; j < SM_NB; ++j) a[j] = A[r + (k0 + j) * SM_LD];
 #pragma unroll
       for (int i = 0; i < SM_NB; ++i) {
         const int p = k0 + i;
@@ -249,23 +249,33 @@ __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_
             a[i] = (r > p) ? l : ((r == p) ? piv : a[i]);
 #pragma unroll
             for (int j = i + 1; j < SM_NB; ++j) a[j] = fma(-l, lane_val(a[j], p), a[j]);
-            // row band: A(k0 + q, c) -= L(k0 + q, p) A(p, c)
-#pragma unroll
-            for (int q = i + 1; q < SM_NB; ++q) u[q] = fma(-lane_val(l, k0 + q), u[i], u[q]);
             if (r == 0) sgn[p] = sg;
           }
         }
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
-      for (int j = 0; j < SM_NB; ++j) {
+      for (int j = 0; j < SM_NB; ++j)
         if (r >= k0) A[r + (k0 + j) * SM_LD] = a[j];
-        if (band) A[(k0 + j) + r * SM_LD] = u[j];
-      }
     }
     __syncthreads();
     const int n2 = SM_N - k0 - SM_NB;
     if (n2 > 0 && k0 + SM_NB < b) {
+      // U12 = L11^-1 A12: column c = k0 + 16 + t, rows k0..k0+15, in order
+      const int t = threadIdx.x;
+      if (t < n2) {
+        const int c = k0 + SM_NB + t;
+        double x[SM_NB];
+#pragma unroll
+        for (int q = 0; q < SM_NB; ++q) x[q] = A[(k0 + q) + c * SM_LD];
+#pragma unroll
+        for (int q = 1; q < SM_NB; ++q)
+#pragma unroll
+          for (int pp = 0; pp < q; ++pp) x[q] = fma(-A[(k0 + q) + (k0 + pp) * SM_LD], x[pp], x[q]);
+#pragma unroll
+        for (int q = 0; q < SM_NB; ++q) A[(k0 + q) + c * SM_LD] = x[q];
+      }
+      __syncthreads();
       // A22 -= L21 U12
       const double* L21 = A + (k0 + SM_NB) + k0 * SM_LD;
       const double* U12 = A + k0 + (k0 + SM_NB) * SM_LD;
@@ -516,49 +526,55 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
     else u = (i == j) ? 1.0 : 0.0;
     C[i + j * SM_LD] = u;
   }
-  // outputs of the top block: R(i, j) = S_ii sum_k R2^-1(k, i) H(k, j) on and
-  // above the diagonal, Y1 below it
-  sm_mm<true>(B, D, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
-    if (i < b && j < b) {
-      if (i <= j) {
-        P[i + (int64_t)j * ldp] = sgn[i] * v;
-        Y[i + (int64_t)j * ldy] = (i == j) ? 1.0 : 0.0;
-      } else {
-        const double y = A[i + j * SM_LD];
-        P[i + (int64_t)j * ldp] = y;
-        Y[i + (int64_t)j * ldy] = y;
-      }
-    }
-  });
   __syncthreads();
-  // -R2^-1 S (columns scaled), kept in registers meanwhile (padding zero)
-  double m3r[SM_N / 4];
+  // The four products that follow use only the factors above, so each
+  // workgroup of the launch (which all computed them) takes one.
+  const int task = blockIdx.x;
+  if (task == 0) {
+    // outputs of the top block: R(i, j) = S_ii sum_k R2^-1(k, i) H(k, j) on and
+    // above the diagonal, Y1 below it
+    sm_mm<true>(B, D, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
+      if (i < b && j < b) {
+        if (i <= j) {
+          P[i + (int64_t)j * ldp] = sgn[i] * v;
+          Y[i + (int64_t)j * ldy] = (i == j) ? 1.0 : 0.0;
+        } else {
+          const double y = A[i + j * SM_LD];
+          P[i + (int64_t)j * ldp] = y;
+          Y[i + (int64_t)j * ldy] = y;
+        }
+      }
+    });
+    return;
+  }
+  if (task == 1) {
+    // tau and T = U inv(Y1^T)
+    for (int i = threadIdx.x; i < b; i += SM_T) tau[i] = C[i + i * SM_LD];
+    // D = Y1^T (unit upper) padded
+    for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
+      const int i = e % SM_N, j = e / SM_N;
+      double v;
+      if (i < b && j < b) v = (i < j) ? A[j + i * SM_LD] : (i == j ? 1.0 : 0.0);
+      else v = (i == j) ? 1.0 : 0.0;
+      D[i + j * SM_LD] = v;
+    }
+    __syncthreads();
+    sm_tri_inv(D, A, B, &flag);   // A = inv(Y1^T) (unit diagonal: never singular)
+    sm_mm<false>(C, A, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
+      if (i < b && j < b) T[i + (int64_t)j * b] = v;
+    });
+    return;
+  }
+  // B = -R2^-1 S (columns scaled; padding zero), for M3 and W11: each
+  // thread rewrites only its own entries
 #pragma unroll
   for (int q = 0; q < SM_N / 4; ++q) {
     const int c = cg + 4 * q;
-    m3r[q] = (r <= c && r < b && c < b) ? -sgn[c] * B[r + c * SM_LD] : 0.0;
+    B[r + c * SM_LD] = (r <= c && r < b && c < b) ? -sgn[c] * B[r + c * SM_LD] : 0.0;
   }
-  for (int i = threadIdx.x; i < b; i += SM_T) tau[i] = C[i + i * SM_LD];
-  // D = Y1^T (unit upper) padded
-  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
-    const int i = e % SM_N, j = e / SM_N;
-    double v;
-    if (i < b && j < b) v = (i < j) ? A[j + i * SM_LD] : (i == j ? 1.0 : 0.0);
-    else v = (i == j) ? 1.0 : 0.0;
-    D[i + j * SM_LD] = v;
-  }
-  __syncthreads();
-  sm_tri_inv(D, A, B, &flag);   // A = inv(Y1^T) (unit diagonal: never singular)
-  // T = U inv(Y1^T)
-  sm_mm<false>(C, A, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
-    if (i < b && j < b) T[i + (int64_t)j * b] = v;
-  });
-  __syncthreads();
-  // B = -R2^-1 S, for M3 and W11
-#pragma unroll
-  for (int q = 0; q < SM_N / 4; ++q) B[r + (cg + 4 * q) * SM_LD] = m3r[q];
-  __syncthreads();
-  if (mJ > b) {  // rows below the top block
+  if (task == 2) {
+    if (mJ <= b) return;  // no rows below the top block
+    __syncthreads();
     // M3 = -R2^-1 S inv(U): A = inv(U) (D scratch)
     if (!sm_tri_inv(C, A, D, &flag)) {  // pivots are >= 1 here: cannot happen
       if (threadIdx.x == 0) atomicOr(st, ST_PIVOT);
@@ -567,7 +583,7 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
     sm_mm<false>(B, A, SM_N, SM_N, SM_N, 1, 0, [&](int, int i, int j, double v) {
       if (i < b && j < b) M3[i + (int64_t)j * b] = v;
     });
-    __syncthreads();
+    return;
   }
   if (W11) {
     // W11 = S11 R11^-1 of the sample update (eq. update1): with the panel
@@ -702,7 +718,8 @@ int launch_panel_cholqr(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int b
   RQ_TRY_RAW(launch_gemm(s, false, false, mJ, b, b, 1.0, X, ldx, M1, b, 0.0, Q1, mJ, nullptr, 0));
   // [G2 H] = Q1^T [Q1 P] in one launch (H follows G2 in the scratch, ld b)
   RQ_TRY_RAW(launch_gemm_pair(s, b, b, mJ, 1.0, Q1, mJ, Q1, mJ, P, ldp, 0.0, G2, b, splitk, splitk_elems));
-  hipLaunchKernelGGL(recon_kernel, dim3(1), dim3(SM_T), SM_LDS, s, b, mJ, G2, H, Q1, mJ, P, ldp, Y, ldy, tau, T, M3,
+  // four workgroups: each forms the factors, then one of the four products
+  hipLaunchKernelGGL(recon_kernel, dim3(4), dim3(SM_T), SM_LDS, s, b, mJ, G2, H, Q1, mJ, P, ldp, Y, ldy, tau, T, M3,
                      st, (const double*)M1, S11 ? W11 : nullptr);
   RQ_HIP(hipGetLastError());
   if (mJ > b) {
