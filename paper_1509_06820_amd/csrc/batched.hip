@@ -50,6 +50,7 @@ constexpr int BT_T = 512;       // threads of the per-matrix kernels
 constexpr int BT_W = BT_T / WAVE;
 constexpr int BT_NMAX = 8192;   // sample columns (norms in LDS)
 constexpr int BT_KMAX = 64;
+constexpr int BT_GP = 16 * 32 * 32;  // doubles of a matrix's Gram partials
 constexpr int BT_LD = BT_KMAX + 1;  // LDS pitch of the small matrices
 // rows of the batched sample: l rounded up to a multiple of 8 (the rows past l are zero)
 __host__ __device__ inline int sample_rows(int l) { return (l + 7) & ~7; }
@@ -78,7 +79,8 @@ struct BMat {
   double* Rg;     // b x n, ld b
   double* V;      // n x k, ld n
   double* V2;     // n x k, ld n
-  double* G;      // k x k (ld k): Gram matrix
+  double* G;      // k x k (ld k): Q^T P of the panel's re-orthogonalisation
+  double* Gp;     // split-K partials of a Gram matrix (BT_GP doubles)
   double* Ri;     // k x k: inverse of the Cholesky factor
   double* X;      // k x k: accumulated triangular factor
   double* W11;    // b x b
@@ -305,13 +307,30 @@ __global__ void __launch_bounds__(256) bt_init_kernel(BMat* __restrict__ mats, i
 // (n rows) or of Z1 (m rows).
 enum { CH_PANEL = 0, CH_V = 1, CH_Z = 2 };
 
+// Split-K of the Gram products that bt_chol_kernel factors: about 256 rows a
+// chunk, at most 16 chunks and at most what the partial buffer holds for
+// nc x nc; chunk lengths are multiples of 16 (the product's k step).  The
+// producer and bt_chol_kernel derive the chunking from the same two numbers.
+__host__ __device__ inline int64_t gram_kchunk(int64_t rows, int nc) {
+  const int64_t cap = BT_GP / ((int64_t)nc * nc);
+  int64_t s = (rows + 255) / 256;
+  if (s > 16) s = 16;
+  if (s > cap) s = cap;
+  if (s < 1) s = 1;
+  const int64_t kc = ((rows + s - 1) / s + 15) / 16 * 16;
+  return kc < 16 ? 16 : kc;
+}
+__host__ __device__ inline int gram_chunks(int64_t rows, int nc) {
+  return rows > 0 ? (int)((rows + gram_kchunk(rows, nc) - 1) / gram_kchunk(rows, nc)) : 1;
+}
+
 // R = chol(G + s I) (upper, R^T R = G + s I) and Ri = R^-1, for the nc x nc
-// Gram matrix M.G (ld nc).  shift: s = 11 (rows nc + nc (nc + 1)) u tr(G),
-// the first pass of shifted CholeskyQR (tr(G) bounds ||X||_2^2 from above);
-// 0 for the later passes.  A pivot that is not positive (breakdown) is
-// replaced by the smallest positive normal so that the pass stays finite,
-// and the matrix's info word is set to -4.  With accumulate, X = R X
-// (X = R on the first pass).
+// Gram matrix G held as its split-K partials in M.Gp (ld nc).  shift:
+// s = 11 (rows nc + nc (nc + 1)) u tr(G), the first pass of shifted
+// CholeskyQR (tr(G) bounds ||X||_2^2 from above); 0 for the later passes.
+// A pivot that is not positive (breakdown) is replaced by the smallest
+// positive normal so that the pass stays finite, and the matrix's info word
+// is set to -4.  With accumulate, X = R X (X = R on the first pass).
 __global__ void __launch_bounds__(256) bt_chol_kernel(BMat* __restrict__ mats, int count, int nc, int which,
                                                       int shifted, int accumulate, int first) {
   __shared__ double R[BT_KMAX * BT_LD];
@@ -320,9 +339,13 @@ __global__ void __launch_bounds__(256) bt_chol_kernel(BMat* __restrict__ mats, i
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
   for (int mi = blockIdx.x; mi < count; mi += gridDim.x) {
     BMat& M = mats[mi];
+    // G = the sum of the Gram product's split-K partials (in chunk order)
+    const int nz = gram_chunks((which == CH_V) ? M.n : M.m, nc);
     for (int e = tid; e < nc * nc; e += 256) {
       const int j = e / nc, i = e - j * nc;
-      R[i + j * BT_LD] = M.G[i + j * nc];
+      double sum = 0.0;
+      for (int z = 0; z < nz; ++z) sum += M.Gp[(int64_t)z * nc * nc + i + j * nc];
+      R[i + j * BT_LD] = sum;
     }
     __syncthreads();
     if (shifted) {
@@ -599,6 +622,7 @@ void carve_matrix(Carve& cv, int64_t m, int64_t n, int64_t k, int b, int l, BMat
   M.V = cv.take<double>((size_t)n * k);
   M.V2 = cv.take<double>((size_t)n * k);
   M.G = cv.take<double>((size_t)k * k);
+  M.Gp = cv.take<double>((size_t)BT_GP);
   M.Ri = cv.take<double>((size_t)k * k);
   M.X = cv.take<double>((size_t)k * k);
   M.Ux = cv.take<double>((size_t)k * k);
@@ -616,7 +640,7 @@ size_t tiles_bound(const rq_batch_matrix* items, int32_t count, int64_t k, int b
     const int64_t m = items[i].m, n = items[i].n;
     // the largest product of a matrix, in the smallest tiles (32 x 32)
     const int64_t tm = (m + 31) / 32, tn = (n + 31) / 32, tk = (k + 31) / 32, tl = (l + 31) / 32;
-    t += (size_t)std::max({tl * tn, tk * tn, tm * tk, tn * tk, tk * tk}) * calls;
+    t += (size_t)std::max({tl * tn, tk * tn, tm * tk, tn * tk, tk * tk * 16}) * calls;
   }
   return t;
 }
@@ -681,9 +705,15 @@ struct Builder {
       const int64_t tx = (g.M > 0 && g.N > 0) ? (g.N + bn - 1) / bn : 0;
       const int64_t ty = (g.M > 0 && g.N > 0) ? (g.M + bm - 1) / bm : 0;
       g.tiles_x = std::max<int64_t>(tx, 1);
+      g.ntile = std::max<int64_t>(tx * ty, 1);
+      if (g.kchunk <= 0) {
+        g.kchunk = std::max<int64_t>(g.K, 1);
+        g.split_stride = 0;
+      }
+      const int64_t nz = (g.K > 0) ? (g.K + g.kchunk - 1) / g.kchunk : 1;
       g.tile0 = (int64_t)tiles.size();
       probs[i] = g;
-      for (int64_t t = 0; t < tx * ty; ++t) tiles.push_back(i);
+      for (int64_t t = 0; t < tx * ty * nz; ++t) tiles.push_back(i);
     }
     BatchOp op;
     op.kind = BatchOp::GEMM;
@@ -715,6 +745,11 @@ struct Builder {
     g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.beta = beta;
     g.C = C; g.ldc = ldc;
   }
+  // a Gram product of `rows` rows into the split-K partials (C = M.Gp, ld nc)
+  static void split(GroupedGemm& g, int64_t rows, int nc) {
+    g.kchunk = gram_kchunk(rows, nc);
+    g.split_stride = (int64_t)nc * nc;
+  }
   // Three passes of CholeskyQR (the first shifted) of the m x nc matrix X0
   // (ld m), through the buffers X0 -> X1 -> X0 -> out; `which` selects the
   // Gram matrix's row count for the shift; acc accumulates the triangular
@@ -724,7 +759,8 @@ struct Builder {
     for (int pass = 0; pass < 3; ++pass) {
       gemm(true, false, false, [&](int, BMat& M, GroupedGemm& g) {
         const double* X = (pass == 1) ? tmp(M) : in(M);
-        set(g, nc, nc, rows(M), 1.0, X, rows(M), X, rows(M), 0.0, M.G, nc);
+        set(g, nc, nc, rows(M), 1.0, X, rows(M), X, rows(M), 0.0, M.Gp, nc);
+        split(g, rows(M), nc);
       });
       simple(BatchOp::CHOL, 0, 0, nc, which, pass == 0, acc, pass == 0);
       gemm(false, false, false, [&](int, BMat& M, GroupedGemm& g) {
@@ -868,7 +904,8 @@ int rq_batch_plan_create(const rq_batch_matrix* items, int32_t count, int64_t k,
   // ---- TUXV (Alg. 7, j_max = 1) ----
   // V: CholeskyQR of Z0^T = Rr^T (n x k); the first pass forms Rr Rr^T and Rr^T Ri
   B.gemm(false, true, false, [&](int, BMat& M, GroupedGemm& g) {
-    Builder::set(g, k, k, M.n, 1.0, M.Rr, k, M.Rr, k, 0.0, M.G, k);
+    Builder::set(g, k, k, M.n, 1.0, M.Rr, k, M.Rr, k, 0.0, M.Gp, k);
+    Builder::split(g, M.n, (int)k);
   });
   B.simple(BatchOp::CHOL, 0, 0, (int)k, CH_V, 1, 0, 1);
   B.gemm(true, false, false, [&](int, BMat& M, GroupedGemm& g) {
@@ -877,7 +914,8 @@ int rq_batch_plan_create(const rq_batch_matrix* items, int32_t count, int64_t k,
   for (int pass = 1; pass < 3; ++pass) {
     B.gemm(true, false, false, [&](int, BMat& M, GroupedGemm& g) {
       const double* X = (pass == 1) ? M.V : M.V2;
-      Builder::set(g, k, k, M.n, 1.0, X, M.n, X, M.n, 0.0, M.G, k);
+      Builder::set(g, k, k, M.n, 1.0, X, M.n, X, M.n, 0.0, M.Gp, k);
+      Builder::split(g, M.n, (int)k);
     });
     B.simple(BatchOp::CHOL, 0, 0, (int)k, CH_V, 0, 0, 0);
     B.gemm(false, false, false, [&](int, BMat& M, GroupedGemm& g) {

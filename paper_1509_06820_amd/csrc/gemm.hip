@@ -250,8 +250,8 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
 // Grouped products (the batched engine): the tiles of many independent
 // products in one persistent launch.  Workgroup g walks the tile list
 // t = g, g + gridDim.x, ...; tile t belongs to product tile_prob[t] and is
-// its tile t - tile0 in row-major tile order (no split-K: every tile runs
-// its whole reduction).
+// its tile t - tile0: chunk z = (t - tile0) / ntile of the reduction (split
+// K, partial products to C + z split_stride), then row-major tile order.
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename Acc>
 __global__ void __launch_bounds__(256, 2) gemm_grouped_kernel(const GroupedGemm* __restrict__ probs,
                                                            const int* __restrict__ tile_prob, int64_t ntiles) {
@@ -259,9 +259,10 @@ __global__ void __launch_bounds__(256, 2) gemm_grouped_kernel(const GroupedGemm*
     const int pi = __builtin_amdgcn_readfirstlane(tile_prob[t]);
     const GroupedGemm& g = probs[pi];
     const int64_t lt = t - g.tile0;
+    const int64_t z = lt / g.ntile, tl = lt - z * g.ntile;
     gemm_tile<BM, BN, BK, WM, WN, TA, TB, double, double, Acc, false>(
-        g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc, g.K, 0, nullptr, 0, 0, lt % g.tiles_x,
-        lt / g.tiles_x, 0);
+        g.M, g.N, g.K, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc, g.kchunk, g.split_stride, nullptr, 0, 0,
+        tl % g.tiles_x, tl / g.tiles_x, z);
     __syncthreads();  // the next tile's LDS stores after every wave's last reads
   }
 }

@@ -51,6 +51,10 @@ struct GroupedGemm {
   int64_t ldc;
   double alpha, beta;
   int64_t tiles_x, tile0;
+  // split-K: the reduction runs in chunks of kchunk (K: no split); chunk z
+  // writes its partial product to C + z * split_stride (beta 0); ntile =
+  // output tiles of one chunk
+  int64_t kchunk, split_stride, ntile;
 };
 // Tile shapes of the grouped launches (output rows x columns per workgroup).
 enum { GT_64x64 = 0, GT_32x32 = 1, GT_128x64 = 2, GT_NCFG = 3 };
