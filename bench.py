@@ -9,18 +9,36 @@ the time of both factorizations and their ratio, the stage breakdown (a pass
 of K steps with HIP events around every stage), the roofline position of the
 dominant stage (its launches timed with HIP events inside the timed region,
 where only that stage records events) and the CPU oracle timed on a bounded
-sample of the same workload.
+sample of the same workload.  Unless --no-extras is given, the same line also
+carries the rest of the metric: the 512 x 512 latency (`c1_rqrcp`, per call
+and per block) and TUXV at k = 256 on the 20000 x 10000 matrix in FP64 and
+both mixed levels (`tuxv_c3*`: solves/s, p99, truncation error next to the
+oracle's and the optimum).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--no-extras] [--check]
 
 Other workloads (one JSON line each, same keys):
-    --workload rsrqrcp_c2   RSRQRCP (Alg. 5, a new sample per block) on the same
-                            matrix, with RQRCP and QR timed beside it
+    --workload c2_lr        RQRCP of the 8192 x 8192 rank-512 product of
+                            Gaussians plus 1e-8 noise (numerical rank, pivots)
+    --workload c1           512 x 512, b = 32: latency per call and per block
+    --workload rsrqrcp_c2   RSRQRCP (Alg. 5, a new sample per block) on the
+                            default matrix, with RQRCP and QR timed beside it
     --workload c3 [--jmax J]  TRQRCP + TUXV (Alg. 7 with j_max = J) at k = 256
     --workload c3 --precision mixed|mixed_bf16
                             the same TUXV in mixed precision (FP32 matrix cores
                             for the products with A, the sketch on the FP32 or
                             BF16 ones, FP64 otherwise)
+    --workload c4 [--tune-cache F]
+                            512 uneven matrices (TRQRCP + TUXV at k = 32) in one
+                            captured batch, mixed and FP64, b and tiles from the
+                            autotuner cache
+    --workload c5 [--requests R --serve-max N --serve-streams S --hbm-budget-gb G]
+                            the request server: a stream of TUXV requests of
+                            mixed sizes and ranks, solves/s and p50/p99 latency
+    --workload select_expect  the selection experiment of Section 3.2 replayed
+                            through the sketch and the sample QRCP (trials/s)
+    --copy-calibration MIB  only a plain device copy (HBM counter calibration)
 """
 
 import argparse

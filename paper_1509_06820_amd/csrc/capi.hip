@@ -192,8 +192,8 @@ int dump_sample(hipStream_t s, const double* smp, int ls, int l, int64_t nJ, int
 // Panel QR of A(i0:m, i0:i0+bJ) + connection matrix T of its reflectors:
 // CholeskyQR2 + Householder reconstruction (preconditioned by the sample's
 // S11 when given), with the column-by-column Householder panel as fallback.
-// W11 (with S11): where a successful CholeskyQR writes S11 R11^-1 for the
-// sample update.
+// W11 (with S11): where the panel writes S11 R11^-1 for the sample update
+// (the reconstruction from its own factors, or the fallback's tail from R11).
 int panel_and_t(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t i0, int bJ, double* tau, double* Y,
                 int64_t ldy, const BlockBufs& bb, const Common& c, int64_t J, const double* S11 = nullptr,
                 int64_t srs = 0, int64_t scs = 0, double* W11 = nullptr) {
@@ -209,7 +209,9 @@ int panel_and_t(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t i0, in
     RQ_TRY(launch_panel_cholqr(s, A + i0 + i0 * lda, lda, mJ, bJ, S11, srs, scs, tau, Y, ldy, bb.T, bb.cq, bb.splitk,
                                bb.splitk_elems, st, W11));
   }
-  const int rc = launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, pw);
+  // the column panel if the status word is set, else the copy of the
+  // reconstructed Y's rows below the top block into the panel's storage
+  const int rc = launch_panel(s, A + i0 + i0 * lda, lda, mJ, bJ, tau, Y, ldy, pw, !forced);
   if (rc == RQ_PANEL_TOO_TALL) {
     // the column panel's workgroups cannot all be resident at this height:
     // forced, that is an enqueue error; as the fallback, a failed CholeskyQR
@@ -219,7 +221,8 @@ int panel_and_t(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t i0, in
   } else if (rc) {
     return rc;
   }
-  RQ_TRY(launch_larft_gated(s, mJ, bJ, Y, ldy, tau, bb.T, st));
+  // after the column panel: its T, and W11 = S11 R11^-1 for the sample update
+  RQ_TRY(launch_fallback_tail(s, mJ, bJ, Y, ldy, tau, bb.T, st, S11, srs, scs, A + i0 + i0 * lda, lda, W11));
   return 0;
 }
 
@@ -338,17 +341,14 @@ int trailing_update_split(hipStream_t s, const Lookahead& la, double* A, int64_t
 
 // Sample update, eq. (update1): B1 = S12 - (S11 R11^-1) R12, B2 = S22, on the
 // sample columns of this block (S + i0 * ls, ld ls).  W11 = S11 R11^-1 is
-// already in sb.w11 unless the panel's status word `st` reports that
-// CholeskyQR failed; then it is formed here from R11.
+// already in sb.w11 (written by the panel).
 int sample_update(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t i0, int bJ, double* s_blk,
-                  const SampleBufs& sb, const int* st) {
+                  const SampleBufs& sb) {
   const int64_t Nt = n - i0 - bJ;
   if (Nt <= 0) return 0;
-  const double* R11 = A + i0 + i0 * lda;
   const double* R12 = A + i0 + (i0 + bJ) * lda;
   const double dn = (double)Nt, db = (double)bJ;
-  ProfScope ps(PC_SAMPLE_UPDATE, s, 8.0 * (3.0 * db * dn + 2.0 * db * db), 2.0 * db * db * dn + db * db * db / 3.0);
-  RQ_TRY(launch_w11(s, bJ, s_blk, 1, sb.ls, R11, lda, sb.w11, st));
+  ProfScope ps(PC_SAMPLE_UPDATE, s, 8.0 * (3.0 * db * dn + 2.0 * db * db), 2.0 * db * db * dn);
   // S(0:bJ, bJ:) -= W11 R12
   RQ_TRY(launch_gemm(s, false, false, bJ, Nt, bJ, -1.0, sb.w11, bJ, R12, lda, 1.0, s_blk + (int64_t)bJ * sb.ls, sb.ls,
                      nullptr, 0));
@@ -456,7 +456,7 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
     } else {
       RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb, mixed));
     }
-    if (upd) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb, panel_work(f.bb, f.c, J).gate));
+    if (upd) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb));
     i0 += bJ;
   }
   if (bulk_pending) RQ_HIP(hipStreamWaitEvent(s, la.done, 0));
@@ -562,7 +562,7 @@ int trqrcp_core(hipStream_t s, int64_t m, int64_t n, int64_t k, double* A, int64
       RQ_TRY(launch_gemm(s, false, false, bJ, Nt, i0 + bJ, -1.0, t.yall + i0, m, wt_tr, k, 1.0, Atr, lda, nullptr,
                          0));
     }
-    if (upd) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, t.sb, panel_work(t.bb, t.c, J).gate));
+    if (upd) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, t.sb));
     i0 += bJ;
   }
   return 0;

@@ -53,20 +53,36 @@ constexpr int ST_CHOL1 = 1, ST_CHOL2 = 2, ST_ORTH = 4, ST_PIVOT = 8, ST_S11 = 16
 __device__ __forceinline__ int sm_r() { return threadIdx.x & 63; }
 __device__ __forceinline__ int sm_cg() { return threadIdx.x >> 6; }
 
+// Global -> LDS and back: each thread's sixteen loads are issued before the
+// first of its stores, so a transfer costs one memory latency, not sixteen.
+constexpr int SM_PER = SM_N / (SM_T / SM_N);  // elements per thread
+
 __device__ __forceinline__ void sm_load(double* M, const double* G, int64_t rs, int64_t cs, int b, bool upper_only) {
-  const int i = sm_r();
-  for (int j = sm_cg(); j < SM_N; j += SM_T / SM_N) {
-    double v;
-    if (i < b && j < b) v = (upper_only && i > j) ? 0.0 : G[(int64_t)i * rs + (int64_t)j * cs];
-    else v = (i == j) ? 1.0 : 0.0;
-    M[i + j * SM_LD] = v;
+  const int i = sm_r(), cg = sm_cg();
+  double v[SM_PER];
+#pragma unroll
+  for (int q = 0; q < SM_PER; ++q) {
+    const int j = cg + q * (SM_T / SM_N);
+    // inside b x b: the entry (zero below the diagonal with upper_only);
+    // outside: the identity
+    const bool in = i < b && j < b && !(upper_only && i > j);
+    v[q] = in ? G[(int64_t)i * rs + (int64_t)j * cs] : ((i == j) ? 1.0 : 0.0);
   }
+#pragma unroll
+  for (int q = 0; q < SM_PER; ++q) M[i + (cg + q * (SM_T / SM_N)) * SM_LD] = v[q];
 }
 
 __device__ __forceinline__ void sm_store(const double* M, double* G, int64_t ld, int b) {
-  const int i = sm_r();
-  if (i < b)
-    for (int j = sm_cg(); j < b; j += SM_T / SM_N) G[i + (int64_t)j * ld] = M[i + j * SM_LD];
+  const int i = sm_r(), cg = sm_cg();
+  if (i >= b) return;
+  double v[SM_PER];
+#pragma unroll
+  for (int q = 0; q < SM_PER; ++q) v[q] = M[i + (cg + q * (SM_T / SM_N)) * SM_LD];
+#pragma unroll
+  for (int q = 0; q < SM_PER; ++q) {
+    const int j = cg + q * (SM_T / SM_N);
+    if (j < b) G[i + (int64_t)j * ld] = v[q];
+  }
 }
 
 // Products of LDS matrices on the matrix cores: for each of nb batches
@@ -172,6 +188,7 @@ __device__ __forceinline__ double lane_val(double v, int lane) {
 // R upper, lower part zeroed).  Returns false (uniformly) if a pivot is not
 // positive.  Block k0: lane c holds G(k0:k0+16, c), the row band of R.
 __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
+  __shared__ double rowbuf[SM_N];  // row p of R, for the broadcast reads
   if (threadIdx.x == 0) *flag = 0;
   __syncthreads();
 #pragma unroll
@@ -181,18 +198,35 @@ __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
       double a[SM_NB];
 #pragma unroll
       for (int i = 0; i < SM_NB; ++i) a[i] = G[(k0 + i) + c * SM_LD];
+      // Step i's pivot chain (pivot, reciprocal square root, row scaling,
+      // the next pivot row's update, read with v_readlane) is formed first,
+      // and the next pivot's reciprocal square root inside step i, so that
+      // it overlaps step i's updates of the rows further down.  Those take
+      // row p of R through LDS: each lane stores its R(p, c), and every lane
+      // reads the entries it needs at one address (a broadcast), in order
+      // within the wave.
       bool ok = true;
+      double d = lane_val(a[0], k0);
+      double dd = (d > 0.0) ? d : 1.0;
+      double isd = rsqrt_nr(dd);
 #pragma unroll
       for (int i = 0; i < SM_NB; ++i) {
         const int p = k0 + i;
-        const double d = lane_val(a[i], p);
         ok = ok && (d > 0.0);
-        const double dd = (d > 0.0) ? d : 1.0;
-        const double isd = rsqrt_nr(dd), sd = dd * isd;
+        const double sd = dd * isd;
         const double r = (c > p) ? a[i] * isd : ((c == p) ? sd : 0.0);  // R(p, c)
         a[i] = r;
+        rowbuf[c] = r;
+        __builtin_amdgcn_wave_barrier();
+        if (i + 1 < SM_NB) {
+          a[i + 1] = fma(-lane_val(r, p + 1), r, a[i + 1]);
+          d = lane_val(a[i + 1], p + 1);
+          dd = (d > 0.0) ? d : 1.0;
+          isd = rsqrt_nr(dd);
+        }
 #pragma unroll
-        for (int q = i + 1; q < SM_NB; ++q) a[q] = fma(-lane_val(r, k0 + q), r, a[q]);
+        for (int q = i + 2; q < SM_NB; ++q) a[q] = fma(-rowbuf[k0 + q], r, a[q]);
+        __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
@@ -225,6 +259,7 @@ __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
 // columns right of the block) by forward substitution, one thread per
 // column; then A22 -= L21 U12 on the matrix cores.
 __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_t mJ) {
+  __shared__ double prow[SM_NB];  // the pivot row's entries, for the broadcast reads
 #pragma unroll
   for (int k0 = 0; k0 < SM_N; k0 += SM_NB) {  // unrolled: every lane index below is a constant
     if (k0 >= b) break;
@@ -237,6 +272,14 @@ __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_
       for (int i = 0; i < SM_NB; ++i) {
         const int p = k0 + i;
         if (p < b) {
+          // the pivot row's entries right of the pivot go through LDS: lane
+          // p stores them, every lane reads them at one address (in order
+          // within the wave)
+          if (r == p) {
+#pragma unroll
+            for (int j = i + 1; j < SM_NB; ++j) prow[j] = a[j];
+          }
+          __builtin_amdgcn_wave_barrier();
           const double c0 = lane_val(a[i], p);
           if (p == mJ - 1) {
             if (r == 0) sgn[p] = (c0 >= 0.0) ? 1.0 : -1.0;
@@ -248,9 +291,10 @@ __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_
             const double l = (r > p) ? a[i] * f : 0.0;  // L(r, p)
             a[i] = (r > p) ? l : ((r == p) ? piv : a[i]);
 #pragma unroll
-            for (int j = i + 1; j < SM_NB; ++j) a[j] = fma(-l, lane_val(a[j], p), a[j]);
+            for (int j = i + 1; j < SM_NB; ++j) a[j] = fma(-l, prow[j], a[j]);
             if (r == 0) sgn[p] = sg;
           }
+          __builtin_amdgcn_wave_barrier();
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -291,43 +335,39 @@ __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_
 // inv([A B; 0 C]) = [inv(A), -inv(A) B inv(C); 0, inv(C)], block size 16, 32.
 // The four diagonal 16 x 16 blocks by back substitution (one wave each), the
 // doubling levels on the matrix cores.  R and Ri
-// must differ; W is scratch (SM_N * SM_LD).  Returns false if a diagonal
-// entry is zero.
+// must differ; W is scratch (SM_N * SM_LD).  Returns false (uniformly) if a
+// diagonal entry is zero; *flag is set to match.
 __device__ __forceinline__ bool sm_tri_inv(const double* R, double* Ri, double* W, int* flag) {
+  __shared__ int zero_diag[SM_T / 64];  // per wave: its diagonal block has a zero
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x == 0) *flag = 0;
-  // blocks below the diagonal blocks are zero
+  // blocks below the diagonal blocks are zero (no barrier before the
+  // diagonal blocks: those write other entries of Ri and read only R)
   for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
     const int i = e & (SM_N - 1), j = e >> 6;
     if ((i >> 4) > (j >> 4)) Ri[i + j * SM_LD] = 0.0;
   }
-  __syncthreads();
   {
-    // diagonal block w, one wave: lane j < 16 holds column j of the block
-    // and forms column j of its inverse by back substitution, taking the
-    // other columns' entries with v_readlane
+    // diagonal block w, one wave: lane j < 16 forms column j of the block's
+    // inverse by back substitution; column k of the block, R(o:o+k, o+k), is
+    // read from LDS at the same address by every lane (a broadcast, off the
+    // substitution's dependency chain, so the reads of later steps can be
+    // issued early: these kernels run one workgroup per CU, registers are
+    // plentiful), the reciprocal of R(o+k, o+k) from lane k with v_readlane
     const int o = SM_NB * w, j = lane & 15;
-    double r[SM_NB], x[SM_NB];
+    double x[SM_NB];
 #pragma unroll
-    for (int i = 0; i < SM_NB; ++i) {
-      r[i] = R[(o + i) + (o + j) * SM_LD];
-      x[i] = (i == j) ? 1.0 : 0.0;
-    }
-    double dj = 0.0;
-#pragma unroll
-    for (int i = 0; i < SM_NB; ++i)
-      if (i == j) dj = r[i];
-    if (lane < SM_NB && dj == 0.0) *flag = 1;
+    for (int i = 0; i < SM_NB; ++i) x[i] = (i == j) ? 1.0 : 0.0;
+    const double dj = R[(o + j) + (o + j) * SM_LD];
+    const bool zero = __any(lane < SM_NB && dj == 0.0);
+    if (lane == 0) zero_diag[w] = zero ? 1 : 0;
     const double rdj = (dj != 0.0) ? 1.0 / dj : 0.0;
 #pragma unroll
     for (int k = SM_NB - 1; k >= 0; --k) {
       const double xk = x[k] * lane_val(rdj, k);
       x[k] = xk;
+      const double* colk = R + o + (o + k) * SM_LD;
 #pragma unroll
-      for (int i = 0; i < k; ++i) x[i] = fma(-lane_val(r[i], k), xk, x[i]);
-      // keep the scheduler from hoisting later steps' v_readlane results
-      // (scalar registers would spill)
-      __builtin_amdgcn_sched_barrier(0);
+      for (int i = 0; i < k; ++i) x[i] = fma(-colk[i], xk, x[i]);
     }
     if (lane < SM_NB) {
 #pragma unroll
@@ -346,7 +386,11 @@ __device__ __forceinline__ bool sm_tri_inv(const double* R, double* Ri, double* 
                  [&](int bi, int i, int j, double v) { Ri[bi * boff + i + (sz + j) * SM_LD] = -v; });
     __syncthreads();
   }
-  return *flag == 0;
+  // (the barriers of the doubling levels order the flags' stores before
+  // these reads)
+  const bool ok = !(zero_diag[0] | zero_diag[1] | zero_diag[2] | zero_diag[3]);
+  if (threadIdx.x == 0) *flag = ok ? 0 : 1;
+  return ok;
 }
 
 // C = A B (all 64 x 64 in LDS, C distinct from A and B).
@@ -602,22 +646,55 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
   }
 }
 
-// W11 = S11 R11^-1 of the sample update (eq. update1), b x b upper
-// triangular.  A zero pivot R11(j, j) gives a zero column j of W11 and takes
-// row j of R11 out of the later columns; that is W11 = S~ R~^-1 with column j
-// of S~ zeroed and row and column j of R~ replaced by the unit vector.
-// With st, it runs only when the panel's CholeskyQR failed (otherwise the
-// reconstruction has written W11 from its own factors).
-__global__ void __launch_bounds__(SM_T) w11_kernel(int b, const double* S, int64_t srs, int64_t scs, const double* R,
-                                                   int64_t ldr, double* W, const int* st) {
+// The fallback panel's tail (runs only when the CholeskyQR panel failed,
+// after the column panel):
+//  * T of its reflectors: G = Y^T Y, then the forward recurrence
+//    T(i, i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) G(0:i, i);
+//  * with W, W11 = S11 R11^-1 of the sample update (eq. update1), b x b upper
+//    triangular.  A zero pivot R11(j, j) gives a zero column j of W11 and
+//    takes row j of R11 out of the later columns; that is W11 = S~ R~^-1
+//    with column j of S~ zeroed and row and column j of R~ replaced by the
+//    unit vector.
+// (When the CholeskyQR panel succeeds, the reconstruction has written T and
+// W11 from its own factors.)
+__global__ void __launch_bounds__(SM_T) fallback_tail_kernel(int64_t mJ, int b, const double* __restrict__ Y,
+                                                             int64_t ldy, const double* __restrict__ tau,
+                                                             double* __restrict__ T, const int* st, const double* S,
+                                                             int64_t srs, int64_t scs, const double* R, int64_t ldr,
+                                                             double* W) {
   extern __shared__ __align__(16) double sm[];
   __shared__ int flag;
-  if (st) {
-    __shared__ int s_ok;
-    if (threadIdx.x == 0) s_ok = (*st == 0);
+  __shared__ int s_failed;
+  if (threadIdx.x == 0) s_failed = (*st != 0);
+  __syncthreads();
+  if (!s_failed) return;
+  {
+    double* Gs = sm;
+    double* Ts = sm + SM_N * SM_N;
+    for (int e = threadIdx.x; e < b * b; e += SM_T) {
+      const int i = e % b, j = e / b;
+      double acc = 0.0;
+      if (i <= j)
+        for (int64_t r = 0; r < mJ; ++r) acc += Y[r + i * ldy] * Y[r + j * ldy];
+      Gs[e] = acc;
+      Ts[e] = 0.0;
+    }
     __syncthreads();
-    if (s_ok) return;
+    for (int i = 0; i < b; ++i) {
+      const int r = threadIdx.x;
+      if (r < i) {
+        double h = 0.0;
+        for (int q = r; q < i; ++q) h += Ts[r + q * b] * Gs[q + i * b];
+        Ts[r + i * b] = -tau[i] * h;
+      } else if (r == i) {
+        Ts[i + i * b] = tau[i];
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < b * b; e += SM_T) T[e] = Ts[e];
+    __syncthreads();
   }
+  if (!W) return;
   double* Rt = sm;
   double* Ri = sm + SM_N * SM_LD;
   double* Wk = sm + 2 * SM_N * SM_LD;
@@ -642,18 +719,6 @@ __global__ void __launch_bounds__(SM_T) w11_kernel(int b, const double* S, int64
   });
 }
 
-// Copy Y(b:mJ, :) into the panel storage below the top block, unless the
-// reconstruction failed.
-__global__ void __launch_bounds__(256) ycopy_kernel(int64_t mJ, int b, const double* Y, int64_t ldy, double* P,
-                                                    int64_t ldp, const int* st) {
-  if (*st) return;
-  const int64_t rows = mJ - b;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * b) return;
-  const int64_t j = idx / rows, i = b + (idx - j * rows);
-  P[i + j * ldp] = Y[i + j * ldy];
-}
-
 constexpr size_t SM_LDS = 4 * SM_N * SM_LD * sizeof(double);
 
 int set_lds(const void* fn) {
@@ -663,14 +728,16 @@ int set_lds(const void* fn) {
 
 }  // namespace
 
-int launch_w11(hipStream_t s, int bJ, const double* S, int64_t srs, int64_t scs, const double* R, int64_t ldr,
-               double* W, const int* st) {
+int launch_fallback_tail(hipStream_t s, int64_t mJ, int bJ, const double* Y, int64_t ldy, const double* tau,
+                         double* T, const int* st, const double* S, int64_t srs, int64_t scs, const double* R,
+                         int64_t ldr, double* W) {
   static bool init = false;
   if (!init) {
-    RQ_TRY_RAW(set_lds((const void*)w11_kernel));
+    RQ_TRY_RAW(set_lds((const void*)fallback_tail_kernel));
     init = true;
   }
-  hipLaunchKernelGGL(w11_kernel, dim3(1), dim3(SM_T), SM_LDS, s, bJ, S, srs, scs, R, ldr, W, st);
+  hipLaunchKernelGGL(fallback_tail_kernel, dim3(1), dim3(SM_T), SM_LDS, s, mJ, bJ, Y, ldy, tau, T, st, S, srs, scs, R,
+                     ldr, W);
   RQ_HIP(hipGetLastError());
   return 0;
 }
@@ -722,12 +789,9 @@ int launch_panel_cholqr(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int b
   hipLaunchKernelGGL(recon_kernel, dim3(4), dim3(SM_T), SM_LDS, s, b, mJ, G2, H, Q1, mJ, P, ldp, Y, ldy, tau, T, M3,
                      st, (const double*)M1, S11 ? W11 : nullptr);
   RQ_HIP(hipGetLastError());
-  if (mJ > b) {
+  // (the panel launch that follows copies Y(b:mJ, :) into P when st is 0)
+  if (mJ > b)
     RQ_TRY_RAW(launch_gemm(s, false, false, mJ - b, b, b, 1.0, Q1 + b, mJ, M3, b, 0.0, Y + b, ldy, nullptr, 0));
-    const int64_t tot = (mJ - b) * b;
-    hipLaunchKernelGGL(ycopy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, mJ, b, Y, ldy, P, ldp, st);
-    RQ_HIP(hipGetLastError());
-  }
   return 0;
 }
 

@@ -11,11 +11,13 @@
 //
 // Tiling: a workgroup of 256 threads (4 waves, WM x WN) owns a BM x BN tile of
 // C (128 x 64 for the large updates, 64 x 64 otherwise); operand tiles of
-// depth BK are staged through two LDS buffers with register prefetch of the
-// next tile, and C is loaded into the accumulators before the k loop.  The MFMA is issued with its operands swapped
-// (B-fragment first) so that lane l, register r of a 16x16 accumulator holds
-// C(i0 + l%16, j0 + 4r + l/16): sixteen consecutive rows of one column of
-// the column-major C, which makes the C loads and stores 128-byte coalesced.
+// depth BK are staged through two LDS buffers with register prefetch (two
+// steps ahead for tiles up to 64 x 64, one step for the 128 x 64 tiles),
+// and C is loaded into the accumulators before the k loop.  The MFMA is
+// issued with its operands swapped (B-fragment first) so that lane l,
+// register r of a 16x16 accumulator holds C(i0 + l%16, j0 + 4r + l/16):
+// sixteen consecutive rows of one column of the column-major C, which makes
+// the C loads and stores 128-byte coalesced.
 //
 // Split-K (grid.z > 1) writes partial sums to a scratch buffer; a second
 // kernel adds them in a fixed order (deterministic, no atomics).
@@ -117,92 +119,206 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, doubl
         for (int r = 0; r < 4; ++r) acc[a][b][r] = (Acc)0;
   }
 
-  TAe ra[A_PER];
-  TBe rb[B_PER];
-
-  auto load_tiles = [&](int64_t k0) {
+  auto compute = [&](int stage) {
+    const Acc* as = As + stage * BK * ALD;
+    const Acc* bs = Bs + stage * BK * BLD;
 #pragma unroll
-    for (int e = 0; e < A_PER; ++e) {
-      const int idx = tid + e * 256;
-      int ii, kk;
-      if (TA) { kk = idx % BK; ii = idx / BK; } else { ii = idx % BM; kk = idx / BM; }
-      const int64_t gi = i0 + ii, gk = k0 + kk;
-      TAe v = (TAe)0;
-      if (gi < M && gk < kend) v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
-      ra[e] = v;
+    for (int kk = 0; kk < BK; kk += 4) {
+      Acc af[TM], bf[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) af[a] = as[(kk + (lane >> 4)) * ALD + wm * WTM + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bf[b] = bs[(kk + (lane >> 4)) * BLD + wn * WTN + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          if constexpr (std::is_same<Acc, double>::value)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[b], af[a], acc[a][b], 0, 0, 0);
+        }
     }
+  };
+
+  if constexpr (BM * BN <= 64 * 64) {
+    // Tiles up to 64 x 64 (few accumulators): prefetch distance two.
+    // Register set s % 2 receives the tiles of step s two steps ahead and LDS
+    // stage s % 2 one step ahead.  The loads have no branches: an element
+    // outside the matrix or past the chunk's end is read at the clamped
+    // position and zeroed when it is stored to LDS, so the loads are issued
+    // unconditionally, the number in flight is the same on every path, and
+    // the wait before an LDS store covers only the older register set.
+    TAe ra[2][A_PER];
+    TBe rb[2][B_PER];
+    auto load_tiles = [&](int64_t k0, TAe* ra_, TBe* rb_) {
 #pragma unroll
-    for (int e = 0; e < B_PER; ++e) {
-      const int idx = tid + e * 256;
-      int jj, kk;
-      if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
-      const int64_t gj = j0 + jj, gk = k0 + kk;
-      TBe v = (TBe)0;
-      if (gj < N && gk < kend) {
+      for (int e = 0; e < A_PER; ++e) {
+        const int idx = tid + e * 256;
+        int ii, kk;
+        if (TA) { kk = idx % BK; ii = idx / BK; } else { ii = idx % BM; kk = idx / BM; }
+        const int64_t gi = i0 + ii, gk = k0 + kk;
+        const int64_t gic = gi < M ? gi : M - 1, gkc = gk < kend ? gk : kend - 1;
+        ra_[e] = TA ? A[gkc + gic * lda] : A[gic + gkc * lda];
+      }
+#pragma unroll
+      for (int e = 0; e < B_PER; ++e) {
+        const int idx = tid + e * 256;
+        int jj, kk;
+        if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
+        const int64_t gj = j0 + jj, gk = k0 + kk;
+        const int64_t gjc = gj < N ? gj : N - 1, gkc = gk < kend ? gk : kend - 1;
+        const TBe* src;
         if constexpr (PAIR) {
-          if (gj >= nsplit) {
-            const int64_t g2 = gj - nsplit;
-            v = TB ? B2[g2 + gk * ldb2] : B2[gk + g2 * ldb2];
+          const bool second = gjc >= nsplit;
+          const int64_t g2 = second ? gjc - nsplit : gjc;
+          const TBe* base = second ? B2 : B;
+          const int64_t ld = second ? ldb2 : ldb;
+          src = TB ? base + g2 + gkc * ld : base + gkc + g2 * ld;
+        } else {
+          src = TB ? B + gjc + gkc * ldb : B + gkc + gjc * ldb;
+        }
+        rb_[e] = *src;
+      }
+    };
+    auto store_tiles = [&](int stage, int64_t k0, const TAe* ra_, const TBe* rb_) {
+      Acc* as = As + stage * BK * ALD;
+      Acc* bs = Bs + stage * BK * BLD;
+#pragma unroll
+      for (int e = 0; e < A_PER; ++e) {
+        const int idx = tid + e * 256;
+        int ii, kk;
+        if (TA) { kk = idx % BK; ii = idx / BK; } else { ii = idx % BM; kk = idx / BM; }
+        const bool ok = i0 + ii < M && k0 + kk < kend;
+        as[kk * ALD + ii] = ok ? (Acc)(alpha * (double)ra_[e]) : (Acc)0;
+      }
+#pragma unroll
+      for (int e = 0; e < B_PER; ++e) {
+        const int idx = tid + e * 256;
+        int jj, kk;
+        if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
+        const bool ok = j0 + jj < N && k0 + kk < kend;
+        bs[kk * BLD + jj] = ok ? (Acc)rb_[e] : (Acc)0;
+      }
+    };
+    if (kbeg < kend) {
+      const int64_t nsteps = (kend - kbeg + BK - 1) / BK;
+      load_tiles(kbeg, ra[0], rb[0]);
+      load_tiles(kbeg + BK, ra[1], rb[1]);
+      store_tiles(0, kbeg, ra[0], rb[0]);
+      __syncthreads();
+      // steps st and st + 1 per iteration while step st + 2 exists; no
+      // branch lies between a load and its LDS store, so the compiler does
+      // not sink the loads past one
+      int64_t st = 0;
+      for (; st + 2 < nsteps; st += 2) {
+        load_tiles(kbeg + (st + 2) * BK, ra[0], rb[0]);
+        __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the products
+        compute(0);
+        store_tiles(1, kbeg + (st + 1) * BK, ra[1], rb[1]);
+        __syncthreads();
+        load_tiles(kbeg + (st + 3) * BK, ra[1], rb[1]);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(1);
+        store_tiles(0, kbeg + (st + 2) * BK, ra[0], rb[0]);
+        __syncthreads();
+      }
+      // the last one or two steps: stage 0 holds step st, set 1 step st + 1
+      compute(0);
+      if (st + 1 < nsteps) {
+        store_tiles(1, kbeg + (st + 1) * BK, ra[1], rb[1]);
+        __syncthreads();
+        compute(1);
+      }
+    }
+  } else {
+    // Larger tiles (more accumulators, less room for a second register
+    // set): prefetch distance one; the loads of step k + 1 are issued before
+    // step k computes.
+    TAe ra[A_PER];
+    TBe rb[B_PER];
+    auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+      for (int e = 0; e < A_PER; ++e) {
+        const int idx = tid + e * 256;
+        int ii, kk;
+        if (TA) { kk = idx % BK; ii = idx / BK; } else { ii = idx % BM; kk = idx / BM; }
+        const int64_t gi = i0 + ii, gk = k0 + kk;
+        TAe v = (TAe)0;
+        if (gi < M && gk < kend) v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
+        ra[e] = v;
+      }
+#pragma unroll
+      for (int e = 0; e < B_PER; ++e) {
+        const int idx = tid + e * 256;
+        int jj, kk;
+        if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
+        const int64_t gj = j0 + jj, gk = k0 + kk;
+        TBe v = (TBe)0;
+        if (gj < N && gk < kend) {
+          if constexpr (PAIR) {
+            if (gj >= nsplit) {
+              const int64_t g2 = gj - nsplit;
+              v = TB ? B2[g2 + gk * ldb2] : B2[gk + g2 * ldb2];
+            } else {
+              v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
+            }
           } else {
             v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
           }
-        } else {
-          v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
         }
+        rb[e] = v;
       }
-      rb[e] = v;
-    }
-  };
-  auto store_tiles = [&](int stage) {
-    Acc* as = As + stage * BK * ALD;
-    Acc* bs = Bs + stage * BK * BLD;
+    };
+    auto store_tiles = [&](int stage) {
+      Acc* as = As + stage * BK * ALD;
+      Acc* bs = Bs + stage * BK * BLD;
 #pragma unroll
-    for (int e = 0; e < A_PER; ++e) {
-      const int idx = tid + e * 256;
-      int ii, kk;
-      if (TA) { kk = idx % BK; ii = idx / BK; } else { ii = idx % BM; kk = idx / BM; }
-      as[kk * ALD + ii] = (Acc)(alpha * (double)ra[e]);
-    }
-#pragma unroll
-    for (int e = 0; e < B_PER; ++e) {
-      const int idx = tid + e * 256;
-      int jj, kk;
-      if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
-      bs[kk * BLD + jj] = (Acc)rb[e];
-    }
-  };
-
-  if (kbeg < kend) {
-    load_tiles(kbeg);
-    store_tiles(0);
-    __syncthreads();
-    int stage = 0;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-      const bool more = k0 + BK < kend;
-      if (more) load_tiles(k0 + BK);
-      const Acc* as = As + stage * BK * ALD;
-      const Acc* bs = Bs + stage * BK * BLD;
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        Acc af[TM], bf[TN];
-#pragma unroll
-        for (int a = 0; a < TM; ++a) af[a] = as[(kk + (lane >> 4)) * ALD + wm * WTM + a * 16 + (lane & 15)];
-#pragma unroll
-        for (int b = 0; b < TN; ++b) bf[b] = bs[(kk + (lane >> 4)) * BLD + wn * WTN + b * 16 + (lane & 15)];
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-          for (int b = 0; b < TN; ++b)
-          {
-            if constexpr (std::is_same<Acc, double>::value)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
-            else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[b], af[a], acc[a][b], 0, 0, 0);
-          }
+      for (int e = 0; e < A_PER; ++e) {
+        const int idx = tid + e * 256;
+        int ii, kk;
+        if (TA) { kk = idx % BK; ii = idx / BK; } else { ii = idx % BM; kk = idx / BM; }
+        as[kk * ALD + ii] = (Acc)(alpha * (double)ra[e]);
       }
-      if (more) store_tiles(stage ^ 1);
+#pragma unroll
+      for (int e = 0; e < B_PER; ++e) {
+        const int idx = tid + e * 256;
+        int jj, kk;
+        if (TB) { jj = idx % BN; kk = idx / BN; } else { kk = idx % BK; jj = idx / BK; }
+        bs[kk * BLD + jj] = (Acc)rb[e];
+      }
+    };
+    if (kbeg < kend) {
+      load_tiles(kbeg);
+      store_tiles(0);
       __syncthreads();
-      stage ^= 1;
+      int stage = 0;
+      for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+        const bool more = k0 + BK < kend;
+        if (more) load_tiles(k0 + BK);
+        const Acc* as = As + stage * BK * ALD;
+        const Acc* bs = Bs + stage * BK * BLD;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          Acc af[TM], bf[TN];
+#pragma unroll
+          for (int a = 0; a < TM; ++a) af[a] = as[(kk + (lane >> 4)) * ALD + wm * WTM + a * 16 + (lane & 15)];
+#pragma unroll
+          for (int b = 0; b < TN; ++b) bf[b] = bs[(kk + (lane >> 4)) * BLD + wn * WTN + b * 16 + (lane & 15)];
+#pragma unroll
+          for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+              if constexpr (std::is_same<Acc, double>::value)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+              else
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[b], af[a], acc[a][b], 0, 0, 0);
+            }
+        }
+        if (more) store_tiles(stage ^ 1);
+        __syncthreads();
+        stage ^= 1;
+      }
     }
   }
 
@@ -227,12 +343,11 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, doubl
 // leaves CUs free for a kernel running beside it on another stream.
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename TAe = double, typename TBe = double,
           typename Acc = double, bool PAIR = false, bool PERSIST = false>
-__global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
-                                                   const TAe* __restrict__ A, int64_t lda,
-                                                   const TBe* __restrict__ B, int64_t ldb, double beta,
-                                                   double* __restrict__ C, int64_t ldc, int64_t kchunk,
-                                                   int64_t split_stride, const TBe* __restrict__ B2, int64_t ldb2,
-                                                   int64_t nsplit, int64_t persist_tiles_x, int64_t persist_tiles) {
+__global__ void __launch_bounds__(256, 2)
+    gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const TAe* __restrict__ A, int64_t lda,
+                const TBe* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
+                int64_t kchunk, int64_t split_stride, const TBe* __restrict__ B2, int64_t ldb2, int64_t nsplit,
+                int64_t persist_tiles_x, int64_t persist_tiles) {
   if constexpr (PERSIST) {
     for (int64_t t = blockIdx.x; t < persist_tiles; t += gridDim.x) {
       gemm_tile<BM, BN, BK, WM, WN, TA, TB, TAe, TBe, Acc, PAIR>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
@@ -253,7 +368,8 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(int64_t M, int64_t N, int6
 // its tile t - tile0: chunk z = (t - tile0) / ntile of the reduction (split
 // K, partial products to C + z split_stride), then row-major tile order.
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, typename Acc>
-__global__ void __launch_bounds__(256, 2) gemm_grouped_kernel(const GroupedGemm* __restrict__ probs,
+__global__ void __launch_bounds__(256, 2)
+    gemm_grouped_kernel(const GroupedGemm* __restrict__ probs,
                                                            const int* __restrict__ tile_prob, int64_t ntiles) {
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int pi = __builtin_amdgcn_readfirstlane(tile_prob[t]);

@@ -121,7 +121,9 @@ int launch_apply_swaps_f32(hipStream_t s, const int* piv, int bJ, int64_t offset
                            int64_t rows);
 
 // Householder panel QR (in-place layout), tau, explicit unit-lower Y, one
-// column at a time.  With `gate` set, the kernel runs only if *gate != 0.
+// column at a time.  With `gate` set, the kernel runs only if *gate != 0;
+// with copy_y as well, a launch whose gate is 0 (the CholeskyQR panel
+// succeeded) copies Y(bJ:mJ, :) into P(bJ:mJ, :) instead.
 struct PanelWork {
   double* slots;       // bmax * 256 * 64 + bmax * 64 doubles
   unsigned* flags;     // 256 words (zeroed by the caller)
@@ -132,13 +134,7 @@ size_t panel_slot_elems(int64_t mmax, int bmax);
 // launch_panel's return value when its workgroups cannot all be resident.
 constexpr int RQ_PANEL_TOO_TALL = RQ_ERR_HIP_BASE + (int)hipErrorCooperativeLaunchTooLarge;
 int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, double* tau, double* Y, int64_t ldy,
-                 const PanelWork& w);
-
-// T (bJ x bJ, ld bJ) from G = Y^T Y (ld bJ) and tau (forward columnwise recurrence).
-int launch_larft(hipStream_t s, int bJ, const double* G, const double* tau, double* T);
-// Same, forming G = Y^T Y itself; runs only if *gate != 0 (fallback path).
-int launch_larft_gated(hipStream_t s, int64_t mJ, int bJ, const double* Y, int64_t ldy, const double* tau, double* T,
-                       const int* gate);
+                 const PanelWork& w, bool copy_y);
 
 // Panel by CholeskyQR2 + Householder reconstruction (see cholqr.hip).
 size_t cholqr_scratch_elems(int64_t mmax, int bmax);
@@ -146,10 +142,14 @@ int launch_panel_cholqr(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int b
                         int64_t scs, double* tau, double* Y, int64_t ldy, double* T, double* scratch,
                         double* splitk, size_t splitk_elems, int* st, double* W11 = nullptr);
 
-// W11 = S11 R11^{-1} (upper triangular, ld bJ); zero-diagonal columns of R11 give 0.
-// S11(i, j) = S[i*srs + j*scs].
-int launch_w11(hipStream_t s, int bJ, const double* S, int64_t srs, int64_t scs, const double* R, int64_t ldr,
-               double* W, const int* st = nullptr);
+// After the column panel (runs only if *st != 0, i.e. the CholeskyQR panel
+// failed): T (bJ x bJ, ld bJ) of the panel's reflectors from Y (mJ x bJ, ld
+// ldy) and tau, and, with W non-null, W11 = S11 R11^{-1} (upper triangular,
+// ld bJ; zero-diagonal columns of R11 give 0), S11(i, j) = S[i*srs + j*scs],
+// R11 the panel's R (ld ldr).
+int launch_fallback_tail(hipStream_t s, int64_t mJ, int bJ, const double* Y, int64_t ldy, const double* tau,
+                         double* T, const int* st, const double* S, int64_t srs, int64_t scs, const double* R,
+                         int64_t ldr, double* W);
 
 // Small utilities.
 int launch_fill(hipStream_t s, void* p, size_t words32);  // zero-fill 32-bit words

@@ -33,8 +33,47 @@ struct PanelParams {
   unsigned* flags;
   int* err;
   const int* gate;
+  int copy_y;  // with gate: a launch whose gate is 0 copies Y(bJ:mJ, :) into P
   int NP;
 };
+
+// Rows per workgroup of the copy of Y(b:mJ, :) into P(b:mJ, :).
+constexpr int CP_ROWS = 64;
+
+// Y -> P for rows [r0, r1) (r0 >= b, r1 - r0 <= CP_ROWS), by the NT threads
+// of one workgroup, consecutive threads on consecutive rows; every load of
+// the thread is issued before its first store.
+template <int NT>
+__device__ __forceinline__ void copy_y_rows(const PanelParams& a, int64_t r0, int64_t r1) {
+  constexpr int PER = CP_ROWS * 64 / NT;
+  const int rows = (int)(r1 - r0);  // at most CP_ROWS
+  if (rows <= 0) return;
+  const int tot = rows * a.bJ;
+  double v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = (int)threadIdx.x + q * NT;
+    const int j = e / rows, i = e - j * rows;
+    v[q] = (e < tot) ? a.Y[r0 + i + j * a.ldy] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = (int)threadIdx.x + q * NT;
+    const int j = e / rows, i = e - j * rows;
+    if (e < tot) a.P[r0 + i + j * a.ldp] = v[q];
+  }
+}
+
+// The copy alone, for panels too tall for the column panel's grid: runs only
+// if *gate is 0.
+__global__ void __launch_bounds__(256) ycopy_gated_kernel(PanelParams a) {
+  __shared__ int s_gate;
+  if (threadIdx.x == 0) s_gate = *a.gate;
+  __syncthreads();
+  if (s_gate != 0) return;
+  const int64_t q = blockIdx.x;
+  copy_y_rows<256>(a, std::max<int64_t>(q * CP_ROWS, a.bJ), std::min<int64_t>(a.mJ, q * CP_ROWS + CP_ROWS));
+}
 
 __global__ void __launch_bounds__(PN_THREADS) panel_kernel(PanelParams a) {
   __shared__ double xs[PN_RB];
@@ -54,8 +93,14 @@ __global__ void __launch_bounds__(PN_THREADS) panel_kernel(PanelParams a) {
     __shared__ int s_gate;
     if (threadIdx.x == 0) s_gate = *a.gate;
     __syncthreads();
-    if (s_gate == 0) return;
+    if (s_gate == 0) {  // the CholeskyQR panel succeeded: workgroup q copies its CP_ROWS rows
+      const int64_t q = me;
+      if (a.copy_y)
+        copy_y_rows<PN_THREADS>(a, std::max<int64_t>(q * CP_ROWS, bJ), std::min<int64_t>(a.mJ, q * CP_ROWS + CP_ROWS));
+      return;
+    }
   }
+  if (me >= a.NP) return;  // workgroups beyond the column panel's (they serve the copy)
   if (earlier_failure(a.err)) return;
 
   double v[PN_RPT];
@@ -160,7 +205,7 @@ size_t panel_slot_elems(int64_t mmax, int bmax) {
 }
 
 int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, double* tau, double* Y, int64_t ldy,
-                 const PanelWork& w) {
+                 const PanelWork& w, bool copy_y) {
   if (bJ <= 0 || mJ <= 0) return 0;
   if (bJ > 64) return -6;
   if (mJ >= (int64_t)1 << 31) return -3;
@@ -172,6 +217,7 @@ int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, doub
   a.flags = w.flags;
   a.err = w.err;
   a.gate = w.gate;
+  a.copy_y = (copy_y && w.gate) ? 1 : 0;
   // An ordinary launch, not a cooperative one: the kernel is the fallback of
   // the CholeskyQR panel and almost always leaves at its gate, before any
   // exchange, and a cooperative dispatch costs the queue tens of
@@ -189,8 +235,17 @@ int launch_panel(hipStream_t s, double* P, int64_t ldp, int64_t mJ, int bJ, doub
     RQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     resident = std::max(1, occ * cus);
   }
-  if (a.NP > resident) return RQ_PANEL_TOO_TALL;
-  hipLaunchKernelGGL(panel_kernel, dim3(a.NP), dim3(PN_THREADS), 0, s, a);
+  // the copy takes one workgroup per CP_ROWS rows; the column panel's
+  // workgroups are the first NP (the others leave at once when it runs)
+  const int64_t ncopy = a.copy_y ? (mJ + CP_ROWS - 1) / CP_ROWS : 0;
+  if (a.NP > resident) {
+    if (a.copy_y) {  // the copy still runs when the CholeskyQR panel succeeded
+      hipLaunchKernelGGL(ycopy_gated_kernel, dim3((unsigned)ncopy), dim3(256), 0, s, a);
+      RQ_HIP(hipGetLastError());
+    }
+    return RQ_PANEL_TOO_TALL;
+  }
+  hipLaunchKernelGGL(panel_kernel, dim3((unsigned)std::max<int64_t>(a.NP, ncopy)), dim3(PN_THREADS), 0, s, a);
   RQ_HIP(hipGetLastError());
   return 0;
 }

@@ -909,62 +909,6 @@ __global__ void __launch_bounds__(256) apply_swaps_kernel(const int* __restrict_
   if (jpvt && blockIdx.x == 0 && tid < np) jpvt[offset + dst[tid]] = itile[tid];
 }
 
-// ------------------------------------------------------------------ T factor
-// T[i,i] = tau_i;  T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]   (G = Y^T Y)
-__global__ void __launch_bounds__(64) larft_kernel(int bJ, const double* __restrict__ G, const double* __restrict__ tau,
-                                                   double* __restrict__ T) {
-  __shared__ double Gs[64 * 64];
-  __shared__ double Ts[64 * 64];
-  const int r = threadIdx.x;
-  for (int e = r; e < bJ * bJ; e += 64) { Gs[e] = G[e]; Ts[e] = 0.0; }
-  __syncthreads();
-  for (int i = 0; i < bJ; ++i) {
-    const double ti = tau[i];
-    if (r < i) {
-      double h = 0.0;
-      for (int q = r; q < i; ++q) h += Ts[r + q * bJ] * Gs[q + i * bJ];
-      Ts[r + i * bJ] = -ti * h;
-    } else if (r == i) {
-      Ts[i + i * bJ] = ti;
-    }
-    __syncthreads();
-  }
-  for (int e = r; e < bJ * bJ; e += 64) T[e] = Ts[e];
-}
-
-// Fallback T: G = Y^T Y accumulated by one workgroup, then the recurrence.
-__global__ void __launch_bounds__(256) larft_gated_kernel(int64_t mJ, int bJ, const double* __restrict__ Y,
-                                                          int64_t ldy, const double* __restrict__ tau,
-                                                          double* __restrict__ T, const int* gate) {
-  __shared__ double Gs[64 * 64];
-  __shared__ double Ts[64 * 64];
-  __shared__ int s_gate;
-  if (threadIdx.x == 0) s_gate = *gate;
-  __syncthreads();
-  if (s_gate == 0) return;
-  for (int e = threadIdx.x; e < bJ * bJ; e += 256) {
-    const int i = e % bJ, j = e / bJ;
-    double acc = 0.0;
-    if (i <= j)
-      for (int64_t r = 0; r < mJ; ++r) acc += Y[r + i * ldy] * Y[r + j * ldy];
-    Gs[e] = acc;
-    Ts[e] = 0.0;
-  }
-  __syncthreads();
-  for (int i = 0; i < bJ; ++i) {
-    const int r = threadIdx.x;
-    if (r < i) {
-      double h = 0.0;
-      for (int q = r; q < i; ++q) h += Ts[r + q * bJ] * Gs[q + i * bJ];
-      Ts[r + i * bJ] = -tau[i] * h;
-    } else if (r == i) {
-      Ts[i + i * bJ] = tau[i];
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < bJ * bJ; e += 256) T[e] = Ts[e];
-}
-
 // ------------------------------------------------------------------ utilities
 __global__ void fill_kernel(unsigned* p, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1066,19 +1010,6 @@ int launch_apply_swaps_f32(hipStream_t s, const int* piv, int bJ, int64_t offset
   const unsigned grid = std::max<unsigned>(1u, blocks_for(rows, SW_ROWS));
   hipLaunchKernelGGL(apply_swaps_kernel<float>, dim3(grid), dim3(256), 0, s, piv, bJ, offset, M, ldm, rows,
                      (int64_t*)nullptr);
-  RQ_HIP(hipGetLastError());
-  return 0;
-}
-
-int launch_larft(hipStream_t s, int bJ, const double* G, const double* tau, double* T) {
-  hipLaunchKernelGGL(larft_kernel, dim3(1), dim3(64), 0, s, bJ, G, tau, T);
-  RQ_HIP(hipGetLastError());
-  return 0;
-}
-
-int launch_larft_gated(hipStream_t s, int64_t mJ, int bJ, const double* Y, int64_t ldy, const double* tau, double* T,
-                       const int* gate) {
-  hipLaunchKernelGGL(larft_gated_kernel, dim3(1), dim3(256), 0, s, mJ, bJ, Y, ldy, tau, T, gate);
   RQ_HIP(hipGetLastError());
   return 0;
 }
