@@ -485,11 +485,14 @@ bool gram_mode(int64_t M, int64_t N, int64_t K) { return M <= 64 && N <= 128 && 
 // Short-wide outputs with a long reduction (b x n products Y^T A, l x n
 // sketches Omega A): one row of tiles (64 x 64 up to 64 rows, 128 x 64 up
 // to 128, so that B is read once), up to WIDE_MAXS splits of at least
-// WIDE_MINK rows, aiming at about 2048 workgroups (eight per CU).
+// wide_mink(K) rows, aiming at about 2048 workgroups (eight per CU).  Short
+// reductions (the last blocks' Y^T A) take chunks down to 64 rows: there the
+// launch is latency-bound and more workgroups shorten it (at 512 rows, 27 ->
+// 10 us per product).
 constexpr int WIDE_MAXS = 16;
-constexpr int64_t WIDE_MINK = 256;
 
-static bool wide_mode(int64_t M, int64_t K) { return M <= 128 && K >= 1024; }
+static bool wide_mode(int64_t M, int64_t K) { return M <= 128 && K >= 256; }
+static int64_t wide_mink(int64_t K) { return K >= 2048 ? 256 : 64; }
 
 size_t gemm_scratch_elems(int64_t M, int64_t N, int64_t K) {
   size_t e = 0;
@@ -529,7 +532,7 @@ static int gemm_dispatch(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, 
     shape = (M <= 64) ? WIDE : BIG;
     const int64_t tiles = (N + 63) / 64;
     const int64_t want = (2048 + tiles - 1) / tiles;
-    const int64_t maxs = K / WIDE_MINK;
+    const int64_t maxs = K / wide_mink(K);
     splits = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, (int64_t)WIDE_MAXS}));
     while (splits > 1 && (size_t)splits * (size_t)M * (size_t)N > scratch_elems) --splits;
     kchunk = (K + splits - 1) / splits;
