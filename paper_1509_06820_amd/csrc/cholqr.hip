@@ -246,6 +246,48 @@ __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
   return *flag == 0;
 }
 
+// Lane src's value in every lane of the wave, through the LDS crossbar
+// (ds_bpermute: no memory access and no scalar registers, so a step's
+// broadcasts can all be in flight at once).
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const int addr = src << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// The 16 elimination steps of block k0 in wave 0 (lane r holds
+// A(r, k0:k0+16) in a).  FULL: every step of the block is an ordinary one
+// (p < b and p != mJ - 1), so the steps need no branches.
+template <bool FULL>
+__device__ __forceinline__ void lu_block_steps(double (&a)[SM_NB], int k0, int r, int b, int64_t mJ, double* sgn) {
+#pragma unroll
+  for (int i = 0; i < SM_NB; ++i) {
+    const int p = k0 + i;
+    if (FULL || p < b) {
+      // the pivot row's entries right of the pivot, from lane p
+      double u[SM_NB];
+#pragma unroll
+      for (int j = i + 1; j < SM_NB; ++j) u[j] = lane_bcast(a[j], p);
+      const double c0 = lane_val(a[i], p);
+      if (!FULL && p == mJ - 1) {
+        if (r == 0) sgn[p] = (c0 >= 0.0) ? 1.0 : -1.0;
+        if (r == p) a[i] = 0.0;
+      } else {
+        const double sg = (c0 >= 0.0) ? -1.0 : 1.0;
+        const double piv = 1.0 + fabs(c0);
+        const double f = -sg * rcp_nr(piv);
+        const double l = (r > p) ? a[i] * f : 0.0;  // L(r, p)
+        a[i] = (r > p) ? l : ((r == p) ? piv : a[i]);
+#pragma unroll
+        for (int j = i + 1; j < SM_NB; ++j) a[j] = fma(-l, u[j], a[j]);
+        if (r == 0) sgn[p] = sg;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // LU without pivoting of E - Q S on the top b x b block (in A, 64 x 64 LDS,
 // identity padded), with the sign choice of Householder reconstruction: at
 // step i with c0 = Q'(i, i), S_ii = -sign(c0) (sign(0) = +1), U(i, i) =
@@ -254,12 +296,11 @@ __device__ __forceinline__ bool sm_chol(double* G, int* flag) {
 // S_ii = sign(c0) and U(i, i) = 0.  On return A holds L (unit, below the
 // diagonal), U(i, i) on the diagonal and Q' above it; sgn[i] = S_ii.
 // Block k0: wave 0 eliminates the 16 columns k0..k0+15 with lane r holding
-// A(r, k0:k0+16) (steps without barriers, the pivot row's entries read with
-// v_readlane); then the row band U12 = L11^-1 A12 (rows k0..k0+15, the
+// A(r, k0:k0+16) (steps without barriers, the pivot row's entries taken by
+// ds_bpermute broadcasts); then the row band U12 = L11^-1 A12 (rows k0..k0+15, the
 // columns right of the block) by forward substitution, one thread per
 // column; then A22 -= L21 U12 on the matrix cores.
 __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_t mJ) {
-  __shared__ double prow[SM_NB];  // the pivot row's entries, for the broadcast reads
 #pragma unroll
   for (int k0 = 0; k0 < SM_N; k0 += SM_NB) {  // unrolled: every lane index below is a constant
     if (k0 >= b) break;
@@ -268,36 +309,11 @@ __device__ __forceinline__ void sm_lu_sign(double* A, double* sgn, int b, int64_
       double a[SM_NB];
 #pragma unroll
       for (int j = 0; j < SM_NB; ++j) a[j] = A[r + (k0 + j) * SM_LD];
-#pragma unroll
-      for (int i = 0; i < SM_NB; ++i) {
-        const int p = k0 + i;
-        if (p < b) {
-          // the pivot row's entries right of the pivot go through LDS: lane
-          // p stores them, every lane reads them at one address (in order
-          // within the wave)
-          if (r == p) {
-#pragma unroll
-            for (int j = i + 1; j < SM_NB; ++j) prow[j] = a[j];
-          }
-          __builtin_amdgcn_wave_barrier();
-          const double c0 = lane_val(a[i], p);
-          if (p == mJ - 1) {
-            if (r == 0) sgn[p] = (c0 >= 0.0) ? 1.0 : -1.0;
-            if (r == p) a[i] = 0.0;
-          } else {
-            const double sg = (c0 >= 0.0) ? -1.0 : 1.0;
-            const double piv = 1.0 + fabs(c0);
-            const double f = -sg * rcp_nr(piv);
-            const double l = (r > p) ? a[i] * f : 0.0;  // L(r, p)
-            a[i] = (r > p) ? l : ((r == p) ? piv : a[i]);
-#pragma unroll
-            for (int j = i + 1; j < SM_NB; ++j) a[j] = fma(-l, prow[j], a[j]);
-            if (r == 0) sgn[p] = sg;
-          }
-          __builtin_amdgcn_wave_barrier();
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      const bool full = k0 + SM_NB <= b && !(mJ - 1 >= k0 && mJ - 1 < k0 + SM_NB);
+      if (full)
+        lu_block_steps<true>(a, k0, r, b, mJ, sgn);
+      else
+        lu_block_steps<false>(a, k0, r, b, mJ, sgn);
 #pragma unroll
       for (int j = 0; j < SM_NB; ++j)
         if (r >= k0) A[r + (k0 + j) * SM_LD] = a[j];
@@ -562,13 +578,25 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
   // pivot is 0.
   sm_lu_sign(A, sgn, b, mJ);
   // C = U (U(i, j) = -S_jj Q'(i, j) above the diagonal, pivots on it);
-  // A keeps L1 below the diagonal.  Padding stays identity.
-  for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
-    const int i = e % SM_N, j = e / SM_N;
-    double u;
-    if (i < b && j < b) u = (i < j) ? -sgn[j] * A[i + j * SM_LD] : (i == j ? A[i + i * SM_LD] : 0.0);
-    else u = (i == j) ? 1.0 : 0.0;
-    C[i + j * SM_LD] = u;
+  // A keeps L1 below the diagonal.  Padding stays identity.  (Thread (r, cg)
+  // reads its sixteen entries before it writes any: A and C are distinct,
+  // which the compiler cannot see.)
+  {
+    double av[SM_N / 4], sv[SM_N / 4];
+#pragma unroll
+    for (int q = 0; q < SM_N / 4; ++q) {
+      const int c = cg + 4 * q;
+      av[q] = A[r + c * SM_LD];
+      sv[q] = sgn[c];
+    }
+#pragma unroll
+    for (int q = 0; q < SM_N / 4; ++q) {
+      const int c = cg + 4 * q;
+      double u;
+      if (r < b && c < b) u = (r < c) ? -sv[q] * av[q] : (r == c ? av[q] : 0.0);
+      else u = (r == c) ? 1.0 : 0.0;
+      C[r + c * SM_LD] = u;
+    }
   }
   __syncthreads();
   // The four products that follow use only the factors above, so each
@@ -594,13 +622,19 @@ __global__ void __launch_bounds__(SM_T) recon_kernel(int b, int64_t mJ, const do
   if (task == 1) {
     // tau and T = U inv(Y1^T)
     for (int i = threadIdx.x; i < b; i += SM_T) tau[i] = C[i + i * SM_LD];
-    // D = Y1^T (unit upper) padded
-    for (int e = threadIdx.x; e < SM_N * SM_N; e += SM_T) {
-      const int i = e % SM_N, j = e / SM_N;
-      double v;
-      if (i < b && j < b) v = (i < j) ? A[j + i * SM_LD] : (i == j ? 1.0 : 0.0);
-      else v = (i == j) ? 1.0 : 0.0;
-      D[i + j * SM_LD] = v;
+    // D = Y1^T (unit upper) padded (reads before writes, as for C above)
+    {
+      double yv[SM_N / 4];
+#pragma unroll
+      for (int q = 0; q < SM_N / 4; ++q) yv[q] = A[(cg + 4 * q) + r * SM_LD];
+#pragma unroll
+      for (int q = 0; q < SM_N / 4; ++q) {
+        const int c = cg + 4 * q;
+        double v;
+        if (r < b && c < b) v = (r < c) ? yv[q] : (r == c ? 1.0 : 0.0);
+        else v = (r == c) ? 1.0 : 0.0;
+        D[r + c * SM_LD] = v;
+      }
     }
     __syncthreads();
     sm_tri_inv(D, A, B, &flag);   // A = inv(Y1^T) (unit diagonal: never singular)
