@@ -16,7 +16,7 @@ both mixed levels (`tuxv_c3*`: solves/s, p99, truncation error next to the
 oracle's and the optimum).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--no-extras] [--check]
+                    [--no-extras] [--check] [--no-lookahead]
 
 Other workloads (one JSON line each, same keys):
     --workload c2_lr        RQRCP of the 8192 x 8192 rank-512 product of
@@ -503,6 +503,9 @@ def main():
     ap.add_argument("--check", action="store_true", help="residual of the last factorization (untimed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--no-lookahead", action="store_true",
+                    help="run each block's trailing update right after its R12 instead of in the next sample "
+                         "QRCP's launch (the sample QRCP's own counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -518,6 +521,8 @@ def main():
     from paper_1509_06820_amd import binding, inputs
 
     torch.cuda.set_device(0)
+    if args.no_lookahead:
+        binding.rq_set_lookahead(False)
     if args.workload == "c3":
         run_c3(args)
         return

@@ -91,15 +91,11 @@ const char* rq_version(void);
 /*
  * Look-ahead switch for rq_rqrcp / rq_rqrcp_omega (host-side, process-wide;
  * on by default).  With it on, each block's trailing update below the new
- * rows of R runs on a second stream beside the sample update and the next
- * block's sample QRCP (which touch other data); the caller's stream waits
- * for it before the next block's column swaps, so the call still completes
- * in the caller's stream order.  The second stream is created by the
- * library, once per device, and shared by all calls on that device: every
- * call orders its own work on it with its own events, so concurrent calls
- * stay correct (their look-ahead updates only queue behind each other).
- * Off: every kernel on the caller's stream.  Results are bitwise the same
- * either way.  Returns the previous setting (0 or 1).
+ * rows of R runs in the next block's sample-QRCP launch, on workgroups of
+ * its own beside the sample QRCP's (which touches only the sample), instead
+ * of right after those rows; everything stays on the caller's stream, in
+ * its order.  Results are bitwise the same either way.  Returns the
+ * previous setting (0 or 1).
  */
 int rq_set_lookahead(int32_t on);
 

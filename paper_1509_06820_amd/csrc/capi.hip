@@ -257,51 +257,36 @@ int trailing_update(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t n,
 // ------------------------------------------------------------------ look-ahead
 // RQRCP's trailing update splits in two once W^T is known: the first bJ rows
 // (R12, which the sample update needs at once) and the rows below them,
-// which nothing reads until the next block's swaps.  The rows below run on a
-// second, library-owned stream per device, beside the sample update and the
-// next block's sample QRCP on the caller's stream; the caller's stream waits
-// for them right before those swaps.  rq_set_lookahead(0) keeps everything
-// on the caller's stream.
-hipStream_t bulk_stream() {
-  static std::mutex mu;
-  static hipStream_t streams[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-  std::lock_guard<std::mutex> lock(mu);
-  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
-    streams[dev] = nullptr;
-  return streams[dev];
-}
-
+// which nothing reads until the next block's swaps.  The rows below run in
+// the next block's sample-QRCP launch, on workgroups of their own beside the
+// sample QRCP's (which touches only the sample): one launch on the caller's
+// stream, ordered before the swaps like any other.  rq_set_lookahead(0) runs
+// them right after R12 instead.  The tiles are the same either way, so the
+// results are bitwise the same.
 std::atomic<int> g_lookahead{1};
 
 bool lookahead_enabled() { return g_lookahead.load(std::memory_order_relaxed) != 0; }
 
-struct Lookahead {
-  hipStream_t s2 = nullptr;
-  hipEvent_t ready = nullptr;  // W^T and R12 formed (recorded on the caller's stream)
-  hipEvent_t done = nullptr;   // the rows below R12 updated (recorded on s2)
-  bool ok = false;
-  explicit Lookahead(bool want) {
-    if (!want || !lookahead_enabled()) return;
-    s2 = bulk_stream();
-    if (!s2) return;
-    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return;
-    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) return;
-    ok = true;
+// Workgroups of the update beside a sample QRCP of nJ columns: the CUs the
+// sample QRCP leaves, less a margin of 16 (at 32 sample-QRCP workgroups,
+// 208 and 224 update workgroups gave 88.5 ms per 8192 x 8192 factorization
+// on two streams, 240 gave 101 ms, a full grid 90.6 ms).
+int64_t beside_update_workgroups(int64_t nJ) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
   }
-  ~Lookahead() {
-    if (ready) (void)hipEventDestroy(ready);
-    if (done) (void)hipEventDestroy(done);
-  }
-  Lookahead(const Lookahead&) = delete;
-  Lookahead& operator=(const Lookahead&) = delete;
-};
+  return std::max<int64_t>(cus / 4, cus - sample_qrcp_workgroups(nJ) - 16);
+}
 
-// Trailing update with look-ahead: W^T = T^T (Y^T C) and R12 on s, the rows
-// below R12 on la.s2 after them (the event la.done marks their end).
-int trailing_update_split(hipStream_t s, const Lookahead& la, double* A, int64_t lda, int64_t m, int64_t n,
-                          int64_t i0, int bJ, const double* Y, int64_t ldy, const BlockBufs& bb, bool mixed) {
+// Trailing update with look-ahead: W^T = T^T (Y^T C) and R12 on s; the rows
+// below R12 are described in `later` for the next sample QRCP's launch
+// (later.M = 0: nothing left).
+int trailing_update_split(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t n, int64_t i0, int bJ,
+                          const double* Y, int64_t ldy, const BlockBufs& bb, bool mixed, BesideUpdate& later) {
   const int64_t mJ = m - i0, Nt = n - i0 - bJ;
   double* C = A + i0 + (i0 + bJ) * lda;
   const double dm = (double)mJ, dn = (double)Nt, db = (double)bJ;
@@ -315,27 +300,15 @@ int trailing_update_split(hipStream_t s, const Lookahead& la, double* A, int64_t
     ProfScope ps(PC_GEMM_UPDATE, s, 8.0 * (2.0 * db * dn + db * db + db * dn), 2.0 * db * dn * db);
     RQ_TRY(gemm_prec(s, mixed, false, false, bJ, Nt, bJ, -1.0, Y, ldy, bb.wt, bJ, 1.0, C, lda, nullptr, 0));
   }
-  RQ_HIP(hipEventRecord(la.ready, s));
-  RQ_HIP(hipStreamWaitEvent(la.s2, la.ready, 0));
-  if (mJ > bJ) {
-    const double dr = dm - db;
-    ProfScope ps(PC_GEMM_UPDATE, la.s2, 8.0 * (2.0 * dr * dn + dr * db + db * dn), 2.0 * dr * dn * db);
-    // a persistent grid that leaves the next sample QRCP's workgroups CUs of
-    // their own (plus a margin of 16: at 32 sample-QRCP workgroups, 208 and
-    // 224 update workgroups gave 88.5 ms per 8192 x 8192 factorization, 240 gave
-    // 101 ms, a full grid 90.6 ms)
-    static int cus = 0;
-    if (!cus) {
-      int dev = 0;
-      if (hipGetDevice(&dev) != hipSuccess ||
-          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
-    }
-    const int64_t wgs = std::max<int64_t>(cus / 4, cus - sample_qrcp_workgroups(Nt) - 16);
-    RQ_TRY(launch_gemm_persistent(la.s2, mJ - bJ, Nt, bJ, -1.0, Y + bJ, ldy, bb.wt, bJ, 1.0, C + bJ, lda, (int)wgs,
-                                  mixed));
+  later = BesideUpdate();
+  if (mJ > bJ && Nt > 0) {
+    later.M = mJ - bJ; later.N = Nt; later.K = bJ;
+    later.A = Y + bJ; later.lda = ldy;
+    later.B = bb.wt; later.ldb = bJ;
+    later.C = C + bJ; later.ldc = lda;
+    later.f32 = mixed;
+    later.wgs = beside_update_workgroups(Nt);
   }
-  RQ_HIP(hipEventRecord(la.done, la.s2));
   return 0;
 }
 
@@ -407,8 +380,8 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
   const int l = b + p;
   RQ_TRY(launch_fill(s, f.c.flags, f.c.flag_words));
   if (pivoting) RQ_TRY(launch_iota(s, n, jpvt));
-  Lookahead la(pivoting && !resample && allow_lookahead);
-  bool bulk_pending = false;  // la.done guards A's rows below the last R12
+  const bool ahead = pivoting && !resample && allow_lookahead && lookahead_enabled();
+  BesideUpdate later;  // the previous block's rows below its R12, not yet updated
   if (pivoting && !resample) {
     const double* Om = Omega;
     int64_t ldom = ldo;
@@ -437,12 +410,11 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
       }
       if (!resample) RQ_TRY(dump_sample(s, s_blk, f.sb.ls, l, nJ, dump_off));
       {
+        // (with the previous block's rows below R12 updated in the same launch)
         ProfScope ps(PC_SAMPLE_QRCP, s, 16.0 * l * nJ, sample_qrcp_flops(l, nJ, bJ));
-        RQ_TRY(launch_sample_qrcp(s, s_blk, f.sb.ls, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J)));
-      }
-      if (bulk_pending) {
-        RQ_HIP(hipStreamWaitEvent(s, la.done, 0));
-        bulk_pending = false;
+        RQ_TRY(launch_sample_qrcp(s, s_blk, f.sb.ls, l, nJ, bJ, f.sb.piv, f.c.info, (int)i0, sq_work(f.sb, f.c, J),
+                                  later.M > 0 ? &later : nullptr));
+        later = BesideUpdate();
       }
       ProfScope ps(PC_SWAP, s, 32.0 * m * bJ, 0.0);
       RQ_TRY(launch_apply_swaps(s, f.sb.piv, bJ, i0, A, lda, m, jpvt));
@@ -450,16 +422,18 @@ int factor_impl(hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda, int
     const bool upd = pivoting && !resample && i0 + bJ < k;
     RQ_TRY(panel_and_t(s, A, lda, m, i0, bJ, tau + i0, f.ybuf, m, f.bb, f.c, J, s_blk, 1, f.sb.ls,
                        upd ? f.sb.w11 : nullptr));
-    if (upd && la.ok) {
-      RQ_TRY(trailing_update_split(s, la, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb, mixed));
-      bulk_pending = true;
+    if (upd && ahead) {
+      RQ_TRY(trailing_update_split(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb, mixed, later));
     } else {
       RQ_TRY(trailing_update(s, A, lda, m, n, i0, bJ, f.ybuf, m, f.bb, mixed));
     }
     if (upd) RQ_TRY(sample_update(s, A, lda, n, i0, bJ, s_blk, f.sb));
     i0 += bJ;
   }
-  if (bulk_pending) RQ_HIP(hipStreamWaitEvent(s, la.done, 0));
+  if (later.M > 0) {  // (every update is taken by the next block's sample QRCP; this ends any other loop)
+    RQ_TRY(gemm_prec(s, later.f32, false, false, later.M, later.N, later.K, -1.0, later.A, later.lda, later.B,
+                     later.ldb, 1.0, later.C, later.ldc, nullptr, 0));
+  }
   if (info) {
     hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, f.c.err, f.c.info, info);
     RQ_HIP(hipGetLastError());

@@ -27,13 +27,6 @@ int launch_gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K
                 size_t scratch_elems);
 // C (M x 2 N1, ldc) = alpha A^T [B1 B2] + beta C, with A K x M and B1, B2 K x N1
 // (separate arrays): one launch for M, N1 <= 64.
-// C = alpha A B + beta C (no transposes) with 128 x 64 tiles on a grid of at
-// most `wgs` workgroups that walk the tiles, so that the launch leaves CUs
-// free for a kernel beside it.
-// With f32, the products on the FP32 matrix cores (added to FP64 C).
-int launch_gemm_persistent(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
-                           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int wgs,
-                           bool f32 = false);
 int launch_gemm_pair(hipStream_t s, int64_t M, int64_t N1, int64_t K, double alpha, const double* A, int64_t lda,
                      const double* B1, int64_t ldb1, const double* B2, int64_t ldb2, double beta, double* C,
                      int64_t ldc, double* scratch, size_t scratch_elems);
@@ -109,8 +102,23 @@ size_t sample_qrcp_theta_elems();
 // past l zero).
 // Workgroups of the sample QRCP on a sample of nJ columns (all resident at once).
 int sample_qrcp_workgroups(int64_t nJ);
+// With upd: the same launch also runs the trailing update C -= A B (M x N,
+// reduction K; A ld lda, B ld ldb, C ld ldc; the products on the FP32 matrix
+// cores with f32) on `wgs` more workgroups -- the previous block's rows below
+// its R12, which the sample QRCP does not touch.
+struct BesideUpdate {
+  int64_t M = 0, N = 0, K = 0;
+  const double* A = nullptr;
+  int64_t lda = 0;
+  const double* B = nullptr;
+  int64_t ldb = 0;
+  double* C = nullptr;
+  int64_t ldc = 0;
+  bool f32 = false;
+  int64_t wgs = 0;
+};
 int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ, int bJ, int* piv, int* info,
-                       int info_base, const SampleQrcpWork& w);
+                       int info_base, const SampleQrcpWork& w, const BesideUpdate* upd = nullptr);
 
 // Apply the sequential swaps (offset+t) <-> (offset+piv[t]), t < bJ, to the
 // columns of an R x ncols matrix (double) and optionally to an int64 vector.

@@ -10,6 +10,7 @@
 #include <float.h>
 #include <type_traits>
 #include "kernels.hpp"
+#include "gemm_tile.hpp"
 
 namespace rq {
 
@@ -522,10 +523,10 @@ __device__ bool sq_barrier(const SqParams& a, unsigned round) {
 // never moved during the rounds; each thread tracks the logical position of
 // its slab column.
 template <int LMAX>
-__global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
+__device__ __forceinline__ void sample_qrcp_body(const SqParams& a, const int me) {
   extern __shared__ __align__(16) double smem[];
   SqLds<LMAX>& L = *reinterpret_cast<SqLds<LMAX>*>(smem);
-  const int me = blockIdx.x, tid = threadIdx.x, wv_id = tid / WAVE;
+  const int tid = threadIdx.x, wv_id = tid / WAVE;
   // the sequential pivot steps are the critical path: ahead of the waves of
   // a trailing update that may share the CU
   __builtin_amdgcn_s_setprio(3);
@@ -817,11 +818,77 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
 }
 
 template <int LMAX>
-int launch_sq(hipStream_t s, SqParams& a) {
+__global__ void __launch_bounds__(SQ_T) sample_qrcp_kernel(SqParams a) {
+  sample_qrcp_body<LMAX>(a, blockIdx.x);
+}
+
+// The trailing update C -= A B (M x N, reduction K = the block size) that
+// runs in the same launch as the next block's sample QRCP: workgroups P..
+// of the grid walk its 128 x 64 tiles, the first P run the sample QRCP.  One
+// launch on one stream orders both before the next block's swaps with no
+// event between streams, and the tiles compute exactly what the ordinary
+// trailing-update launch computes.
+struct UpdParams {
+  int64_t M, N, K;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  int64_t tiles_x, tiles;
+};
+
+template <int LMAX, typename Acc>
+__global__ void __launch_bounds__(SQ_T) sample_qrcp_update_kernel(SqParams a, UpdParams u) {
+  if ((int)blockIdx.x < a.P) {
+    sample_qrcp_body<LMAX>(a, blockIdx.x);
+    return;
+  }
+  const int64_t wg = (int64_t)blockIdx.x - a.P, nwg = (int64_t)gridDim.x - a.P;
+  for (int64_t t = wg; t < u.tiles; t += nwg) {
+    gemm_tile<128, 64, 16, 2, 2, false, false, double, double, Acc, false>(
+        u.M, u.N, u.K, -1.0, u.A, u.lda, u.B, u.ldb, 1.0, u.C, u.ldc, u.K, 0, nullptr, 0, 0, t % u.tiles_x,
+        t / u.tiles_x, 0);
+    __syncthreads();  // the next tile's LDS stores after every wave's last reads
+  }
+}
+
+template <int LMAX, typename Acc>
+int launch_sq_update(hipStream_t s, SqParams& a, const BesideUpdate& b) {
+  constexpr size_t lds = std::max(sizeof(SqLds<LMAX>), gemm_lds_bytes<128, 64, 16, Acc>());
+  static_assert(lds <= 160 * 1024, "LDS budget");
+  auto kern = sample_qrcp_update_kernel<LMAX, Acc>;
+  static int resident = 0;
+  if (!resident) {
+    RQ_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int occ = 0, dev = 0, cus = 0;
+    RQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, SQ_T, lds));
+    RQ_HIP(hipGetDevice(&dev));
+    RQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    resident = occ * cus;
+  }
+  UpdParams u;
+  u.M = b.M; u.N = b.N; u.K = b.K; u.A = b.A; u.lda = b.lda; u.B = b.B; u.ldb = b.ldb; u.C = b.C; u.ldc = b.ldc;
+  u.tiles_x = (b.N + 63) / 64;
+  u.tiles = u.tiles_x * ((b.M + 127) / 128);
+  const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>(b.wgs, u.tiles));
+  // every workgroup of the grid must be resident at once (the sample QRCP's
+  // wait on each other; the update's are dispatched after them)
+  if (a.P + wgs > resident) return RQ_ERR_HIP_BASE + (int)hipErrorCooperativeLaunchTooLarge;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(a.P + wgs)), dim3(SQ_T), lds, s, a, u);
+  RQ_HIP(hipGetLastError());
+  return 0;
+}
+
+template <int LMAX>
+int launch_sq(hipStream_t s, SqParams& a, const BesideUpdate* upd) {
   const int64_t P = (a.nJ + SQ_T - 1) / SQ_T;
   if (P > SQ_MAXP) return -4;  // n too large for this kernel
   a.P = (int)P;
   a.K = SQ_T / a.P;
+  if (upd && upd->M > 0 && upd->N > 0 && upd->K > 0)
+    return upd->f32 ? launch_sq_update<LMAX, float>(s, a, *upd) : launch_sq_update<LMAX, double>(s, a, *upd);
   constexpr size_t lds = sizeof(SqLds<LMAX>);
   static_assert(lds <= 160 * 1024, "LDS budget");
   // The P workgroups wait on each other, so all of them must be resident
@@ -978,18 +1045,18 @@ size_t sample_qrcp_theta_elems() { return 2 * (size_t)SQ_MAXP; }
 int sample_qrcp_workgroups(int64_t nJ) { return (int)((nJ + SQ_T - 1) / SQ_T); }
 
 int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ, int bJ, int* piv, int* info,
-                       int info_base, const SampleQrcpWork& w) {
+                       int info_base, const SampleQrcpWork& w, const BesideUpdate* upd) {
   if (bJ <= 0 || nJ <= 0) return 0;
   if (bJ > SQ_BMAX || bJ > nJ) return -5;
   if (lds != sample_rows_padded(l)) return -6;
   SqParams a;
   a.S = S; a.l = l; a.nJ = nJ; a.bJ = bJ; a.piv = piv; a.info = info; a.info_base = info_base;
   a.cand = w.cand; a.cand_idx = w.cand_idx; a.theta = w.theta; a.flags = w.flags; a.err = w.err;
-  if (l <= 32) return launch_sq<32>(s, a);
-  if (l <= 64) return launch_sq<64>(s, a);
-  if (l <= 72) return launch_sq<72>(s, a);
-  if (l <= 80) return launch_sq<80>(s, a);
-  if (l <= 128) return launch_sq<128>(s, a);
+  if (l <= 32) return launch_sq<32>(s, a, upd);
+  if (l <= 64) return launch_sq<64>(s, a, upd);
+  if (l <= 72) return launch_sq<72>(s, a, upd);
+  if (l <= 80) return launch_sq<80>(s, a, upd);
+  if (l <= 128) return launch_sq<128>(s, a, upd);
   return -7;
 }
 
