@@ -30,9 +30,12 @@
  * - Empty matrices: for m = 0 or n = 0 the factorizations write only jpvt
  *   (the identity) and info (0); rq_sketch with m = 0 writes B = 0.
  * - Limits of this version: 1 <= b <= 64, 0 <= p, b + p <= 128, n <= 65536,
- *   k <= 1024 for rq_tuxv and rq_tuxv_iter, and m small enough for the
- *   fallback panel's workgroups (one per 256 rows) to be resident together
- *   (checked at launch; about 10^5 rows on MI355X).
+ *   m <= RQ_MAX_ROWS (and m, n <= RQ_MAX_ROWS for rq_sketch and rq_omega, so
+ *   that no size computed by the library can overflow), k <= 1024 for
+ *   rq_tuxv and rq_tuxv_iter, and m small enough for the fallback panel's
+ *   workgroups (one per 256 rows) to be resident together (checked at
+ *   launch; about 10^5 rows on MI355X).  The size queries reject what the
+ *   entry points would reject.
  * - Pivot indices are 0-based int64.  jpvt[j] is the original index of column
  *   j of A P.
  */
@@ -82,6 +85,9 @@ enum {
  */
 enum { RQ_FP64 = 0, RQ_MIXED = 1, RQ_MIXED_BF16 = 2 };
 
+/* Largest row count (m) accepted by any entry point or size query. */
+#define RQ_MAX_ROWS ((int64_t)1 << 40)
+
 /* Largest j_max accepted by rq_tuxv_iter. */
 #define RQ_TUXV_MAX_ITER 64
 
@@ -103,7 +109,11 @@ int rq_set_lookahead(int32_t on);
  * Workspace size in bytes for operation `op` at the given sizes and
  * precision (host-only query, no GPU work).  k is ignored for RQ_OP_RQRCP,
  * RQ_OP_RSRQRCP and RQ_OP_QR; precision other than RQ_FP64 is accepted for
- * RQ_OP_RQRCP, RQ_OP_TRQRCP and RQ_OP_TUXV.
+ * RQ_OP_RQRCP, RQ_OP_TRQRCP and RQ_OP_TUXV.  For RQ_OP_SAMPLE_QRCP, m is
+ * the sample's row count l (1..128), n its column count and b the pivot
+ * steps (b <= l, b <= n); RQ_OP_SVD reads only k (1..1024; m, n, p are
+ * not used, b must still lie in 1..64).  Sizes beyond the limits of the
+ * entry points (m > RQ_MAX_ROWS, n > 65536) are rejected, never wrapped.
  * Arguments: 1 op, 2 m, 3 n, 4 k, 5 b, 6 p, 7 precision, 8 bytes (out, host).
  * Returns 0 on success or -i for an invalid argument i.
  */

@@ -17,7 +17,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librqrcp.so")
+# RQRCP_LIB selects another build of the same ABI (the host-sanitized one)
+LIB_PATH = os.environ.get("RQRCP_LIB") or os.path.join(_HERE, "librqrcp.so")
 
 (RQ_OP_RQRCP, RQ_OP_TRQRCP, RQ_OP_TUXV, RQ_OP_QR, RQ_OP_SAMPLE_QRCP, RQ_OP_SVD, RQ_OP_RSRQRCP) = range(7)
 RQ_FP64, RQ_MIXED, RQ_MIXED_BF16 = 0, 1, 2

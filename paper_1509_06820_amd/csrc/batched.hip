@@ -601,7 +601,7 @@ int check_items(const rq_batch_matrix* items, int32_t count, int64_t k, int32_t 
   if (precision != RQ_FP64 && precision != RQ_MIXED) return -6;
   for (int i = 0; i < count; ++i) {
     const rq_batch_matrix& it = items[i];
-    if (it.m < k || it.n < k || it.n > BT_NMAX) return -1;
+    if (it.m < k || it.m > RQ_MAX_ROWS || it.n < k || it.n > BT_NMAX) return -1;
     if (it.lda < it.m || it.ldu < it.m || it.ldvt < k) return -1;
     if (!it.A || !it.U || !it.sigma || !it.VT) return -1;
   }
@@ -641,6 +641,8 @@ size_t tiles_bound(const rq_batch_matrix* items, int32_t count, int64_t k, int b
     // the largest product of a matrix, in the smallest tiles (32 x 32)
     const int64_t tm = (m + 31) / 32, tn = (n + 31) / 32, tk = (k + 31) / 32, tl = (l + 31) / 32;
     t += (size_t)std::max({tl * tn, tk * tn, tm * tk, tn * tk, tk * tk * 16}) * calls;
+    // tile indices are 32-bit in the launches (each term is far below 2^62)
+    if (t > (size_t)INT32_MAX) return ~(size_t)0;
   }
   return t;
 }
@@ -660,7 +662,9 @@ size_t batch_bytes(const rq_batch_matrix* items, int32_t count, int64_t k, int b
     BMat M;
     carve_matrix(cv, items[i].m, items[i].n, k, b, l, M);
   }
-  return align_up(desc_bytes(count, k, b, tiles_bound(items, count, k, b, l)), 256) + cv.off + 256;
+  const size_t tiles = tiles_bound(items, count, k, b, l);
+  if (cv.overflowed() || tiles == ~(size_t)0) return ~(size_t)0;  // no workspace can be that large
+  return align_up(desc_bytes(count, k, b, tiles), 256) + cv.off + 256;
 }
 
 struct Builder {
@@ -781,7 +785,9 @@ int rq_batch_workspace_bytes(const rq_batch_matrix* items, int32_t count, int64_
   if (!bytes) return -7;
   int rc = check_items(items, count, k, b, p, precision);
   if (rc) return rc;
-  *bytes = batch_bytes(items, count, k, b, b + p);
+  const size_t need = batch_bytes(items, count, k, b, b + p);
+  if (need == ~(size_t)0) return -1;
+  *bytes = need;
   return 0;
 }
 
@@ -793,7 +799,9 @@ int rq_batch_plan_create(const rq_batch_matrix* items, int32_t count, int64_t k,
   if (rc) return rc;
   if (tile < 0 || tile >= GT_NCFG) return -7;
   const int l = b + p;
-  if (!work || work_bytes < batch_bytes(items, count, k, b, l)) return -9;
+  const size_t need = batch_bytes(items, count, k, b, l);
+  if (need == ~(size_t)0) return -1;
+  if (!work || work_bytes < need) return -9;
   rq_batch_plan* plan = new rq_batch_plan();
   plan->count = count;
   plan->k = k;

@@ -89,8 +89,8 @@ struct Common {
 void carve_common(Carve& cv, int64_t nblk, Common& c) {
   c.flag_words = (size_t)nblk * FLAG_STRIDE + 64;
   c.flags = cv.take<unsigned>(c.flag_words);
-  c.err = (int*)(c.flags + (size_t)nblk * FLAG_STRIDE);
-  c.info = c.err + 1;
+  c.err = (int*)carved_at(c.flags, (size_t)nblk * FLAG_STRIDE);
+  c.info = carved_at(c.err, 1);
 }
 
 struct SampleBufs {
@@ -734,7 +734,7 @@ int empty_result(hipStream_t s, int64_t n, int64_t* jpvt, int32_t* info) {
 
 // ------------------------------------------------------------------ argument checks
 int check_common(int64_t m, int64_t n, int64_t lda, int b, int p, int im, int in, int ilda, int ib, int ip) {
-  if (m < 0) return -im;
+  if (m < 0 || m > RQ_MAX_ROWS) return -im;
   if (n < 0) return -in;
   if (lda < std::max<int64_t>(1, m)) return -ilda;
   if (b < 1 || b > 64) return -ib;
@@ -800,6 +800,9 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
   if (p < 0 || b + p > 128) return -6;
   if (precision < RQ_FP64 || precision > RQ_MIXED_BF16) return -7;
   if (precision != RQ_FP64 && op != RQ_OP_RQRCP && op != RQ_OP_TRQRCP && op != RQ_OP_TUXV) return -7;
+  // the limits of the entry points (RQ_OP_SVD reads only k)
+  if (op != RQ_OP_SVD && m > RQ_MAX_ROWS) return -2;
+  if (op != RQ_OP_SVD && n > 65536) return -3;
   const bool mixed = precision != RQ_FP64;
   size_t sz = 0;
   switch (op) {
@@ -809,6 +812,7 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
       FactorWS f;
       Carve cv(nullptr, 0);
       carve_factor(cv, m, n, b, p, op != RQ_OP_QR, f);
+      if (cv.overflowed()) return -2;
       sz = cv.off;
       break;
     }
@@ -818,6 +822,7 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
       Carve cv(nullptr, 0);
       carve_trq(cv, m, n, k, b, p, t);
       if (mixed) t.a32 = cv.take<float>((size_t)m * n);
+      if (cv.overflowed()) return -2;
       sz = cv.off;
       break;
     }
@@ -826,11 +831,15 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
       TuxvWS t;
       Carve cv(nullptr, 0);
       carve_tuxv(cv, m, n, k, b, p, t, precision);
+      if (cv.overflowed()) return -2;
       sz = cv.off;
       break;
     }
     case RQ_OP_SAMPLE_QRCP: {
-      // m = l (sample rows), n = sample columns
+      // m = l (sample rows), n = sample columns, b = pivot steps
+      if (m < 1 || m > 128) return -2;
+      if (n < 1) return -3;
+      if (b > m || b > n) return -5;
       Carve cv(nullptr, 0);
       Common c;
       carve_common(cv, 1, c);
@@ -840,6 +849,7 @@ int rq_workspace_bytes(int32_t op, int64_t m, int64_t n, int64_t k, int32_t b, i
       break;
     }
     case RQ_OP_SVD: {
+      if (k < 1 || k > 1024) return -4;
       sz = align_up((size_t)k * k * sizeof(double), 256) + 4096;
       break;
     }
@@ -997,17 +1007,17 @@ int rq_tuxv_omega(void* stream, int64_t m, int64_t n, int64_t k, const double* A
 }
 
 int rq_omega(void* stream, uint64_t seed, int64_t l, int64_t m, double* Omega, int64_t ldo) {
-  if (l < 0) return -3;
-  if (m < 0) return -4;
-  if (!Omega && l * m > 0) return -5;
+  if (l < 0 || l > 65536) return -3;
+  if (m < 0 || m > RQ_MAX_ROWS) return -4;
+  if (!Omega && l > 0 && m > 0) return -5;
   if (ldo < std::max<int64_t>(1, l)) return -6;
   return launch_omega((hipStream_t)stream, seed, l, m, Omega, 1, ldo);
 }
 
 int rq_sketch(void* stream, int64_t m, int64_t n, const double* A, int64_t lda, int32_t l, uint64_t seed,
               int32_t precision, double* B, int64_t ldb, void* work, size_t work_bytes) {
-  if (m < 0) return -2;
-  if (n < 0) return -3;
+  if (m < 0 || m > RQ_MAX_ROWS) return -2;
+  if (n < 0 || n > RQ_MAX_ROWS) return -3;
   if (lda < std::max<int64_t>(1, m)) return -5;
   if (l < 1 || l > 128) return -6;
   if (precision < RQ_FP64 || precision > RQ_MIXED_BF16) return -8;

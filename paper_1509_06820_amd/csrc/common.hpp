@@ -226,14 +226,29 @@ struct Carve {
   size_t cap;
   bool ok;
   explicit Carve(void* b, size_t c) : base((char*)b), off(0), cap(c), ok(true) {}
+  // A request whose size overflows size_t saturates `off` (and fails `ok`),
+  // so a size query can never wrap round to a small number.
   template <class T>
   T* take(size_t count) {
+    constexpr size_t kMax = ~(size_t)0 - 511;
+    size_t bytes = 0;
+    if (off > kMax || __builtin_mul_overflow(count, sizeof(T), &bytes) || bytes > kMax - align_up(off, 256)) {
+      off = ~(size_t)0;
+      ok = false;
+      return nullptr;
+    }
     size_t o = align_up(off, 256);
-    size_t bytes = align_up(count * sizeof(T), 256);
+    bytes = align_up(bytes, 256);
     off = o + bytes;
     if (off > cap) ok = false;
     return base ? (T*)(base + o) : nullptr;
   }
+  bool overflowed() const { return off == ~(size_t)0; }
 };
+// p + k for a carved pointer: stays null in a size query (no arithmetic on null)
+template <class T>
+inline T* carved_at(T* p, size_t k) {
+  return p ? p + k : nullptr;
+}
 
 }  // namespace rq

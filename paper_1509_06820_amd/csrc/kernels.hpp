@@ -182,7 +182,7 @@ struct SvdWork {
   int* order;          // k
   unsigned* flags;
   int* err;
-  double* tmp;         // 2 * k * k
+  double* tmp;         // k * k
 };
 int launch_jacobi_svd(hipStream_t s, int k, double* X, int64_t ldx, double* U, int64_t ldu, double* sigma,
                       double* V, int64_t ldv, const SvdWork& w);

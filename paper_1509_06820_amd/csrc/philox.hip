@@ -39,31 +39,33 @@ __device__ __forceinline__ double u52(uint64_t x) {
   return ((double)(x >> 12) + 0.5) * 0x1.0p-52;
 }
 
-// One thread per Philox block (four consecutive stream positions).
-// Omega(r, c) is stored at out[r * rs + c * cs].
+// One thread per Philox block (four consecutive stream positions), grid-
+// stride so that any l * m fits a bounded grid.  Omega(r, c) is stored at
+// out[r * rs + c * cs].
 __global__ void __launch_bounds__(256) omega_kernel(uint64_t seed, uint64_t key1, int64_t l, int64_t m,
                                                      double* out, int64_t rs, int64_t cs) {
   const int64_t total = l * m;
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q * 4 >= total) return;
-  uint64_t w[4];
-  philox_block((uint64_t)q, seed, key1, w);
-  const double two_pi = 2.0 * M_PI;
-  double z[4];
-  const double r01 = sqrt(-2.0 * log(u52(w[0])));
-  const double r23 = sqrt(-2.0 * log(u52(w[2])));
-  const double a01 = two_pi * u52(w[1]);
-  const double a23 = two_pi * u52(w[3]);
-  z[0] = r01 * cos(a01);
-  z[1] = r01 * sin(a01);
-  z[2] = r23 * cos(a23);
-  z[3] = r23 * sin(a23);
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q * 4 < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t w[4];
+    philox_block((uint64_t)q, seed, key1, w);
+    const double two_pi = 2.0 * M_PI;
+    double z[4];
+    const double r01 = sqrt(-2.0 * log(u52(w[0])));
+    const double r23 = sqrt(-2.0 * log(u52(w[2])));
+    const double a01 = two_pi * u52(w[1]);
+    const double a23 = two_pi * u52(w[3]);
+    z[0] = r01 * cos(a01);
+    z[1] = r01 * sin(a01);
+    z[2] = r23 * cos(a23);
+    z[3] = r23 * sin(a23);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t t = q * 4 + i;
-    if (t < total) {
-      const int64_t r = t / m, c = t - r * m;
-      out[r * rs + c * cs] = z[i];
+    for (int i = 0; i < 4; ++i) {
+      const int64_t t = q * 4 + i;
+      if (t < total) {
+        const int64_t r = t / m, c = t - r * m;
+        out[r * rs + c * cs] = z[i];
+      }
     }
   }
 }
@@ -111,7 +113,7 @@ int launch_omega(hipStream_t s, uint64_t seed, int64_t l, int64_t m, double* out
                  uint64_t key1) {
   const int64_t blocks = (l * m + 3) / 4;
   if (blocks == 0) return 0;
-  const int64_t grid = (blocks + 255) / 256;
+  const int64_t grid = std::min<int64_t>((blocks + 255) / 256, 65536);
   hipLaunchKernelGGL(omega_kernel, dim3((unsigned)grid), dim3(256), 0, s, seed, key1, l, m, out, rs, cs);
   RQ_HIP(hipGetLastError());
   return 0;

@@ -1,4 +1,6 @@
-// Per-stage timing with HIP events (host side only).
+// Per-stage timing with HIP events, and roctx ranges (host side only).
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <mutex>
 #include <vector>
 
@@ -46,6 +48,17 @@ hipEvent_t get_event() {
 }  // namespace
 
 bool prof_enabled() { return g_on; }
+
+void prof_range_push(int cls) {
+  static const char* const kRange[PC_NCLASS] = {
+      "rq:omega",       "rq:sketch",        "rq:sample_qrcp",  "rq:swap",          "rq:panel",
+      "rq:tfactor",     "rq:gemm_yta",      "rq:gemm_update",  "rq:sample_update", "rq:trq_products",
+      "rq:tuxv_products", "rq:svd"};
+  static_assert(PC_NCLASS == 12, "one range name per stage class");
+  roctxRangePushA(cls >= 0 && cls < PC_NCLASS ? kRange[cls] : "rq:?");
+}
+
+void prof_range_pop() { roctxRangePop(); }
 
 static bool selected(int cls) { return cls >= 0 && cls < 32 && ((g_mask >> cls) & 1u); }
 

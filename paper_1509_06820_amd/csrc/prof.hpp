@@ -26,6 +26,10 @@ enum ProfClass {
 bool prof_enabled();
 void prof_begin(int cls, hipStream_t s);
 void prof_end(int cls, hipStream_t s, double bytes, double flops);
+// roctx range "rq:<stage>" around the host code that enqueues a stage (always
+// on: a no-op unless a tracing tool, e.g. rocprofv3 --marker-trace, listens)
+void prof_range_push(int cls);
+void prof_range_pop();
 
 struct ProfScope {
   int cls;
@@ -33,10 +37,12 @@ struct ProfScope {
   double bytes, flops;
   bool on;
   ProfScope(int c, hipStream_t st, double by, double fl) : cls(c), s(st), bytes(by), flops(fl), on(prof_enabled()) {
+    prof_range_push(cls);
     if (on) prof_begin(cls, s);
   }
   ~ProfScope() {
     if (on) prof_end(cls, s, bytes, flops);
+    prof_range_pop();
   }
 };
 

@@ -213,3 +213,67 @@ def test_noalloc_rejects_oversize_before_any_launch(lib):
     assert lib.rq_rqrcp_noalloc(null, m, n, null, m, b, p, 1, 0, null, null, null) == binding.RQ_ERR_SCRATCH_TOO_SMALL
     assert lib.rq_rqrcp_noalloc(null, -1, 4, null, 1, 8, 0, 1, 0, null, null, null) == -2
     assert lib.rq_rqrcp_noalloc(null, 4, 4, null, 4, 8, 0, 1, 7, null, null, null) == -9
+
+
+# sizes spanning the valid range, the limits and far past them (2^62)
+_SIZES = [0, 1, 7, 64, 65, 4096, 65536, 65537, 2 ** 31, 2 ** 40, 2 ** 40 + 1, 2 ** 62, -1]
+
+
+def test_workspace_queries_never_wrap(lib):
+    """Random and extreme arguments to rq_workspace_bytes: either a documented
+    argument error (-1 .. -8) or a size that holds at least the buffers every
+    path needs -- Omega (l x m) and the sample (l x n) for the sampled
+    factorizations, the FP32 copy of A (m x n) for mixed TRQRCP and TUXV, the
+    rotations (k x k) for the SVD -- so that no size query wraps round to a
+    small number (overflowed sizes once came back as a few MB)."""
+    import random
+    rng = random.Random(1509)
+    out = ctypes.c_size_t(0)
+    for _ in range(4000):
+        op = rng.choice([0, 1, 2, 3, 4, 5, 6, 7, -1])
+        m, n, k = (rng.choice(_SIZES) for _ in range(3))
+        b, p = rng.choice([0, 1, 8, 32, 64, 65]), rng.choice([0, 4, 8, 64, 100])
+        prec = rng.choice([0, 1, 2, 3])
+        out.value = 0
+        rc = lib.rq_workspace_bytes(op, m, n, k, b, p, prec, ctypes.byref(out))
+        if rc:
+            assert -8 <= rc <= -1, (op, m, n, k, b, p, prec, rc)
+            continue
+        nbytes, l = out.value, b + p
+        assert 0 < nbytes < 2 ** 62
+        if op in (binding.RQ_OP_RQRCP, binding.RQ_OP_RSRQRCP):
+            assert nbytes >= 8 * l * (m + n), (op, m, n, b, p)
+        elif op == binding.RQ_OP_TRQRCP or op == binding.RQ_OP_TUXV:
+            assert nbytes >= 8 * l * (m + n) + (4 * m * n if prec else 0), (op, m, n, k, b, p, prec)
+        elif op == binding.RQ_OP_SAMPLE_QRCP:
+            assert 1 <= m <= 128 and nbytes >= 8 * m * n
+        elif op == binding.RQ_OP_SVD:
+            assert nbytes >= 8 * k * k
+        elif op == binding.RQ_OP_QR:
+            assert m <= 2 ** 40 and n <= 65536
+
+
+def test_batch_workspace_query_never_wraps(lib):
+    """rq_batch_workspace_bytes over batches with huge or many matrices:
+    an error on the items, or a size covering every matrix's Omega (l x m)
+    and its Q, P, P2 (m x k each)."""
+    import random
+    rng = random.Random(6820)
+    for _ in range(300):
+        count = rng.choice([1, 2, 5, 40])
+        k, b, p = 32, 16, 8
+        shapes = [(rng.choice([32, 1000, 2 ** 20, 2 ** 40, 2 ** 40 + 1, 2 ** 62]),
+                   rng.choice([32, 500, 8192, 8193])) for _ in range(count)]
+        try:
+            nbytes = binding.batch_workspace_bytes(shapes, k, b, p)
+        except binding.RQError as e:
+            assert "returned -1" in str(e)
+            assert any(m > 2 ** 40 or n > 8192 for m, n in shapes) or nbytes_would_exceed(shapes, k)
+            continue
+        need = sum(8 * (b + p) * m + 3 * 8 * m * k for m, _ in shapes)
+        assert need <= nbytes < 2 ** 64
+
+
+def nbytes_would_exceed(shapes, k):
+    """More output tiles than 32-bit tile indices can address."""
+    return sum(((m + 31) // 32) * ((k + 31) // 32) for m, _ in shapes) > 2 ** 24
