@@ -189,10 +189,17 @@ __device__ __forceinline__ int wave_min_i(int v) {
 }
 
 // Wave-level (value, position) argmax: the largest value, ties to the lowest
-// position.  Values must not be NaN.  Uniform result.
+// position.  Values must not be NaN; every lane of the wave active.  Uniform
+// result.  The position is read from the first lane at the maximum; only
+// when lanes at the maximum disagree on it (equal values at different
+// positions) does a second reduction take the lowest.
 __device__ __forceinline__ void wave_argmax_vp(double v, int p, double& bv, int& bp) {
   bv = uni(wave_max(v));
-  bp = uni(wave_min_i((v == bv) ? p : INT_MAX));
+  const bool top = v == bv;
+  const int first = (int)__builtin_ctzll(__ballot(top));
+  const int p0 = __builtin_amdgcn_readlane(p, first);
+  if (__ballot(top && p != p0) == 0ull) bp = p0;
+  else bp = uni(wave_min_i(top ? p : INT_MAX));
 }
 
 // Quad lanes (tid & ~3 .. tid | 3) exchange values with DPP quad permutes.
@@ -611,11 +618,16 @@ __device__ __forceinline__ void sample_qrcp_body(const SqParams& a, const int me
     // about 64 eps * 10; the pivot's reflector always uses the exact norm
     // of its column.
     double alpha[4], nu[4], nu_ref[4];
+    // eg[c] = x[c][gi]: the rows 4 gi .. 4 gi + 3 of each column across the
+    // quad, the group that holds the next pivot row.  It gets the same update
+    // as x, so it is picked out of x (a branch tree) only when the pivot row
+    // enters a new group, once in four steps.
+    double eg[4];
+    int gi = t >> 2;
     {
-      double e[4];
-      sq_pick_rows<RQ, 0, RQ>(x, t >> 2, e);
+      sq_pick_rows<RQ, 0, RQ>(x, gi, eg);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) alpha[c] = quad_bcast(e[c], t & 3);
+      for (int c = 0; c < 4; ++c) alpha[c] = quad_bcast(eg[c], t & 3);
       sq_tail2<RQ>(x, q, t, nu);
 #pragma unroll
       for (int c = 0; c < 4; ++c) nu_ref[c] = nu[c];
@@ -638,15 +650,22 @@ __device__ __forceinline__ void sample_qrcp_body(const SqParams& a, const int me
       wave_argmax_vp(bv, bp, vwave, pwave);
       if ((tid & (WAVE - 1)) == 0) { L.rv[par][wv_id] = vwave; L.rp[par][wv_id] = pwave; }
       __syncthreads();
-      double v = uni(L.rv[par][0]);
-      int p = uni(L.rp[par][0]);
-#pragma unroll
-      for (int w = 1; w < SQ_T / WAVE; ++w) {
-        const double vw = uni(L.rv[par][w]);
-        const int pw = uni(L.rp[par][w]);
-        const bool bw = beats(vw, pw, v, p);
-        v = bw ? vw : v;
-        p = bw ? pw : p;
+      // the best of the four waves' results: a two-level tree (beats is a
+      // strict order, so the result is the one a sequential scan gives)
+      static_assert(SQ_T / WAVE == 4, "four waves per workgroup");
+      double v;
+      int p;
+      {
+        const double v0 = uni(L.rv[par][0]), v1 = uni(L.rv[par][1]);
+        const double v2 = uni(L.rv[par][2]), v3 = uni(L.rv[par][3]);
+        const int p0 = uni(L.rp[par][0]), p1 = uni(L.rp[par][1]);
+        const int p2 = uni(L.rp[par][2]), p3 = uni(L.rp[par][3]);
+        const bool b10 = beats(v1, p1, v0, p0), b32 = beats(v3, p3, v2, p2);
+        const double va = b10 ? v1 : v0, vb = b32 ? v3 : v2;
+        const int pa = b10 ? p1 : p0, pb = b32 ? p3 : p2;
+        const bool bba = beats(vb, pb, va, pa);
+        v = bba ? vb : va;
+        p = bba ? pb : pa;
       }
       if ((t > t0 && !(v > bound)) || p == INT_MAX) break;
       double* vt = L.vq + t * LMAX;
@@ -720,6 +739,14 @@ __device__ __forceinline__ void sample_qrcp_body(const SqParams& a, const int me
       __syncthreads();
       {
         const double tau = uni(L.taus[t]);
+        {
+          const int gn = (t + 1) >> 2;
+          if (gn != gi) {  // row t + 1 starts a new group (picked before this step's update)
+            gi = gn < RQ ? gn : RQ - 1;
+            sq_pick_rows<RQ, 0, RQ>(x, gi, eg);
+          }
+        }
+        const double vg = vt[q * RQ + gi];  // this lane's reflector entry in that group
         double vr[RQ];
         const double2* src = reinterpret_cast<const double2*>(vt + q * RQ);
 #pragma unroll
@@ -743,6 +770,8 @@ __device__ __forceinline__ void sample_qrcp_body(const SqParams& a, const int me
         for (int i = 0; i < RQ; ++i)
 #pragma unroll
           for (int c = 0; c < 4; ++c) x[c][i] = fma(-d[c], vr[i], x[c][i]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) eg[c] = fma(-d[c], vg, eg[c]);
         // downdate with the new row-t entries alpha - d (v[t] = 1)
         bool redo = false;
 #pragma unroll
@@ -758,10 +787,8 @@ __device__ __forceinline__ void sample_qrcp_body(const SqParams& a, const int me
           for (int c = 0; c < 4; ++c)
             if (!(nu[c] >= 0.1 * nu_ref[c])) { nu[c] = ex[c]; nu_ref[c] = ex[c]; }
         }
-        double e[4];
-        sq_pick_rows<RQ, 0, RQ>(x, (t + 1) >> 2, e);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) alpha[c] = quad_bcast(e[c], (t + 1) & 3);
+        for (int c = 0; c < 4; ++c) alpha[c] = quad_bcast(eg[c], (t + 1) & 3);
       }
       ++t;
     }
