@@ -93,7 +93,7 @@ struct SampleQrcpWork {
 };
 size_t sample_qrcp_flag_words();
 // Rows of the sample as the sample QRCP stores it (l rounded up to its
-// register tile: 32, 64, 72, 80 or 128; -1 if l > 128).
+// register tile: 32, 40, 48, 64, 72, 80 or 128; -1 if l > 128).
 int sample_rows_padded(int l);
 size_t sample_qrcp_cand_elems();
 size_t sample_qrcp_idx_elems();

@@ -40,6 +40,9 @@ struct SqParams {
 
 template <int LMAX>
 struct SqLds {
+  // the scan's row pairs (rows 8 i + 2 q, 8 i + 2 q + 1) and the steps'
+  // 16-byte reads of a quad lane's LMAX / 4 rows need LMAX to be a multiple of 8
+  static_assert(LMAX % 8 == 0 && LMAX <= SQ_LCAP, "sample register tile");
   double vlog[SQ_BMAX * LMAX];        // reflector of step t (zero above row t, one at row t)
   // Quad layout (row 4 i + q at [q * LMAX / 4 + i]): during a round, the
   // reflectors of its steps; at its end they are copied to vlog and their
@@ -1063,7 +1066,7 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 size_t sample_qrcp_flag_words() { return 128; }
 int sample_rows_padded(int l) {
-  return l <= 32 ? 32 : l <= 64 ? 64 : l <= 72 ? 72 : l <= 80 ? 80 : l <= 128 ? 128 : -1;
+  return l <= 32 ? 32 : l <= 40 ? 40 : l <= 48 ? 48 : l <= 64 ? 64 : l <= 72 ? 72 : l <= 80 ? 80 : l <= 128 ? 128 : -1;
 }
 size_t sample_qrcp_cand_elems() { return 2 * (size_t)SQ_LCAP * SQ_T; }
 size_t sample_qrcp_idx_elems() { return 2 * 2 * (size_t)SQ_T; }
@@ -1080,6 +1083,8 @@ int launch_sample_qrcp(hipStream_t s, double* S, int64_t lds, int l, int64_t nJ,
   a.S = S; a.l = l; a.nJ = nJ; a.bJ = bJ; a.piv = piv; a.info = info; a.info_base = info_base;
   a.cand = w.cand; a.cand_idx = w.cand_idx; a.theta = w.theta; a.flags = w.flags; a.err = w.err;
   if (l <= 32) return launch_sq<32>(s, a, upd);
+  if (l <= 40) return launch_sq<40>(s, a, upd);
+  if (l <= 48) return launch_sq<48>(s, a, upd);
   if (l <= 64) return launch_sq<64>(s, a, upd);
   if (l <= 72) return launch_sq<72>(s, a, upd);
   if (l <= 80) return launch_sq<80>(s, a, upd);
