@@ -111,6 +111,8 @@ def test_sketch_matches_oracle():
     (16, 20, 16),       # bsteps = l
     (9, 9, 9),          # square, every column pivoted
     (33, 40, 1),        # one step
+    (44, 900, 40),      # l in (40, 48]: the 48-row tile
+    (48, 5000, 48),     # l = 48, every row a pivot row
     (80, 3000, 64),     # l in (72, 80]
     (128, 700, 64),     # largest l (b + p = 128)
     (128, 65536, 64),   # largest l and n: 256 workgroups
@@ -183,6 +185,8 @@ def test_rqrcp_512_more_seeds(seed):
     (600, 500, 64, 64, 10),    # largest oversampling, l = b + p = 128
     (10, 300, 64, 8, 11),      # fewer rows than b and than l: one block of 10 steps
     (5000, 3, 64, 8, 12),      # tall and three columns
+    (900, 700, 40, 8, 13),     # l = 48: the 48-row sample tile
+    (700, 650, 36, 8, 14),     # l = 44 in the 48-row tile, ragged last block
 ])
 def test_rqrcp_shapes(m, n, b, p, seed):
     say(f"rqrcp {m}x{n} b={b} p={p} seed={seed}")
@@ -248,6 +252,7 @@ def test_unpivoted_qr_matches_oracle(m, n, b):
     (300, 400, 37, 16, 6, 2),
     (1200, 900, 128, 64, 8, 3),
     (200, 150, 150, 64, 8, 4),   # k = min(m, n)
+    (500, 400, 96, 32, 16, 5),   # l = 48 (the 48-row sample tile)
 ])
 def test_trqrcp_matches_oracle(m, n, k, b, p, seed):
     say(f"trqrcp {m}x{n} k={k} b={b} p={p}")
