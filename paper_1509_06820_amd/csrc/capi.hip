@@ -267,10 +267,11 @@ std::atomic<int> g_lookahead{1};
 
 bool lookahead_enabled() { return g_lookahead.load(std::memory_order_relaxed) != 0; }
 
-// Workgroups of the update beside a sample QRCP of nJ columns: the CUs the
-// sample QRCP leaves, less a margin of 16 (at 32 sample-QRCP workgroups,
-// 208 and 224 update workgroups gave 88.5 ms per 8192 x 8192 factorization
-// on two streams, 240 gave 101 ms, a full grid 90.6 ms).
+// Workgroups of the update beside a sample QRCP of nJ columns: every CU
+// the sample QRCP leaves (one workgroup per CU; the launch clamps this to
+// the places that are free).  Leaving 16 or 8 of them idle measured 0.4 and
+// 0.2 ms slower per 8192 x 8192 factorization: in the first blocks the
+// update is the longer of the two.
 int64_t beside_update_workgroups(int64_t nJ) {
   static int cus = 0;
   if (!cus) {
@@ -279,7 +280,7 @@ int64_t beside_update_workgroups(int64_t nJ) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 256;
   }
-  return std::max<int64_t>(cus / 4, cus - sample_qrcp_workgroups(nJ) - 16);
+  return std::max<int64_t>(1, cus - sample_qrcp_workgroups(nJ));
 }
 
 // Trailing update with look-ahead: W^T = T^T (Y^T C) and R12 on s; the rows

@@ -884,6 +884,11 @@ __global__ void __launch_bounds__(SQ_T) sample_qrcp_update_kernel(SqParams a, Up
   }
 }
 
+// launch_sq_update's answer when the sample QRCP's workgroups leave no
+// place for the update's (not an error code: every error is negative or
+// at least RQ_ERR_HIP_BASE)
+constexpr int SQ_NO_ROOM = 1;
+
 template <int LMAX, typename Acc>
 int launch_sq_update(hipStream_t s, SqParams& a, const BesideUpdate& b) {
   constexpr size_t lds = std::max(sizeof(SqLds<LMAX>), gemm_lds_bytes<128, 64, 16, Acc>());
@@ -902,14 +907,20 @@ int launch_sq_update(hipStream_t s, SqParams& a, const BesideUpdate& b) {
   u.M = b.M; u.N = b.N; u.K = b.K; u.A = b.A; u.lda = b.lda; u.B = b.B; u.ldb = b.ldb; u.C = b.C; u.ldc = b.ldc;
   u.tiles_x = (b.N + 63) / 64;
   u.tiles = u.tiles_x * ((b.M + 127) / 128);
-  const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>(b.wgs, u.tiles));
   // every workgroup of the grid must be resident at once (the sample QRCP's
-  // wait on each other; the update's are dispatched after them)
-  if (a.P + wgs > resident) return RQ_ERR_HIP_BASE + (int)hipErrorCooperativeLaunchTooLarge;
+  // wait on each other; the update's are dispatched after them): the update
+  // gets at most the places the sample QRCP leaves, and none left means no
+  // room (the caller then runs the two one after the other)
+  const int64_t room = (int64_t)resident - a.P;
+  if (room < 1) return SQ_NO_ROOM;
+  const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>({b.wgs, u.tiles, room}));
   hipLaunchKernelGGL(kern, dim3((unsigned)(a.P + wgs)), dim3(SQ_T), lds, s, a, u);
   RQ_HIP(hipGetLastError());
   return 0;
 }
+
+template <int LMAX>
+int launch_sq_alone(hipStream_t s, SqParams& a);
 
 template <int LMAX>
 int launch_sq(hipStream_t s, SqParams& a, const BesideUpdate* upd) {
@@ -917,8 +928,24 @@ int launch_sq(hipStream_t s, SqParams& a, const BesideUpdate* upd) {
   if (P > SQ_MAXP) return -4;  // n too large for this kernel
   a.P = (int)P;
   a.K = SQ_T / a.P;
-  if (upd && upd->M > 0 && upd->N > 0 && upd->K > 0)
-    return upd->f32 ? launch_sq_update<LMAX, float>(s, a, *upd) : launch_sq_update<LMAX, double>(s, a, *upd);
+  if (upd && upd->M > 0 && upd->N > 0 && upd->K > 0) {
+    const int rc = upd->f32 ? launch_sq_update<LMAX, float>(s, a, *upd) : launch_sq_update<LMAX, double>(s, a, *upd);
+    if (rc != SQ_NO_ROOM) return rc;
+    // the sample QRCP fills every place on the device: the update follows it
+    // as an ordinary launch (the same products, so the same bits)
+    const int rs = launch_sq_alone<LMAX>(s, a);
+    if (rs) return rs;
+    const BesideUpdate& b = *upd;
+    return b.f32 ? launch_gemm_f32(s, false, false, b.M, b.N, b.K, -1.0, b.A, b.lda, b.B, b.ldb, 1.0, b.C, b.ldc,
+                                   nullptr, 0)
+                 : launch_gemm(s, false, false, b.M, b.N, b.K, -1.0, b.A, b.lda, b.B, b.ldb, 1.0, b.C, b.ldc, nullptr,
+                               0);
+  }
+  return launch_sq_alone<LMAX>(s, a);
+}
+
+template <int LMAX>
+int launch_sq_alone(hipStream_t s, SqParams& a) {
   constexpr size_t lds = sizeof(SqLds<LMAX>);
   static_assert(lds <= 160 * 1024, "LDS budget");
   // The P workgroups wait on each other, so all of them must be resident

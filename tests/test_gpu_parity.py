@@ -482,10 +482,10 @@ def test_empty_matrices():
 
 
 def test_rqrcp_lookahead_is_bitwise_sequential():
-    """The look-ahead (bulk of each trailing update on a second stream, as a
-    persistent grid that here walks several tiles per workgroup: about 900
-    tiles of 128 x 64 on fewer than 240 workgroups) gives the factorization
-    of the all-on-one-stream order bit for bit."""
+    """The look-ahead (the bulk of each trailing update in the next sample
+    QRCP's launch, on workgroups of its own that walk several tiles each:
+    about 900 tiles of 128 x 64 on fewer than 256 workgroups) gives the
+    factorization of the sequential order bit for bit."""
     say("rqrcp look-ahead on/off 3000x2500 b=64")
     A = dev(inputs.with_spectrum(17, 3000, 2500, inputs.sigma_decade(2500, 8)))
     prev = binding.rq_set_lookahead(True)
@@ -496,6 +496,26 @@ def test_rqrcp_lookahead_is_bitwise_sequential():
     finally:
         binding.rq_set_lookahead(prev)
     for x, y in zip(on, off):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("n", [60000, 65536])
+def test_rqrcp_wide_sample_fills_the_device(n):
+    """Samples so wide that the sample QRCP's workgroups (one per 256
+    columns: 235 and 256) leave few or no CUs for the previous block's
+    trailing update in the same launch: the update gets what is left, or
+    runs right after the sample QRCP.  Pivots against the oracle, and the
+    factorization bit for bit the one without look-ahead."""
+    m, b, p, seed = 200, 64, 8, 21
+    say(f"rqrcp wide sample {m}x{n} b={b}")
+    A = inputs.with_spectrum(seed, m, n, inputs.sigma_decade(m, 8))
+    F, tau, jpvt, _ = compare_rqrcp(A, b, p, seed)
+    prev = binding.rq_set_lookahead(False)
+    try:
+        off = [host(x) for x in binding.rq_rqrcp(dev(A), b, p, seed)]
+    finally:
+        binding.rq_set_lookahead(prev)
+    for x, y in zip((F, tau, jpvt), off[:3]):
         assert np.array_equal(x, y)
 
 
