@@ -277,3 +277,26 @@ def test_batch_workspace_query_never_wraps(lib):
 def nbytes_would_exceed(shapes, k):
     """More output tiles than 32-bit tile indices can address."""
     return sum(((m + 31) // 32) * ((k + 31) // 32) for m, _ in shapes) > 2 ** 24
+
+
+def test_sample_register_tiles_in_the_size_query(lib):
+    """The sample is stored in register tiles of 32, 40, 48, 64, 72, 80 or
+    128 rows: the sample QRCP's workspace grows with the tile, not with l,
+    so every l of one tile asks for the same bytes and the next l for more."""
+    out = ctypes.c_size_t(0)
+    n = 4096
+
+    def q(l):
+        assert lib.rq_workspace_bytes(binding.RQ_OP_SAMPLE_QRCP, l, n, 0, 1, 0, 0, ctypes.byref(out)) == 0
+        return out.value
+
+    tiles = [32, 40, 48, 64, 72, 80, 128]
+    lo = 1
+    for t in tiles:
+        sizes = {q(l) for l in range(lo, t + 1)}
+        assert len(sizes) == 1, (lo, t)
+        lo = t + 1
+    per_tile = [q(t) for t in tiles]
+    assert per_tile == sorted(per_tile) and len(set(per_tile)) == len(tiles)
+    # the sample itself (n columns of the tile's rows) is part of it
+    assert q(41) - q(40) >= 8 * n * (48 - 40)
