@@ -539,3 +539,29 @@ def test_tuxv_rank_one_and_full_rank():
     assert np.linalg.norm(A - (U * s) @ VT) <= 1e-12 * np.linalg.norm(A)
     assert np.linalg.norm(U.T @ U - np.eye(200)) <= orth_tol(200)
     assert np.linalg.norm(VT @ VT.T - np.eye(200)) <= orth_tol(200)
+
+
+@pytest.mark.parametrize("m,n,b,p,seed,lookahead", [
+    (2100, 1300, 32, 8, 9, True),
+    (2100, 1300, 32, 8, 9, False),
+    (1000, 700, 64, 8, 8, True),
+])
+def test_rqrcp_result_does_not_depend_on_workspace_contents(m, n, b, p, seed, lookahead):
+    """Every buffer the factorization reads from its workspace is written
+    first: a workspace full of NaNs, one full of zeros and one full of
+    ones give the same factorization bit for bit."""
+    say(f"rqrcp workspace contents {m}x{n} b={b} lookahead={lookahead}")
+    A = dev(inputs.with_spectrum(seed, m, n, inputs.sigma_decade(min(m, n), 8)))
+    nbytes = binding.rq_workspace_bytes(binding.RQ_OP_RQRCP, m, n, 0, b, p)
+    prev = binding.rq_set_lookahead(lookahead)
+    try:
+        outs = []
+        for fill in (float("nan"), 0.0, 1.0):
+            work = torch.full(((nbytes + 7) // 8,), fill, dtype=torch.float64, device="cuda").view(torch.uint8)
+            outs.append([host(x) for x in binding.rq_rqrcp(A, b, p, seed, work=work)])
+    finally:
+        binding.rq_set_lookahead(prev)
+    assert outs[0][3][0] == 0
+    for other in outs[1:]:
+        for x, y in zip(outs[0], other):
+            assert np.array_equal(x, y)
