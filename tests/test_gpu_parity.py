@@ -541,6 +541,24 @@ def test_tuxv_rank_one_and_full_rank():
     assert np.linalg.norm(VT @ VT.T - np.eye(200)) <= orth_tol(200)
 
 
+@pytest.mark.xfail(strict=False, reason="open issue: with the look-ahead on, repeated b = 32 factorizations of this "
+                   "matrix differed from run to run in two of four GPU probes (every result a valid "
+                   "factorization); not seen at b = 64 or with the look-ahead off; cause not found")
+def test_rqrcp_lookahead_repeatable_at_b32():
+    """The look-ahead factorization at b = 32 repeats bit for bit."""
+    m, n, b, p, seed = 2100, 1300, 32, 8, 9
+    say(f"rqrcp look-ahead repeatability {m}x{n} b={b}")
+    A = dev(inputs.with_spectrum(seed, m, n, inputs.sigma_decade(min(m, n), 8)))
+    prev = binding.rq_set_lookahead(True)
+    try:
+        runs = [[host(x) for x in binding.rq_rqrcp(A, b, p, seed)] for _ in range(6)]
+    finally:
+        binding.rq_set_lookahead(prev)
+    for r in runs[1:]:
+        for x, y in zip(runs[0], r):
+            assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("m,n,b,p,seed,lookahead", [
     (2100, 1300, 32, 8, 9, True),
     (2100, 1300, 32, 8, 9, False),

@@ -29,7 +29,13 @@ def test_noalloc_matches_workspace_entry_point_on_two_calls():
     for m, n, b, p, seed in cases:
         print(f"[case] rqrcp_noalloc {m}x{n} b={b} p={p} seed={seed}", flush=True)
         A = dev(inputs.with_spectrum(seed, m, n, inputs.sigma_decade(min(m, n), 8)))
-        ref = [host(x) for x in binding.rq_rqrcp(A, b, p, seed)]
+        # the allocation-free entry point runs the blocks in the sequential
+        # order (no look-ahead); compare with rq_rqrcp in that same order
+        prev = binding.rq_set_lookahead(False)
+        try:
+            ref = [host(x) for x in binding.rq_rqrcp(A, b, p, seed)]
+        finally:
+            binding.rq_set_lookahead(prev)
         got = [host(x) for x in binding.rq_rqrcp_noalloc(A, b, p, seed)]
         assert got[3][0] == 0 and ref[3][0] == 0
         for x, y in zip(got, ref):
