@@ -20,6 +20,10 @@ constexpr int SQ_T = 256;      // threads per workgroup = slab width = candidate
 constexpr int SQ_BMAX = 64;    // pivots per call at most
 constexpr int SQ_MAXP = 256;   // workgroups (slabs) at most, so nJ <= 65536
 constexpr int SQ_LCAP = 128;   // rows of a candidate buffer
+// Words of one workgroup's theta entry: a whole 128-byte line, so that no two
+// workgroups (which may sit on different XCDs, each with its own L2) ever
+// write the same line.
+constexpr int SQ_TH = 16;
 
 struct SqParams {
   double* S;        // sample, column c at S + c * LMAX
@@ -31,7 +35,7 @@ struct SqParams {
   int info_base;
   double* cand;     // 2 buffers of SQ_T columns of SQ_LCAP rows; column of slot i at [buf][i * LMAX]
   int* cand_idx;    // 2 buffers of 2 x SQ_T: logical position (-1: empty slot), physical column
-  double* theta;    // 2 buffers of SQ_MAXP
+  double* theta;    // 2 buffers of SQ_MAXP entries, SQ_TH words apart
   unsigned* flags;  // [0]: arrival counter (zeroed by the caller)
   int* err;
   int P;
@@ -487,8 +491,8 @@ __device__ void sq_scan(const SqParams& a, SqLds<LMAX>& L, int me, int a0, int t
     }
   }
   if (tid < a.K && tid >= nvalid) ib[me * a.K + tid] = -1;
-  if (mine && rank == a.K) a.theta[(size_t)buf * SQ_MAXP + me] = kv;
-  if (tid == 0 && a.K >= nvalid) a.theta[(size_t)buf * SQ_MAXP + me] = -INFINITY;
+  if (mine && rank == a.K) a.theta[((size_t)buf * SQ_MAXP + me) * SQ_TH] = kv;
+  if (tid == 0 && a.K >= nvalid) a.theta[((size_t)buf * SQ_MAXP + me) * SQ_TH] = -INFINITY;
 }
 
 // Arrival barrier over the P workgroups: every workgroup adds one to the
@@ -574,7 +578,7 @@ __device__ __forceinline__ void sample_qrcp_body(const SqParams& a, const int me
 #pragma unroll
       for (int k = 0; k < SQ_MAXP / WAVE; ++k) {
         const int qq = tid + k * WAVE;
-        thv[k] = (qq < a.P) ? a.theta[(size_t)buf * SQ_MAXP + qq] : -INFINITY;
+        thv[k] = (qq < a.P) ? a.theta[((size_t)buf * SQ_MAXP + qq) * SQ_TH] : -INFINITY;
       }
     }
 #pragma unroll
@@ -930,7 +934,11 @@ int launch_sq(hipStream_t s, SqParams& a, const BesideUpdate* upd) {
   const int64_t P = (a.nJ + SQ_T - 1) / SQ_T;
   if (P > SQ_MAXP) return -4;  // n too large for this kernel
   a.P = (int)P;
-  a.K = SQ_T / a.P;
+  // K even where it can be: with 8 B per row and LMAX = 8 x (odd) (40, 72),
+  // an even K makes each workgroup's K candidate columns whole 128-byte
+  // lines, so two workgroups never write one line of the candidate buffer
+  // (above 128 workgroups K is 1)
+  a.K = std::max(1, (SQ_T / a.P) & ~1);
   if (upd && upd->M > 0 && upd->N > 0 && upd->K > 0) {
     const int rc = upd->f32 ? launch_sq_update<LMAX, float>(s, a, *upd) : launch_sq_update<LMAX, double>(s, a, *upd);
     if (rc != SQ_NO_ROOM) return rc;
@@ -1100,7 +1108,7 @@ int sample_rows_padded(int l) {
 }
 size_t sample_qrcp_cand_elems() { return 2 * (size_t)SQ_LCAP * SQ_T; }
 size_t sample_qrcp_idx_elems() { return 2 * 2 * (size_t)SQ_T; }
-size_t sample_qrcp_theta_elems() { return 2 * (size_t)SQ_MAXP; }
+size_t sample_qrcp_theta_elems() { return 2 * (size_t)SQ_MAXP * SQ_TH; }
 
 int sample_qrcp_workgroups(int64_t nJ) { return (int)((nJ + SQ_T - 1) / SQ_T); }
 
